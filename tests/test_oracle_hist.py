@@ -1,0 +1,108 @@
+"""Pins for the oracle's colour histogram (section "Visual ETL", Transformers).
+
+The oracle is checked against things other than itself: a hand-computed
+example, numpy's histogramdd (an independent binning routine), and
+invariants (mass, permutation, bin edges)."""
+import numpy as np
+import pytest
+
+from conftest import read_golden
+
+
+def histogramdd_reference(patches, bins):
+    """Counts via numpy.histogramdd with uniform edges 0, 256/bins, ..., 256."""
+    n = patches.shape[0]
+    edges = np.linspace(0, 256, bins + 1)
+    out = np.empty((n, bins ** 3), np.int64)
+    for p in range(n):
+        px = patches[p].reshape(-1, 3).astype(np.float64)
+        c, _ = np.histogramdd(px, bins=(edges, edges, edges))
+        out[p] = c.astype(np.int64).reshape(-1)  # C order: r major, then g, then b
+    return out
+
+
+def test_hand_example(orc):
+    rows = read_golden("hist_2x2.txt")
+    bins = int([r for r in rows if r[0] == "bins"][0][1])
+    h, w = map(int, [r for r in rows if r[0] == "size"][0][1:])
+    px = np.array([list(map(int, r[1:])) for r in rows if r[0] == "pixel"], np.uint8)
+    patch = px.reshape(1, h, w, 3)
+    expect = np.zeros(bins ** 3, np.float32)
+    for r in rows:
+        if r[0] == "expect":
+            expect[int(r[1])] = float(r[2])
+    got = orc.hist_rgb8(patch, bins)
+    assert got.shape == (1, bins ** 3)
+    assert np.array_equal(got[0], expect)
+
+
+@pytest.mark.parametrize("bins", [8, 4, 16, 2])
+@pytest.mark.parametrize("hw", [(32, 32), (7, 5), (1, 1), (17, 31)])
+def test_matches_histogramdd(orc, bins, hw):
+    rng = np.random.default_rng(bins * 100 + hw[0])
+    patches = rng.integers(0, 256, size=(6, hw[0], hw[1], 3), dtype=np.uint8)
+    h, cnt = orc.hist_rgb8(patches, bins, counts=True)
+    ref = histogramdd_reference(patches, bins)
+    assert np.array_equal(cnt, ref)
+    npx = hw[0] * hw[1]
+    # L1 normalisation: one correctly rounded division per bin
+    assert np.array_equal(h, (ref.astype(np.float64) / npx).astype(np.float32))
+
+
+def test_single_colour_patch(orc):
+    rng = np.random.default_rng(7)
+    for _ in range(20):
+        c = rng.integers(0, 256, size=3)
+        patch = np.broadcast_to(c.astype(np.uint8), (1, 8, 8, 3)).copy()
+        h = orc.hist_rgb8(patch, 8)[0]
+        ref = histogramdd_reference(patch, 8)[0]
+        assert h.max() == 1.0 and np.count_nonzero(h) == 1
+        assert np.argmax(h) == np.argmax(ref)
+
+
+def test_bin_edges(orc):
+    # values on either side of the first, an interior and the last edge
+    vals = [0, 31, 32, 223, 224, 255]
+    for ch in range(3):
+        for v in vals:
+            px = np.zeros((1, 1, 1, 3), np.uint8)
+            px[0, 0, 0, ch] = v
+            h = orc.hist_rgb8(px, 8)[0]
+            ref = histogramdd_reference(px, 8)[0]
+            assert np.argmax(h) == np.argmax(ref), (ch, v)
+    # 31 and 32 fall in different bins, 223 and 224 too; 0 and 31 share one
+    def binof(v):
+        return int(np.argmax(orc.hist_rgb8(np.full((1, 1, 1, 3), v, np.uint8), 8)[0]))
+    assert binof(0) == binof(31) != binof(32)
+    assert binof(223) != binof(224) == binof(255)
+
+
+def test_mass_and_permutation(orc):
+    rng = np.random.default_rng(11)
+    patches = rng.integers(0, 256, size=(5, 32, 32, 3), dtype=np.uint8)
+    h, cnt = orc.hist_rgb8(patches, 8, counts=True)
+    assert np.all(cnt.sum(axis=1) == 32 * 32)
+    # 1024 pixels: every bin is a multiple of 2^-10, so the float32 sum is exact
+    assert np.all(h.astype(np.float32).sum(axis=1, dtype=np.float32) == np.float32(1.0))
+    for p in range(5):
+        flat = patches[p].reshape(-1, 3)
+        perm = flat[rng.permutation(flat.shape[0])].reshape(1, 32, 32, 3)
+        assert np.array_equal(orc.hist_rgb8(perm, 8)[0], h[p])
+
+
+def test_nonpow2_pixel_count_rounding(orc):
+    # 3 pixels in one bin out of 7: value is the float32 nearest to 3/7
+    px = np.zeros((1, 1, 7, 3), np.uint8)
+    px[0, 0, 3:, 0] = 200
+    h = orc.hist_rgb8(px, 8)[0]
+    assert h[0] == np.float32(3 / 7) and h[6 * 64] == np.float32(4 / 7)
+
+
+def test_empty_batch(orc):
+    h = orc.hist_rgb8(np.zeros((0, 4, 4, 3), np.uint8), 8)
+    assert h.shape == (0, 512)
+
+
+def test_rejects_bad_bins(orc):
+    with pytest.raises(ValueError):
+        orc.hist_rgb8(np.zeros((1, 2, 2, 3), np.uint8), 3)
