@@ -1,0 +1,163 @@
+"""Benchmark: featurise + exact eps self-join of 100,000 RGB patches on one GPU.
+
+One step is the whole hot path over one batch of synthetic input already
+resident in HBM: colour histograms of 100,000 uint8 32x32 patches (8x8x8
+bins), operand prep, the matrix-core candidate pass with the fused eps
+filter, the float32 / float64 recheck and the canonical (i, j) sort, for the
+self-join i < j at the 0.01% distance quantile.  `value` is the number of
+distance pairs in the join's domain (n(n-1)/2) per second of step time.
+
+Prints one JSON line.  Runs on one GPU only.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp16": 2500.0, "bf16": 2500.0, "fp8": 5000.0, "fp32": 157.3}
+METRIC = "G distance-pairs/s for ε-join at exact pair set; p50/p99 query latency"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--prec", default="fp16", choices=sorted(PEAK_TFLOPS))
+    ap.add_argument("--n", type=int, default=100000, help="patches (default: the full workload)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for the CPU baseline")
+    ap.add_argument("--no-fp32-compare", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(H, eps, n, target_s):
+    """The oracle (plain C, float64) on a bounded sample of rows of the same
+    self-join, on all host cores."""
+    import numpy as np
+
+    import oracle
+    from paper_1812_07607_amd import synth
+    threads = oracle.max_threads()
+    t0 = time.perf_counter()
+    feat = oracle.hist_rgb8(H["patches"][:2000], 8, nthreads=threads)
+    t_feat = (time.perf_counter() - t0) / 2000
+    del feat
+    Hn = H["hist"]
+    # probe the per-pair cost on a few rows, then size the sample to target_s
+    probe = synth.sample_rows(n, 8, seed=77)
+    pp = int(sum(n - 1 - r for r in probe))
+    t0 = time.perf_counter()
+    oracle.eps_join(np.ascontiguousarray(Hn[probe]), Hn, eps, self_join=True, row_ids=probe, nthreads=threads)
+    per_pair = max((time.perf_counter() - t0) / max(pp, 1), 1e-12)
+    m = int(min(n, max(8, target_s / per_pair / max(n / 2, 1))))
+    rows = synth.sample_rows(n, m, seed=78)
+    pairs = int(sum(n - 1 - r for r in rows))
+    t0 = time.perf_counter()
+    oracle.eps_join(np.ascontiguousarray(Hn[rows]), Hn, eps, self_join=True, row_ids=rows, nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": pairs / dt / 1e9, "unit": "G distance-pairs/s", "cores": threads, "kind": "oracle",
+            "sample": "eps self-join of %d seeded rows x all later rows (%d pairs, %.1f s); featurise %.2f us/patch "
+                      "(not in value)" % (m, pairs, dt, t_feat * 1e6)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1812_07607_amd import ops, synth
+
+    torch.cuda.set_device(0)
+    n = args.n
+    cfg = synth.config2(n / 100000.0)
+    patches = torch.from_numpy(cfg["patches"]).cuda()
+    hist = torch.empty((n, 512), dtype=torch.float32, device="cuda")
+    ops.featurize_rgb8(patches, 8, out=hist)
+    pi, pj = cfg["pairs"]
+    d2 = ops.pair_d2(hist, hist, torch.from_numpy(pi), torch.from_numpy(pj)).cpu().numpy()
+    eps = float(np.sqrt(synth.order_statistic(d2, cfg["q"])))
+    ctx = ops.context()
+    ws = ops.Workspace(hist.device)
+
+    def step(prec, out=None):
+        ops.featurize_rgb8(patches, 8, out=hist)
+        return ops.join_eps(hist, None, eps, prec, workspace=ws, out=out)
+
+    r = step(args.prec)
+    cap = max(r.count * 2, 1 << 16)
+    out = (torch.empty(cap, dtype=torch.int32, device="cuda"), torch.empty(cap, dtype=torch.int32, device="cuda"),
+           torch.empty(cap, dtype=torch.float32, device="cuda"))
+    for _ in range(args.warmup):
+        step(args.prec, out)
+    torch.cuda.synchronize()
+    ctx.timing(reset=True)
+    ctx.set_timing(True)
+    lat = []
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        r = step(args.prec, out)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_all
+    ctx.set_timing(False)
+    stages = ctx.timing(reset=True)
+    pairs = n * (n - 1) // 2
+    ms_step = elapsed / args.steps * 1e3
+    value = pairs / (elapsed / args.steps) / 1e9
+
+    # dominant kernel: the matrix-core contraction (stage "contract")
+    c_ms, c_calls = stages["contract"]
+    c_avg = c_ms / max(c_calls, 1)
+    flops = pairs * 2.0 * 512
+    achieved = flops / (c_avg * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.prec]
+    roof = {"kernel": "cand_kernel<%s, eps>" % args.prec, "bound": "mfma", "achieved": achieved, "peak": peak,
+            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+            "flops_per_launch": flops, "avg_launch_ms": c_avg}
+    res = {
+        "metric": METRIC, "value": value, "unit": "G distance-pairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
+        "config": {"workload": "featurise %d RGB 32x32 patches (8x8x8 histograms, 16 base colours + N(0,20^2)) + "
+                               "exact eps self-join i<j at the 0.01%% distance quantile" % n,
+                   "patches": n, "dim": 512, "pairs": pairs, "eps": eps, "result_pairs": r.count,
+                   "candidates": r.candidates, "fp64_ties": r.ties},
+        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3)},
+        "stages_ms_per_step": {k: v[0] / max(args.steps, 1) for k, v in stages.items() if v[1]},
+        "roofline": roof,
+    }
+    if not args.no_fp32_compare and args.prec != "fp32":
+        # the plain fp32 GPU join on the same input, for comparison
+        step("fp32", out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        k32 = max(1, min(3, args.steps))
+        for _ in range(k32):
+            r32 = step("fp32", out)
+        torch.cuda.synchronize()
+        t32 = (time.perf_counter() - t0) / k32
+        res["fp32_join"] = {"value": pairs / t32 / 1e9, "ms_per_step": t32 * 1e3, "candidates": r32.candidates,
+                            "same_pairs": bool(r32.count == r.count)}
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline({"patches": cfg["patches"], "hist": hist.cpu().numpy()}, eps, n,
+                                           args.cpu_seconds)
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

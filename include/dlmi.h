@@ -1,0 +1,198 @@
+/*
+ * dlmi.h -- C ABI of the MI355X (gfx950) patch-featurisation and exact
+ * similarity-join library (libdlmi.so).
+ *
+ * The operations follow the patch/query model of Krishnan et al., "DeepLens:
+ * Towards a Visual Data Management System" (CIDR 2019):
+ *   - a patch carries a dense n-dimensional vector as its data (section
+ *     "Iterator API for Patches"); here a relation of patches is a row-major
+ *     float32 matrix, one row per patch, and a row index stands for the
+ *     patch's image reference;
+ *   - featurisation is the colour-histogram transformer (section "Visual
+ *     ETL", Transformers);
+ *   - the join compares all pairs of two patch collections and returns those
+ *     that satisfy a predicate (section "Query Processing", Nested Loop Join),
+ *     here the Euclidean threshold predicate of image matching (section
+ *     "Derived Data") or the k closest patches (query q1, section "Queries").
+ *
+ * Conventions for every call:
+ *   - Pointers documented as "device" point to memory on the context's GPU;
+ *     the library never frees or retains them after the call's GPU work has
+ *     finished.  "host" pointers are read or written before the call returns.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     All GPU work of a call is enqueued on it.  A call that reports a count
+ *     synchronises the stream before returning; other results are ready when
+ *     the stream reaches the end of the call's work.
+ *   - No call allocates device memory except where stated: scratch memory is
+ *     the caller's `ws` buffer, sized by the matching *_workspace query.
+ *   - Errors are status codes; dl_last_error() gives a message.  No C++
+ *     exception crosses this boundary.  On error, output buffers may hold
+ *     partial results.
+ *   - The library is thread-safe for distinct contexts; one context must not
+ *     be used by two threads at once.
+ */
+#ifndef DLMI_H
+#define DLMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum dl_status {
+  DL_OK = 0,
+  DL_ERR_INVALID = 1,   /* null pointer, bad shape or size, non-finite input */
+  DL_ERR_OOM = 2,       /* request does not fit the memory budget            */
+  DL_ERR_CAPACITY = 3,  /* output buffer too small: the count says how many   */
+  DL_ERR_WORKSPACE = 4, /* `ws` too small: dl_required_workspace() says how much */
+  DL_ERR_DEVICE = 5,    /* HIP runtime error                                  */
+  DL_ERR_BUSY = 6,      /* server queue full                                  */
+  DL_ERR_CANCELLED = 7  /* request cancelled                                  */
+} dl_status;
+
+/* Operand format of the candidate pass on the matrix cores.  The emitted
+ * results do not depend on it; only speed and the candidate count do. */
+typedef enum dl_prec {
+  DL_FP32 = 0, /* plain fp32 operands                                    */
+  DL_BF16 = 1, /* bfloat16, round to nearest even                        */
+  DL_FP16 = 2, /* IEEE half, round to nearest even, saturating           */
+  DL_FP8 = 3   /* OCP E4M3 with a power-of-two scale per row             */
+} dl_prec;
+
+typedef struct dl_ctx dl_ctx;
+
+/* A relation of patch vectors: n rows of d float32 values, row r at
+ * data + r*ld (ld >= d, in elements).  Device memory, borrowed.
+ * 0 <= n < 2^31, 1 <= d <= 4096. */
+typedef struct dl_mat {
+  const float* data;
+  int64_t n;
+  int32_t d;
+  int64_t ld;
+} dl_mat;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`.  Allocates a few bytes of pinned
+ * host memory for counts; no device memory. */
+dl_status dl_create(int device, dl_ctx** out);
+void dl_destroy(dl_ctx* ctx);
+/* Message for the last error on this context ("" if none).  Valid until the
+ * next call on the context. */
+const char* dl_last_error(const dl_ctx* ctx);
+/* Library version string. */
+const char* dl_version(void);
+
+/* Per-stage GPU timing with HIP events, recorded on the call's stream.
+ * Stages: 0 featurize, 1 prep, 2 candidate contraction (the matrix-core
+ * kernel), 3 recheck (fp32 + fp64 ties), 4 canonical sort, 5 top-k select.
+ * dl_get_timing adds, per stage, the summed milliseconds and the number of
+ * timed launches since the last reset into ms[] and calls[] (arrays of
+ * DL_NUM_STAGES); it synchronises on the recorded events. */
+#define DL_NUM_STAGES 6
+dl_status dl_set_timing(dl_ctx* ctx, int enable);
+dl_status dl_get_timing(dl_ctx* ctx, double* ms, int64_t* calls, int reset);
+
+/* ----------------------------------------------------------- featurise */
+
+/* Colour histogram of each patch (section "Visual ETL", Transformers).
+ *   patches   device, n*h*w*3 uint8, patch-major, pixels row-major, channels
+ *             R,G,B interleaved (HWC), contiguous.
+ *   bins      bins per channel; must divide 256 (bin width 256/bins).
+ *   out_hist  device, n * bins^3 float32, row-major: entry
+ *             ((r/width)*bins + g/width)*bins + b/width counts the pixels of
+ *             that colour cell, divided by h*w (correctly rounded).
+ * Errors: DL_ERR_INVALID for null pointers, n < 0, h or w < 1, h*w >= 2^24,
+ * bins not dividing 256 or bins^3 > 4096. */
+dl_status dl_featurize_rgb8(dl_ctx* ctx, const uint8_t* patches, int64_t n,
+                            int32_t h, int32_t w, int32_t bins,
+                            float* out_hist, void* stream);
+
+/* -------------------------------------------------------- pair distances */
+
+/* Squared Euclidean distance in float64 for listed pairs, summed over
+ * k = 0..d-1 in order with separately rounded subtract, multiply and add
+ * (the canonical definition every join decision is exact against).
+ *   pi, pj  device uint32[m]: row of R and row of S of each pair.
+ *   out_d2  device double[m].
+ * Indices must be in range (checked on the GPU: out-of-range pairs get NaN
+ * and the call returns DL_ERR_INVALID). */
+dl_status dl_pair_d2(dl_ctx* ctx, dl_mat R, dl_mat S, const uint32_t* pi,
+                     const uint32_t* pj, int64_t m, double* out_d2,
+                     void* stream);
+
+/* ------------------------------------------------------------- eps-join */
+
+/* Output of dl_join_eps: caller-owned device arrays of `capacity` entries. */
+typedef struct dl_pairs {
+  uint32_t* i;        /* device: row of R                                  */
+  uint32_t* j;        /* device: row of S                                  */
+  float* dist;        /* device: distance rounded to float32               */
+  int64_t capacity;   /* entries available in i, j, dist                   */
+  int64_t count;      /* out: number of matching pairs (may exceed capacity) */
+  int64_t candidates; /* out: pairs that passed the margin-widened filter  */
+  int64_t ties;       /* out: candidates decided by the float64 recheck    */
+} dl_pairs;
+
+/* Scratch bytes needed by dl_join_eps for up to `max_candidates` candidate
+ * pairs after the matrix-core filter.  self_join != 0 means S is R. */
+size_t dl_join_eps_workspace(int64_t nR, int64_t nS, int32_t d, dl_prec prec,
+                             int self_join, int64_t max_candidates);
+
+/* eps-range join (section "Query Processing", Nested Loop Join, with the
+ * Euclidean threshold predicate of section "Derived Data").
+ * Emits every pair (i, j) of R x S -- i < j when self_join != 0, S ignored
+ * and R joined with itself (query q4's deduplication) -- whose float64
+ * canonical distance (see dl_pair_d2) satisfies sqrt(d2) <= eps, sorted by
+ * (i, j).  dist is within the documented float32 error of sqrt(d2).
+ * The pair set does not depend on `prec`.
+ *   eps    >= 0, may be +inf; NaN is rejected.
+ *   ws     device scratch of ws_bytes (see dl_join_eps_workspace).
+ *   out    host struct; its arrays are device memory.
+ * Returns DL_ERR_CAPACITY if count > capacity (the first `capacity` pairs in
+ * (i, j) order are written, out->count holds the total), DL_ERR_WORKSPACE if
+ * the candidates exceed what ws holds (dl_required_workspace() gives the
+ * bytes that would have sufficed), DL_ERR_INVALID for bad shapes or a
+ * non-finite value in R or S.  Synchronises `stream`. */
+dl_status dl_join_eps(dl_ctx* ctx, dl_mat R, dl_mat S, int self_join,
+                      double eps, dl_prec prec, void* ws, size_t ws_bytes,
+                      dl_pairs* out, void* stream);
+
+/* Bytes of workspace the last DL_ERR_WORKSPACE failure on ctx needed. */
+size_t dl_required_workspace(const dl_ctx* ctx);
+
+/* ---------------------------------------------------------------- top-k */
+
+typedef struct dl_topk_info {
+  int64_t band_entries; /* candidates kept by the margin-widened band filter */
+  int64_t ties;         /* entries whose order was decided in float64       */
+} dl_topk_info;
+
+/* Scratch bytes for dl_join_topk with `band_cap` band entries per row and
+ * S-split (0 = library default). */
+size_t dl_join_topk_workspace(int64_t nR, int64_t nS, int32_t d, dl_prec prec,
+                              int self_join, int32_t k, int32_t band_cap);
+
+/* k closest rows of S for every row of R (query q1, section "Queries":
+ * the closest image to a query image), by float64 canonical d2 with ties
+ * broken by the smaller j, ascending.  self_join != 0: S is R, and
+ * exclude_self drops j == i.
+ *   out_j     device uint32[nR*k]; UINT32_MAX pads rows with fewer than k.
+ *   out_dist  device float[nR*k];  +inf pads.
+ *   info      host, nullable.
+ * Returns DL_ERR_WORKSPACE if a row's band does not fit band_cap (retry with
+ * a larger band_cap), DL_ERR_INVALID for bad arguments.  Synchronises
+ * `stream`. */
+dl_status dl_join_topk(dl_ctx* ctx, dl_mat R, dl_mat S, int self_join,
+                       int32_t k, int exclude_self, dl_prec prec,
+                       int32_t band_cap, void* ws, size_t ws_bytes,
+                       uint32_t* out_j, float* out_dist, dl_topk_info* info,
+                       void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DLMI_H */

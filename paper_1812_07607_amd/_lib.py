@@ -1,0 +1,78 @@
+"""ctypes declarations of libdlmi.so (the C ABI in include/dlmi.h).
+
+Argument marshalling only.  Loading fails loudly when the library has not
+been built: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdlmi.so")
+
+DL_OK, DL_ERR_INVALID, DL_ERR_OOM, DL_ERR_CAPACITY, DL_ERR_WORKSPACE, DL_ERR_DEVICE, DL_ERR_BUSY, DL_ERR_CANCELLED = range(8)
+STATUS_NAMES = {0: "DL_OK", 1: "DL_ERR_INVALID", 2: "DL_ERR_OOM", 3: "DL_ERR_CAPACITY", 4: "DL_ERR_WORKSPACE",
+                5: "DL_ERR_DEVICE", 6: "DL_ERR_BUSY", 7: "DL_ERR_CANCELLED"}
+PREC = {"fp32": 0, "bf16": 1, "fp16": 2, "fp8": 3}
+NUM_STAGES = 6
+STAGES = ["featurize", "prep", "contract", "recheck", "sort", "select"]
+
+
+class dl_mat(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("n", ctypes.c_int64), ("d", ctypes.c_int32), ("ld", ctypes.c_int64)]
+
+
+class dl_pairs(ctypes.Structure):
+    _fields_ = [("i", ctypes.c_void_p), ("j", ctypes.c_void_p), ("dist", ctypes.c_void_p),
+                ("capacity", ctypes.c_int64), ("count", ctypes.c_int64), ("candidates", ctypes.c_int64),
+                ("ties", ctypes.c_int64)]
+
+
+class dl_topk_info(ctypes.Structure):
+    _fields_ = [("band_entries", ctypes.c_int64), ("ties", ctypes.c_int64)]
+
+
+# name -> (restype, argtypes); every symbol include/dlmi.h declares
+P, i32, i64, f64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+SIGNATURES = {
+    "dl_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(P)]),
+    "dl_destroy": (None, [P]),
+    "dl_last_error": (ctypes.c_char_p, [P]),
+    "dl_version": (ctypes.c_char_p, []),
+    "dl_set_timing": (ctypes.c_int, [P, ctypes.c_int]),
+    "dl_get_timing": (ctypes.c_int, [P, P, P, ctypes.c_int]),
+    "dl_featurize_rgb8": (ctypes.c_int, [P, P, i64, i32, i32, i32, P, P]),
+    "dl_pair_d2": (ctypes.c_int, [P, dl_mat, dl_mat, P, P, i64, P, P]),
+    "dl_join_eps_workspace": (sz, [i64, i64, i32, ctypes.c_int, ctypes.c_int, i64]),
+    "dl_join_eps": (ctypes.c_int, [P, dl_mat, dl_mat, ctypes.c_int, f64, ctypes.c_int, P, sz,
+                                   ctypes.POINTER(dl_pairs), P]),
+    "dl_required_workspace": (sz, [P]),
+    "dl_join_topk_workspace": (sz, [i64, i64, i32, ctypes.c_int, ctypes.c_int, i32, i32]),
+    "dl_join_topk": (ctypes.c_int, [P, dl_mat, dl_mat, ctypes.c_int, i32, ctypes.c_int, ctypes.c_int, i32, P, sz,
+                                    P, P, ctypes.POINTER(dl_topk_info), P]),
+}
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libdlmi.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libdlmi.so is not built (run `python -c 'import __graft_entry__ as g; g.build()'` "
+                               "or `python paper_1812_07607_amd/build.py`); there is no CPU fallback")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class DLError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status

@@ -1,0 +1,579 @@
+// api.hip -- the C ABI of libdlmi.so: validation, workspace layout, launch
+// sequencing and status codes.  Kernels live in the other sources.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "dl_internal.hpp"
+
+namespace dl {
+// featurize.hip
+hipError_t launch_hist_rgb8(const uint8_t*, int64_t, int32_t, int32_t, int32_t, float*, hipStream_t, int);
+// prep.hip
+hipError_t launch_prep(const float*, int64_t, int32_t, int64_t, dl_prec, const Prep&, RelStats*, hipStream_t, int);
+hipError_t launch_threshold(const Prep&, int64_t, const RelStats*, int, double, float*, float*, hipStream_t);
+}  // namespace dl
+
+#include "join_params.hpp"
+
+namespace dl {
+hipError_t launch_cand_eps(dl_prec, CandParams, hipStream_t, int);
+hipError_t launch_cand_band(dl_prec, CandParams, hipStream_t);
+hipError_t launch_recheck_eps(const RecheckParams&, hipStream_t, int);
+hipError_t launch_pair_d2(const float*, int64_t, int64_t, const float*, int64_t, int64_t, int, const uint32_t*,
+                          const uint32_t*, int64_t, double*, int*, hipStream_t, int);
+hipError_t launch_topk_select(const SelectParams&, hipStream_t);
+int64_t scan_scratch_words(int64_t);
+int64_t radix_hist_words(int64_t);
+int radix_sort_pairs(unsigned long long*, float*, unsigned long long*, float*, int64_t, int, uint32_t*, uint32_t*,
+                     hipStream_t, hipError_t*);
+hipError_t launch_unpack_pairs(const unsigned long long*, const float*, int64_t, int, uint32_t*, uint32_t*, float*,
+                               hipStream_t, int);
+
+// ------------------------------------------------------------ small kernels
+__global__ void zero_words_kernel(uint32_t* p, int64_t n) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) p[t] = 0;
+}
+
+// Device-side counters of one call (zeroed by a kernel, so the sequence can
+// be captured in a graph).
+struct Counters {
+  unsigned long long cand;   // candidates appended
+  unsigned long long out;    // pairs confirmed
+  unsigned long long ties;   // float64 decisions
+  unsigned long long band;   // top-k band entries
+  int bad_index;
+  int overflow;
+  int too_many;
+  int pad[13];
+};
+static_assert(sizeof(Counters) == 96, "counter block size");
+
+// ------------------------------------------------------------ workspace
+struct Bump {
+  uint8_t* base;
+  size_t off = 0;
+  explicit Bump(void* b) : base(static_cast<uint8_t*>(b)) {}
+  template <class T>
+  T* take(int64_t count) {
+    off = (size_t)round_up((int64_t)off, 256);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += (size_t)count * sizeof(T);
+    return p;
+  }
+};
+
+static Prep carve_prep(Bump& b, int64_t n, int d, dl_prec prec) {
+  Prep P;
+  P.npad = round_up(n < 1 ? 1 : n, kTile);
+  P.qld = dpad_of(d, prec) * elem_bytes(prec);
+  P.q = b.take<uint8_t>(P.npad * P.qld);
+  P.nrm2 = b.take<double>(P.npad);
+  P.h = b.take<float>(P.npad);
+  P.qnorm = b.take<float>(P.npad);
+  P.rho = b.take<float>(P.npad);
+  P.dh = b.take<float>(P.npad);
+  P.xnorm = b.take<float>(P.npad);
+  P.qlsb = b.take<int>(P.npad);
+  P.hlsb = b.take<int>(P.npad);
+  P.mlsb = b.take<int>(P.npad);
+  P.sexp = b.take<int>(P.npad);
+  return P;
+}
+
+struct EpsLayout {
+  Prep pr, ps;
+  RelStats *sr, *ss;
+  Counters* cnt;
+  float* thr;
+  uint2* cand;
+  unsigned long long *k0, *k1;
+  float *v0, *v1;
+  uint32_t *hist, *scan;
+  size_t bytes;
+};
+
+static EpsLayout layout_eps(void* ws, int64_t nR, int64_t nS, int d, dl_prec prec, bool self, int64_t cap) {
+  EpsLayout L;
+  Bump b(ws);
+  L.cnt = b.take<Counters>(1);
+  L.sr = b.take<RelStats>(1);
+  L.ss = self ? L.sr : b.take<RelStats>(1);
+  L.pr = carve_prep(b, nR, d, prec);
+  L.ps = self ? L.pr : carve_prep(b, nS, d, prec);
+  L.thr = b.take<float>(L.pr.npad);
+  const int64_t c = cap < 1 ? 1 : cap;
+  L.cand = b.take<uint2>(c);
+  L.k0 = b.take<unsigned long long>(c);
+  L.k1 = b.take<unsigned long long>(c);
+  L.v0 = b.take<float>(c);
+  L.v1 = b.take<float>(c);
+  const int64_t hw = radix_hist_words(c);
+  L.hist = b.take<uint32_t>(hw);
+  L.scan = b.take<uint32_t>(scan_scratch_words(hw) + 1);
+  L.bytes = round_up((int64_t)b.off, 256);
+  return L;
+}
+
+struct TopkLayout {
+  Prep pr, ps;
+  RelStats *sr, *ss;
+  Counters* cnt;
+  float* marg;
+  uint2* band;
+  int* bcount;
+  size_t bytes;
+};
+
+static int topk_splits(int64_t nR, int64_t nS, int cu_count, int64_t* tps_out) {
+  const int64_t nTR = (nR + kTile - 1) / kTile, nTS = (nS + kTile - 1) / kTile;
+  int64_t P = (2 * (int64_t)cu_count + nTR - 1) / (nTR < 1 ? 1 : nTR);
+  if (P < 1) P = 1;
+  if (P > nTS) P = nTS < 1 ? 1 : nTS;
+  int64_t tps = (nTS + P - 1) / P;
+  if (tps < 1) tps = 1;
+  P = (nTS + tps - 1) / tps;
+  if (P < 1) P = 1;
+  if (tps_out) *tps_out = tps;
+  return (int)P;
+}
+
+static TopkLayout layout_topk(void* ws, int64_t nR, int64_t nS, int d, dl_prec prec, bool self, int P, int cap) {
+  TopkLayout L;
+  Bump b(ws);
+  L.cnt = b.take<Counters>(1);
+  L.sr = b.take<RelStats>(1);
+  L.ss = self ? L.sr : b.take<RelStats>(1);
+  L.pr = carve_prep(b, nR, d, prec);
+  L.ps = self ? L.pr : carve_prep(b, nS, d, prec);
+  L.marg = b.take<float>(L.pr.npad);
+  L.band = b.take<uint2>((nR < 1 ? 1 : nR) * (int64_t)P * cap);
+  L.bcount = b.take<int>((nR < 1 ? 1 : nR) * (int64_t)P);
+  L.bytes = round_up((int64_t)b.off, 256);
+  return L;
+}
+
+static int bits_for(int64_t n) {  // bits to hold values 0..n-1 (at least 1)
+  int b = 1;
+  while (b < 62 && (1ll << b) < n) ++b;
+  return b;
+}
+
+// Largest double T with sqrt(T) <= eps (sqrt is monotone and correctly
+// rounded, so d2 <= T exactly when sqrt(d2) <= eps).
+static double threshold_from_eps(double eps) {
+  if (std::isinf(eps)) return INFINITY;
+  double x = eps * eps;
+  while (x > 0 && std::sqrt(x) > eps) x = std::nextafter(x, 0.0);
+  for (;;) {
+    const double y = std::nextafter(x, INFINITY);
+    if (std::isinf(y) || std::sqrt(y) > eps) break;
+    x = y;
+  }
+  return x;
+}
+
+}  // namespace dl
+
+using namespace dl;
+
+// ---------------------------------------------------------------- helpers
+static dl_status fail(dl_ctx* c, dl_status s, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+static dl_status fail(dl_ctx* c, dl_status s, const char* fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return s;
+}
+
+#define DL_HIP(c, call)                                                                          \
+  do {                                                                                           \
+    hipError_t e_ = (call);                                                                      \
+    if (e_ != hipSuccess) return fail((c), DL_ERR_DEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+namespace {
+struct StageTimer {
+  dl_ctx* c;
+  int stage;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  StageTimer(dl_ctx* c_, int s, hipStream_t st_) : c(c_), stage(s), st(st_) {
+    if (c->timing && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, st);
+  }
+  ~StageTimer() {
+    if (!a) return;
+    hipEvent_t b;
+    if (hipEventCreate(&b) == hipSuccess) {
+      (void)hipEventRecord(b, st);
+      c->pending->push_back({a, b, stage});
+    } else {
+      (void)hipEventDestroy(a);
+    }
+  }
+};
+
+dl_status check_mat(dl_ctx* c, const dl_mat& m, const char* name) {
+  if (m.n < 0 || m.n >= (1ll << 31)) return fail(c, DL_ERR_INVALID, "%s.n = %lld out of range", name, (long long)m.n);
+  if (m.d < 1 || m.d > kMaxDim) return fail(c, DL_ERR_INVALID, "%s.d = %d out of range [1, %d]", name, m.d, kMaxDim);
+  if (m.ld < m.d) return fail(c, DL_ERR_INVALID, "%s.ld = %lld < d", name, (long long)m.ld);
+  if (m.n > 0 && !m.data) return fail(c, DL_ERR_INVALID, "%s.data is null", name);
+  return DL_OK;
+}
+
+bool prec_ok(int p) { return p == DL_FP32 || p == DL_BF16 || p == DL_FP16 || p == DL_FP8; }
+
+// Counters and both relations' statistics into the pinned block, then wait:
+// the one host synchronisation of a join.
+hipError_t readback(dl_ctx* c, const Counters* cnt, const RelStats* sr, const RelStats* ss, hipStream_t st) {
+  hipError_t e;
+  if ((e = hipMemcpyAsync(c->pinned, cnt, sizeof(Counters), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(c->pinned + 12, sr, sizeof(RelStats), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(c->pinned + 20, ss, sizeof(RelStats), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+  return hipStreamSynchronize(st);
+}
+
+// Rows must be finite, and |x| < 2^62 so that every squared distance
+// (at most (|a| + |b|)^2 < 2^126) and norm is finite in float32.
+dl_status check_inputs(dl_ctx* c) {
+  const RelStats* r = reinterpret_cast<const RelStats*>(c->pinned + 12);
+  const RelStats* s = reinterpret_cast<const RelStats*>(c->pinned + 20);
+  if (r->nonfinite || s->nonfinite)
+    return fail(c, DL_ERR_INVALID, "non-finite values in R (%d) or S (%d)", r->nonfinite, s->nonfinite);
+  if (!(r->xnorm_max < 0x1p62f) || !(s->xnorm_max < 0x1p62f))
+    return fail(c, DL_ERR_INVALID, "row norms up to %g exceed the float32 range of squared distances (2^62)",
+                (double)fmaxf(r->xnorm_max, s->xnorm_max));
+  return DL_OK;
+}
+}  // namespace
+
+extern "C" {
+
+const char* dl_version(void) { return "dlmi 0.1 (gfx950)"; }
+
+dl_status dl_create(int device, dl_ctx** out) {
+  if (!out) return DL_ERR_INVALID;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return DL_ERR_DEVICE;
+  dl_ctx* c = new (std::nothrow) dl_ctx();
+  if (!c) return DL_ERR_OOM;
+  c->device = device;
+  c->pending = new (std::nothrow) std::vector<dl_ctx::Rec>();
+  if (hipSetDevice(device) != hipSuccess || !c->pending ||
+      hipHostMalloc(reinterpret_cast<void**>(&c->pinned), 256, hipHostMallocDefault) != hipSuccess) {
+    delete c->pending;
+    delete c;
+    return DL_ERR_DEVICE;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->cu_count = prop.multiProcessorCount;
+  *out = c;
+  return DL_OK;
+}
+
+void dl_destroy(dl_ctx* c) {
+  if (!c) return;
+  if (c->pending) {
+    for (auto& r : *c->pending) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    delete c->pending;
+  }
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  delete c;
+}
+
+const char* dl_last_error(const dl_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+size_t dl_required_workspace(const dl_ctx* c) { return c ? c->required_ws : 0; }
+
+dl_status dl_set_timing(dl_ctx* c, int enable) {
+  if (!c) return DL_ERR_INVALID;
+  c->timing = enable != 0;
+  return DL_OK;
+}
+
+dl_status dl_get_timing(dl_ctx* c, double* ms, int64_t* calls, int reset) {
+  if (!c) return DL_ERR_INVALID;
+  (void)hipSetDevice(c->device);
+  for (auto& r : *c->pending) {
+    float t = 0.0f;
+    if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+      c->stage_ms[r.stage] += t;
+      c->stage_calls[r.stage] += 1;
+    }
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  c->pending->clear();
+  for (int s = 0; s < DL_NUM_STAGES; ++s) {
+    if (ms) ms[s] = c->stage_ms[s];
+    if (calls) calls[s] = c->stage_calls[s];
+    if (reset) {
+      c->stage_ms[s] = 0;
+      c->stage_calls[s] = 0;
+    }
+  }
+  return DL_OK;
+}
+
+dl_status dl_featurize_rgb8(dl_ctx* c, const uint8_t* patches, int64_t n, int32_t h, int32_t w, int32_t bins,
+                            float* out_hist, void* stream) {
+  if (!c) return DL_ERR_INVALID;
+  c->err.clear();
+  if (n < 0) return fail(c, DL_ERR_INVALID, "n = %lld < 0", (long long)n);
+  if (h < 1 || w < 1 || (int64_t)h * w >= (1 << 24)) return fail(c, DL_ERR_INVALID, "bad patch size %dx%d", h, w);
+  if (bins < 1 || bins > 256 || 256 % bins != 0 || bins * bins * bins > 4096)
+    return fail(c, DL_ERR_INVALID, "bins = %d must divide 256 with bins^3 <= 4096", bins);
+  if (n > 0 && (!patches || !out_hist)) return fail(c, DL_ERR_INVALID, "null pointer");
+  DL_HIP(c, hipSetDevice(c->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  StageTimer t(c, 0, st);
+  DL_HIP(c, launch_hist_rgb8(patches, n, h, w, bins, out_hist, st, c->cu_count));
+  return DL_OK;
+}
+
+dl_status dl_pair_d2(dl_ctx* c, dl_mat R, dl_mat S, const uint32_t* pi, const uint32_t* pj, int64_t m, double* out,
+                     void* stream) {
+  if (!c) return DL_ERR_INVALID;
+  c->err.clear();
+  dl_status s;
+  if ((s = check_mat(c, R, "R")) != DL_OK || (s = check_mat(c, S, "S")) != DL_OK) return s;
+  if (R.d != S.d) return fail(c, DL_ERR_INVALID, "R.d %d != S.d %d", R.d, S.d);
+  if (m < 0) return fail(c, DL_ERR_INVALID, "m < 0");
+  if (m > 0 && (!pi || !pj || !out)) return fail(c, DL_ERR_INVALID, "null pointer");
+  DL_HIP(c, hipSetDevice(c->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // out-of-range flag: a plain store into the context's pinned host block
+  volatile int* bad = reinterpret_cast<volatile int*>(c->pinned + 31);
+  *bad = 0;
+  DL_HIP(c, launch_pair_d2(R.data, R.ld, R.n, S.data, S.ld, S.n, R.d, pi, pj, m, out, (int*)bad, st, c->cu_count));
+  DL_HIP(c, hipStreamSynchronize(st));
+  if (*bad) return fail(c, DL_ERR_INVALID, "pair index out of range");
+  return DL_OK;
+}
+
+size_t dl_join_eps_workspace(int64_t nR, int64_t nS, int32_t d, dl_prec prec, int self_join, int64_t max_cand) {
+  if (nR < 0 || d < 1 || d > kMaxDim || !prec_ok(prec) || max_cand < 0) return 0;
+  if (self_join) nS = nR;
+  return layout_eps(nullptr, nR, nS, d, prec, self_join != 0, max_cand).bytes;
+}
+
+dl_status dl_join_eps(dl_ctx* c, dl_mat R, dl_mat S, int self_join, double eps, dl_prec prec, void* ws,
+                      size_t ws_bytes, dl_pairs* out, void* stream) {
+  if (!c) return DL_ERR_INVALID;
+  c->err.clear();
+  c->required_ws = 0;
+  if (self_join) S = R;
+  dl_status s;
+  if ((s = check_mat(c, R, "R")) != DL_OK || (s = check_mat(c, S, "S")) != DL_OK) return s;
+  if (R.d != S.d) return fail(c, DL_ERR_INVALID, "R.d %d != S.d %d", R.d, S.d);
+  if (std::isnan(eps) || eps < 0) return fail(c, DL_ERR_INVALID, "eps must be >= 0 (got %g)", eps);
+  if (!prec_ok(prec)) return fail(c, DL_ERR_INVALID, "unknown precision %d", (int)prec);
+  if (!out || out->capacity < 0) return fail(c, DL_ERR_INVALID, "bad output struct");
+  if (out->capacity > 0 && (!out->i || !out->j || !out->dist)) return fail(c, DL_ERR_INVALID, "null output array");
+  out->count = out->candidates = out->ties = 0;
+  const bool self = self_join != 0;
+  // candidate capacity from the workspace size
+  const size_t fixed = layout_eps(nullptr, R.n, S.n, R.d, prec, self, 1).bytes;
+  if (!ws || ws_bytes < fixed) {
+    c->required_ws = layout_eps(nullptr, R.n, S.n, R.d, prec, self, 1 << 20).bytes;
+    return fail(c, DL_ERR_WORKSPACE, "workspace of %zu bytes below the minimum %zu", ws_bytes, fixed);
+  }
+  const size_t per = layout_eps(nullptr, R.n, S.n, R.d, prec, self, 1 << 16).bytes - fixed;
+  int64_t cap = (int64_t)((double)(ws_bytes - fixed) / ((double)per / (1 << 16))) - 1024;
+  while (cap > 1 && layout_eps(nullptr, R.n, S.n, R.d, prec, self, cap).bytes > ws_bytes) cap = cap * 63 / 64;
+  if (cap < 1) cap = 1;
+  if (R.n == 0 || S.n == 0) return DL_OK;
+
+  EpsLayout L = layout_eps(ws, R.n, S.n, R.d, prec, self, cap);
+  DL_HIP(c, hipSetDevice(c->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const double T = threshold_from_eps(eps);
+  hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(L.cnt),
+                     (int64_t)(sizeof(Counters) / 4));
+  {
+    StageTimer t(c, 1, st);
+    DL_HIP(c, launch_prep(R.data, R.n, R.d, R.ld, prec, L.pr, L.sr, st, c->cu_count));
+    if (!self) DL_HIP(c, launch_prep(S.data, S.n, S.d, S.ld, prec, L.ps, L.ss, st, c->cu_count));
+    DL_HIP(c, launch_threshold(L.pr, R.n, L.ss, R.d, T, L.thr, nullptr, st));
+  }
+  {
+    StageTimer t(c, 2, st);
+    CandParams p{};
+    p.qa = static_cast<const uint8_t*>(L.pr.q);
+    p.qb = static_cast<const uint8_t*>(L.ps.q);
+    p.qld = L.pr.qld;
+    p.nchunks = (int)(L.pr.qld / kChunkBytes);
+    p.hb = L.ps.h;
+    p.sexa = L.pr.sexp;
+    p.sexb = L.ps.sexp;
+    p.nR = R.n;
+    p.nS = S.n;
+    p.self_join = self;
+    p.thr = L.thr;
+    p.ccount = &L.cnt->cand;
+    p.cand = L.cand;
+    p.ccap = cap;
+    DL_HIP(c, launch_cand_eps(prec, p, st, c->cu_count));
+  }
+  const int bj = bits_for(S.n), bi = bits_for(R.n);
+  {
+    StageTimer t(c, 3, st);
+    RecheckParams q{};
+    q.R = R.data; q.ldr = R.ld;
+    q.S = S.data; q.lds = S.ld;
+    q.d = R.d;
+    q.cand = L.cand; q.ccount = &L.cnt->cand; q.ccap = cap;
+    q.xnR = L.pr.xnorm; q.mlR = L.pr.mlsb;
+    q.xnS = L.ps.xnorm; q.mlS = L.ps.mlsb;
+    q.T = T;
+    q.bj = bj;
+    q.keys = L.k0; q.dist = L.v0; q.ocount = &L.cnt->out; q.nties = &L.cnt->ties;
+    DL_HIP(c, launch_recheck_eps(q, st, c->cu_count));
+  }
+  DL_HIP(c, readback(c, L.cnt, L.sr, L.ss, st));
+  const Counters hc = *reinterpret_cast<const Counters*>(c->pinned);
+  if (dl_status bad = check_inputs(c)) return bad;
+  out->candidates = (int64_t)hc.cand;
+  out->ties = (int64_t)hc.ties;
+  if ((int64_t)hc.cand > cap) {
+    c->required_ws = layout_eps(nullptr, R.n, S.n, R.d, prec, self, (int64_t)hc.cand + (int64_t)hc.cand / 8 + 1024).bytes;
+    return fail(c, DL_ERR_WORKSPACE, "%llu candidates exceed the workspace capacity %lld", hc.cand, (long long)cap);
+  }
+  const int64_t m = (int64_t)hc.out;
+  out->count = m;
+  {
+    StageTimer t(c, 4, st);
+    hipError_t e;
+    const int which = radix_sort_pairs(L.k0, L.v0, L.k1, L.v1, m, bi + bj, L.hist, L.scan, st, &e);
+    DL_HIP(c, e);
+    const int64_t w = m < out->capacity ? m : out->capacity;
+    DL_HIP(c, launch_unpack_pairs(which ? L.k1 : L.k0, which ? L.v1 : L.v0, w, bj, out->i, out->j, out->dist, st,
+                                  c->cu_count));
+  }
+  if (m > out->capacity)
+    return fail(c, DL_ERR_CAPACITY, "%lld pairs exceed the output capacity %lld", (long long)m,
+                (long long)out->capacity);
+  return DL_OK;
+}
+
+size_t dl_join_topk_workspace(int64_t nR, int64_t nS, int32_t d, dl_prec prec, int self_join, int32_t k,
+                              int32_t band_cap) {
+  if (nR < 0 || nS < 0 || d < 1 || d > kMaxDim || !prec_ok(prec) || k < 1) return 0;
+  if (self_join) nS = nR;
+  if (band_cap <= 0) band_cap = 1024;
+  band_cap = (int32_t)round_up(band_cap < 512 ? 512 : band_cap, 64);
+  int cu = 256;
+  int dev;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) cu = prop.multiProcessorCount;
+  const int P = topk_splits(nR, nS, cu, nullptr);
+  return layout_topk(nullptr, nR, nS, d, prec, self_join != 0, P, band_cap).bytes;
+}
+
+dl_status dl_join_topk(dl_ctx* c, dl_mat R, dl_mat S, int self_join, int32_t k, int exclude_self, dl_prec prec,
+                       int32_t band_cap, void* ws, size_t ws_bytes, uint32_t* out_j, float* out_dist,
+                       dl_topk_info* info, void* stream) {
+  if (!c) return DL_ERR_INVALID;
+  c->err.clear();
+  c->required_ws = 0;
+  if (self_join) S = R;
+  dl_status s;
+  if ((s = check_mat(c, R, "R")) != DL_OK || (s = check_mat(c, S, "S")) != DL_OK) return s;
+  if (R.d != S.d) return fail(c, DL_ERR_INVALID, "R.d %d != S.d %d", R.d, S.d);
+  if (k < 1 || k > 256) return fail(c, DL_ERR_INVALID, "k = %d outside [1, 256]", k);
+  if (!prec_ok(prec)) return fail(c, DL_ERR_INVALID, "unknown precision %d", (int)prec);
+  if (R.n > 0 && (!out_j || !out_dist)) return fail(c, DL_ERR_INVALID, "null output array");
+  if (band_cap <= 0) band_cap = 1024;
+  band_cap = (int32_t)round_up(band_cap < 512 ? 512 : band_cap, 64);
+  if (band_cap < 2 * k + kTile) band_cap = (int32_t)round_up(2 * k + kTile, 64);
+  if (info) info->band_entries = info->ties = 0;
+  const bool self = self_join != 0;
+  const bool excl = self && exclude_self;
+  int64_t tps = 1;
+  const int P = topk_splits(R.n, S.n, c->cu_count, &tps);
+  const size_t need = layout_topk(nullptr, R.n, S.n, R.d, prec, self, P, band_cap).bytes;
+  if (!ws || ws_bytes < need) {
+    c->required_ws = need;
+    return fail(c, DL_ERR_WORKSPACE, "workspace of %zu bytes below the %zu needed", ws_bytes, need);
+  }
+  if (R.n == 0) return DL_OK;
+  DL_HIP(c, hipSetDevice(c->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  TopkLayout L = layout_topk(ws, R.n, S.n, R.d, prec, self, P, band_cap);
+  hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(L.cnt),
+                     (int64_t)(sizeof(Counters) / 4));
+  if (S.n == 0) {
+    // nothing to match: every row is padding
+    hipLaunchKernelGGL(zero_words_kernel, dim3(256), dim3(256), 0, st, reinterpret_cast<uint32_t*>(L.bcount),
+                       R.n * (int64_t)P);
+  }
+  {
+    StageTimer t(c, 1, st);
+    DL_HIP(c, launch_prep(R.data, R.n, R.d, R.ld, prec, L.pr, L.sr, st, c->cu_count));
+    if (!self) DL_HIP(c, launch_prep(S.data, S.n, S.d, S.ld, prec, L.ps, L.ss, st, c->cu_count));
+    DL_HIP(c, launch_threshold(L.pr, R.n, L.ss, R.d, 0.0, nullptr, L.marg, st));
+  }
+  if (S.n > 0) {
+    StageTimer t(c, 2, st);
+    CandParams p{};
+    p.qa = static_cast<const uint8_t*>(L.pr.q);
+    p.qb = static_cast<const uint8_t*>(L.ps.q);
+    p.qld = L.pr.qld;
+    p.nchunks = (int)(L.pr.qld / kChunkBytes);
+    p.hb = L.ps.h;
+    p.sexa = L.pr.sexp;
+    p.sexb = L.ps.sexp;
+    p.nR = R.n;
+    p.nS = S.n;
+    p.self_join = self;
+    p.exclude_self = excl;
+    p.P = P;
+    p.k = k;
+    p.cap = band_cap;
+    p.marg = L.marg;
+    p.band = L.band;
+    p.bcount = L.bcount;
+    p.overflow = &L.cnt->overflow;
+    DL_HIP(c, launch_cand_band(prec, p, st));
+  }
+  {
+    StageTimer t(c, 5, st);
+    SelectParams q{};
+    q.R = R.data; q.ldr = R.ld;
+    q.S = S.data; q.lds = S.ld;
+    q.d = R.d; q.nR = R.n;
+    q.band = L.band; q.bcount = L.bcount; q.P = P; q.cap = band_cap; q.k = k;
+    q.marg = L.marg;
+    q.xnR = L.pr.xnorm; q.mlR = L.pr.mlsb;
+    q.sS = L.ss;
+    q.out_j = out_j; q.out_dist = out_dist;
+    q.nband = &L.cnt->band; q.nties = &L.cnt->ties; q.too_many = &L.cnt->too_many;
+    DL_HIP(c, launch_topk_select(q, st));
+  }
+  DL_HIP(c, readback(c, L.cnt, L.sr, L.ss, st));
+  const Counters hc = *reinterpret_cast<const Counters*>(c->pinned);
+  if (dl_status bad = check_inputs(c)) return bad;
+  if (info) {
+    info->band_entries = (int64_t)hc.band;
+    info->ties = (int64_t)hc.ties;
+  }
+  if (hc.overflow || hc.too_many) {
+    c->required_ws = layout_topk(nullptr, R.n, S.n, R.d, prec, self, P, band_cap * 2).bytes;
+    return fail(c, DL_ERR_WORKSPACE, "top-k band exceeded its capacity (%s); retry with band_cap %d",
+                hc.overflow ? "band buffer" : "near-tie contenders", band_cap * 2);
+  }
+  return DL_OK;
+}
+
+}  // extern "C"

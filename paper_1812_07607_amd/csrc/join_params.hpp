@@ -1,0 +1,69 @@
+// join_params.hpp -- launch parameters shared by the join kernels and the
+// C ABI layer.
+#pragma once
+
+#include "dl_internal.hpp"
+
+namespace dl {
+
+// Candidate pass on the matrix cores (join_mfma.hip).
+struct CandParams {
+  const uint8_t* qa;   // R operand rows (qld bytes each, npad rows)
+  const uint8_t* qb;   // S operand rows
+  int64_t qld;         // bytes per operand row (multiple of kChunkBytes)
+  int nchunks;         // qld / kChunkBytes
+  const float* hb;     // S accumulator init h_j (npadS)
+  const int* sexa;     // FP8 row scales of R / S
+  const int* sexb;
+  int64_t nR, nS;      // real rows
+  int64_t nTR, nTS;    // tiles
+  int self_join;       // eps: keep j > i only; band: exclude j == i when excl
+  int exclude_self;
+  // tile order (eps mode)
+  int GM;              // row tiles per group
+  int64_t ngroups;
+  int64_t nlogical;    // logical tiles incl. skipped ones
+  // eps mode
+  const float* thr;    // per R row (npadR)
+  unsigned long long* ccount;  // candidate counter
+  uint2* cand;         // (i, j) records
+  int64_t ccap;
+  // band mode
+  int P;               // S splits
+  int64_t tps;         // S tiles per split
+  int k;
+  int cap;             // band entries per (row, split)
+  const float* marg;   // E_i per R row
+  uint2* band;         // (P~ bits, j): [(row * P + split) * cap + slot]
+  int* bcount;         // [row * P + split]
+  int* overflow;       // set when a band exceeds cap - 256
+};
+
+// eps-join recheck (recheck.hip).
+struct RecheckParams {
+  const float* R; int64_t ldr;
+  const float* S; int64_t lds;
+  int d;
+  const uint2* cand; const unsigned long long* ccount; int64_t ccap;
+  const float* xnR; const int* mlR;
+  const float* xnS; const int* mlS;
+  double T;
+  int bj;  // bits of j in the output key
+  unsigned long long* keys; float* dist; unsigned long long* ocount;
+  unsigned long long* nties;
+};
+
+// top-k exact selection (recheck.hip).
+struct SelectParams {
+  const float* R; int64_t ldr;
+  const float* S; int64_t lds;
+  int d; int64_t nR;
+  uint2* band; const int* bcount; int P; int cap; int k;
+  const float* marg;
+  const float* xnR; const int* mlR;
+  const RelStats* sS;  // S maxima: xnorm_max, mlsb_min
+  uint32_t* out_j; float* out_dist;
+  unsigned long long* nband; unsigned long long* nties; int* too_many;
+};
+
+}  // namespace dl

@@ -1,0 +1,223 @@
+// prep.hip -- operand copies and per-row error bounds for the candidate pass.
+//
+// For every row x of a relation the prep kernel writes the matrix-core
+// operand q (fp32, bf16, fp16 or E4M3 with a power-of-two row scale, zero
+// padded to whole K-chunks) and the quantities the margin of the candidate
+// filter is built from: |x|^2, the accumulator initial value h = fl32(|x|^2)/2,
+// upper bounds on |q~|, |x - q~|, |x| and | |x|^2/2 - h |, and the exponent
+// of the lowest set bit of q~, h and x (an exactness certificate: sums of
+// products on a common binary grid are exact in fp32 while they stay below
+// 2^24 grid steps).  The reduction kernel folds these into maxima over the
+// relation, and the threshold kernel turns them into one float per row of R,
+// so the candidate epilogue needs a single compare per pair.
+//
+// Paper: the Euclidean threshold predicate of image matching (section
+// "Derived Data") evaluated as |a|^2 + |b|^2 - 2 a.b on matrix cores; the
+// margin and the recheck that restore exactness are this library's design.
+#include "dl_internal.hpp"
+
+namespace dl {
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ inline int wave_min(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// One wave per row; rows in [n, npad) get zero operands and zero statistics.
+template <int kPrec>
+__global__ __launch_bounds__(256) void prep_kernel(const float* __restrict__ X, int64_t n, int32_t d,
+                                                   int64_t ld, int64_t dpad, Prep P,
+                                                   RelStats* __restrict__ rs) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= P.npad) return;
+  const bool real = row < n;
+  const float* x = X + (real ? row * ld : 0);
+  int sexp = 0;
+  if (kPrec == DL_FP8 && real) {
+    float amax = 0.0f;
+    for (int k = lane; k < d; k += 64) amax = fmaxf(amax, fabsf(x[k]));
+    amax = wave_max(amax);
+    if (amax > 0.0f && amax <= 3.4e38f) {
+      // smallest s with amax <= 448 * 2^s, clamped to the E8M0 range
+      int s = ilogbf(amax) - 8;
+      while (amax > ldexpf(448.0f, s)) ++s;
+      while (s > -127 && amax <= ldexpf(448.0f, s - 1)) --s;
+      sexp = s < -127 ? -127 : (s > 127 ? 127 : s);
+    }
+  }
+  const float inv_scale = ldexpf(1.0f, -sexp), scale = ldexpf(1.0f, sexp);
+  double nrm2 = 0.0, qn2 = 0.0, r2 = 0.0;
+  int qlsb = kLsbNone, mlsb = kLsbNone, bad = 0;
+  uint8_t* qrow = reinterpret_cast<uint8_t*>(P.q) + row * P.qld;
+  for (int64_t k = lane; k < dpad; k += 64) {
+    float v = (real && k < d) ? x[k] : 0.0f;
+    if (!isfinite(v)) { bad++; v = 0.0f; }
+    float qv;
+    if (kPrec == DL_FP32) {
+      qv = v;
+      reinterpret_cast<float*>(qrow)[k] = v;
+    } else if (kPrec == DL_BF16) {
+      uint16_t c = enc_bf16(v);
+      qv = dec_bf16(c);
+      reinterpret_cast<uint16_t*>(qrow)[k] = c;
+    } else if (kPrec == DL_FP16) {
+      uint16_t c = enc_f16(v);
+      qv = dec_f16(c);
+      reinterpret_cast<uint16_t*>(qrow)[k] = c;
+    } else {
+      uint8_t c = enc_e4m3(v * inv_scale);
+      qv = dec_e4m3(c) * scale;  // exact: power-of-two scale of a normal value
+      qrow[k] = c;
+    }
+    const double dv = v, dq = qv, dr = dv - dq;  // exact in float64
+    nrm2 += dv * dv;
+    qn2 += dq * dq;
+    r2 += dr * dr;
+    qlsb = min(qlsb, lsb_exp(qv));
+    mlsb = min(mlsb, lsb_exp(v));
+  }
+  nrm2 = wave_sum(nrm2);
+  qn2 = wave_sum(qn2);
+  r2 = wave_sum(r2);
+  qlsb = wave_min(qlsb);
+  mlsb = wave_min(mlsb);
+  bad = (int)wave_sum((double)bad);
+  if (lane == 0) {
+    // float64 sums of at most dpad exact squares: relative error <= gamma_dpad
+    const double g = gamma_n((double)dpad + 2.0, 0x1p-53);
+    const float h = ((float)nrm2) * 0.5f;
+    P.nrm2[row] = nrm2;
+    P.h[row] = h;
+    P.qnorm[row] = f32_up(sqrt(qn2 * (1.0 + g)) * (1.0 + 0x1p-50));
+    P.rho[row] = f32_up(sqrt(r2 * (1.0 + g)) * (1.0 + 0x1p-50));
+    P.xnorm[row] = f32_up(sqrt(nrm2 * (1.0 + g)) * (1.0 + 0x1p-50));
+    P.dh[row] = f32_up((fabs(nrm2 * 0.5 - (double)h) + g * nrm2) * (1.0 + 0x1p-50));
+    P.qlsb[row] = qlsb;
+    P.hlsb[row] = lsb_exp(h);
+    P.mlsb[row] = mlsb;
+    P.sexp[row] = sexp;
+    if (bad && real) atomicAdd(&rs->nonfinite, bad);
+  }
+}
+
+__global__ void stats_init_kernel(RelStats* rs) {
+  if (threadIdx.x == 0) {
+    rs->h_max = rs->qnorm_max = rs->rho_max = rs->dh_max = rs->xnorm_max = 0.0f;
+    rs->qlsb_min = rs->hlsb_min = rs->mlsb_min = kLsbNone;
+    rs->nonfinite = 0;
+  }
+}
+
+// Maxima / minima over the real rows.  Non-negative floats order like their
+// bit patterns, so integer atomics suffice.
+__global__ __launch_bounds__(256) void stats_reduce_kernel(Prep P, int64_t n, RelStats* rs) {
+  float hm = 0, qm = 0, rm = 0, dm = 0, xm = 0;
+  int ql = kLsbNone, hl = kLsbNone, ml = kLsbNone;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    hm = fmaxf(hm, P.h[r]);
+    qm = fmaxf(qm, P.qnorm[r]);
+    rm = fmaxf(rm, P.rho[r]);
+    dm = fmaxf(dm, P.dh[r]);
+    xm = fmaxf(xm, P.xnorm[r]);
+    ql = min(ql, P.qlsb[r]);
+    hl = min(hl, P.hlsb[r]);
+    ml = min(ml, P.mlsb[r]);
+  }
+  hm = wave_max(hm); qm = wave_max(qm); rm = wave_max(rm); dm = wave_max(dm); xm = wave_max(xm);
+  ql = wave_min(ql); hl = wave_min(hl); ml = wave_min(ml);
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(reinterpret_cast<unsigned*>(&rs->h_max), __float_as_uint(hm));
+    atomicMax(reinterpret_cast<unsigned*>(&rs->qnorm_max), __float_as_uint(qm));
+    atomicMax(reinterpret_cast<unsigned*>(&rs->rho_max), __float_as_uint(rm));
+    atomicMax(reinterpret_cast<unsigned*>(&rs->dh_max), __float_as_uint(dm));
+    atomicMax(reinterpret_cast<unsigned*>(&rs->xnorm_max), __float_as_uint(xm));
+    atomicMin(&rs->qlsb_min, ql);
+    atomicMin(&rs->hlsb_min, hl);
+    atomicMin(&rs->mlsb_min, ml);
+  }
+}
+
+// Bound E_i on |d~2 - d2_64| over every row j of S, where d~2 = |a|^2 - 2 P~
+// and P~ is the matrix-core value of a.b - h_j (see the derivation in the
+// design notes):
+//   accumulation  2 gamma_{d+2}(h_max + |q~_i| max|q~_j|) + (d+1) 2^-126,
+//                 or 0 when every partial sum is exact on a common grid;
+//   operands      |q~_i| max rho_j + rho_i max|q~_j| + rho_i max rho_j;
+//   init          max | |b|^2/2 - h_j |;
+//   float64       (d+4) 2^-52 ((|a| + max|b|)^2 + |a|^2).
+__device__ inline double row_margin(const Prep& R, const RelStats& s, int64_t i, int d) {
+  const double qa = R.qnorm[i], ra = R.rho[i];
+  const int ql = R.qlsb[i];
+  const int prod = (ql >= kLsbNone || s.qlsb_min >= kLsbNone) ? kLsbNone : ql + s.qlsb_min;
+  const int m = min(prod, s.hlsb_min);
+  const bool exact = m >= -126 && (qa * (double)s.qnorm_max + (double)s.h_max) <= ldexp(1.0, min(m + 24, 1000));
+  const double acc = exact ? 0.0
+                           : 2.0 * gamma_n((double)d + 2.0, 0x1p-24) * ((double)s.h_max + qa * s.qnorm_max) +
+                                 ((double)d + 1.0) * 0x1p-126;
+  const double opnd = qa * s.rho_max + ra * s.qnorm_max + ra * s.rho_max;
+  const double xa = R.xnorm[i], xs = s.xnorm_max;
+  const double canon = ((double)d + 4.0) * 0x1p-52 * ((xa + xs) * (xa + xs) + R.nrm2[i]);
+  return (2.0 * (acc + opnd + (double)s.dh_max) + canon) * (1.0 + 0x1p-40);
+}
+
+// eps mode: thr_i such that P~ >= thr_i for every pair with d2_64 <= T.
+// band mode: marg_i = E_i rounded up (the top-k band is P~ >= P~_(k) - E_i).
+__global__ __launch_bounds__(256) void threshold_kernel(Prep R, int64_t nR, const RelStats* __restrict__ S,
+                                                        int d, double T, float* __restrict__ thr,
+                                                        float* __restrict__ marg) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= R.npad) return;
+  if (i >= nR) {
+    if (thr) thr[i] = INFINITY;
+    if (marg) marg[i] = 0.0f;
+    return;
+  }
+  const RelStats s = *S;
+  const double E = row_margin(R, s, i, d);
+  if (marg) marg[i] = f32_up(E);
+  if (thr) {
+    const double a2 = R.nrm2[i];
+    if (isinf(T)) thr[i] = -INFINITY;
+    else thr[i] = f32_down(0.5 * (a2 - T - E) - 0x1p-50 * (fabs(a2) + fabs(T) + E));
+  }
+}
+
+hipError_t launch_prep(const float* X, int64_t n, int32_t d, int64_t ld, dl_prec prec, const Prep& P,
+                       RelStats* rs, hipStream_t st, int cu_count) {
+  hipLaunchKernelGGL(stats_init_kernel, dim3(1), dim3(64), 0, st, rs);
+  const int64_t dpad = dpad_of(d, prec);
+  const dim3 grid((unsigned)((P.npad + 3) / 4)), block(256);
+  switch (prec) {
+    case DL_FP32: hipLaunchKernelGGL(prep_kernel<DL_FP32>, grid, block, 0, st, X, n, d, ld, dpad, P, rs); break;
+    case DL_BF16: hipLaunchKernelGGL(prep_kernel<DL_BF16>, grid, block, 0, st, X, n, d, ld, dpad, P, rs); break;
+    case DL_FP16: hipLaunchKernelGGL(prep_kernel<DL_FP16>, grid, block, 0, st, X, n, d, ld, dpad, P, rs); break;
+    case DL_FP8: hipLaunchKernelGGL(prep_kernel<DL_FP8>, grid, block, 0, st, X, n, d, ld, dpad, P, rs); break;
+  }
+  if (n > 0) {
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > (int64_t)cu_count * 4) blocks = (int64_t)cu_count * 4;
+    hipLaunchKernelGGL(stats_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, st, P, n, rs);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_threshold(const Prep& R, int64_t nR, const RelStats* S, int d, double T, float* thr,
+                            float* marg, hipStream_t st) {
+  const dim3 grid((unsigned)((R.npad + 255) / 256));
+  hipLaunchKernelGGL(threshold_kernel, grid, dim3(256), 0, st, R, nR, S, d, T, thr, marg);
+  return hipGetLastError();
+}
+
+}  // namespace dl

@@ -1,0 +1,217 @@
+"""Python entry points over libdlmi.so, on torch device tensors.
+
+PyTorch supplies device memory (tensors) and streams; every step of the
+featurisation and the joins runs in the library's HIP kernels.  Calls go to
+the GPU path only: when the library or a GPU is missing they raise.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+
+_ctx_cache = {}
+
+
+def _stream_ptr(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """One dl_ctx per device (created lazily, destroyed at exit)."""
+
+    def __init__(self, device: int = 0):
+        L = _lib.load()
+        self.L = L
+        self.device = device
+        h = ctypes.c_void_p()
+        st = L.dl_create(device, ctypes.byref(h))
+        if st != _lib.DL_OK:
+            raise _lib.DLError(st, "dl_create(%d) failed" % device)
+        self.h = h
+
+    def check(self, st: int):
+        if st != _lib.DL_OK:
+            raise _lib.DLError(st, self.L.dl_last_error(self.h).decode())
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                self.L.dl_destroy(self.h)
+        except Exception:
+            pass
+
+    def set_timing(self, on: bool):
+        self.check(self.L.dl_set_timing(self.h, int(on)))
+
+    def timing(self, reset: bool = False):
+        ms = (ctypes.c_double * _lib.NUM_STAGES)()
+        calls = (ctypes.c_int64 * _lib.NUM_STAGES)()
+        self.check(self.L.dl_get_timing(self.h, ms, calls, int(reset)))
+        return {name: (ms[s], calls[s]) for s, name in enumerate(_lib.STAGES)}
+
+
+def context(device=None) -> Context:
+    if not torch.cuda.is_available():
+        raise RuntimeError("the dlmi library needs a ROCm GPU; none is visible")
+    dev = torch.cuda.current_device() if device is None else int(device)
+    c = _ctx_cache.get(dev)
+    if c is None:
+        c = _ctx_cache[dev] = Context(dev)
+    return c
+
+
+def _mat(x: torch.Tensor) -> _lib.dl_mat:
+    if x.dtype != torch.float32 or x.dim() != 2 or not x.is_cuda:
+        raise TypeError("expected a 2-D float32 CUDA tensor")
+    if x.shape[0] > 0 and x.stride(1) != 1:
+        raise ValueError("rows must be contiguous")
+    ld = x.stride(0) if x.shape[0] > 1 else x.shape[1]
+    return _lib.dl_mat(x.data_ptr(), x.shape[0], x.shape[1], max(ld, x.shape[1]))
+
+
+# ---------------------------------------------------------------- featurise
+def featurize_rgb8(patches: torch.Tensor, bins: int = 8, out: torch.Tensor | None = None,
+                   stream=None) -> torch.Tensor:
+    """Colour histograms (bins^3, L1-normalised) of uint8 (n, h, w, 3) patches."""
+    if patches.dtype != torch.uint8 or patches.dim() != 4 or patches.shape[3] != 3 or not patches.is_cuda:
+        raise TypeError("patches must be a (n, h, w, 3) uint8 CUDA tensor")
+    patches = patches.contiguous()
+    n, h, w, _ = patches.shape
+    if out is None:
+        out = torch.empty((n, bins ** 3), dtype=torch.float32, device=patches.device)
+    c = context(patches.device.index)
+    c.check(c.L.dl_featurize_rgb8(c.h, ctypes.c_void_p(patches.data_ptr()), n, h, w, bins,
+                                  ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    return out
+
+
+# ---------------------------------------------------------------- distances
+def pair_d2(R: torch.Tensor, S: torch.Tensor, pi: torch.Tensor, pj: torch.Tensor, stream=None) -> torch.Tensor:
+    """Canonical float64 squared distances of listed pairs."""
+    pi = pi.to(device=R.device, dtype=torch.int32).contiguous()
+    pj = pj.to(device=R.device, dtype=torch.int32).contiguous()
+    out = torch.empty(pi.shape[0], dtype=torch.float64, device=R.device)
+    c = context(R.device.index)
+    c.check(c.L.dl_pair_d2(c.h, _mat(R), _mat(S), ctypes.c_void_p(pi.data_ptr()), ctypes.c_void_p(pj.data_ptr()),
+                           pi.shape[0], ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    return out
+
+
+# ---------------------------------------------------------------- eps-join
+@dataclass
+class EpsResult:
+    i: torch.Tensor      # int32 (as uint32 bits), sorted by (i, j)
+    j: torch.Tensor
+    dist: torch.Tensor   # float32
+    count: int
+    candidates: int
+    ties: int
+
+
+class Workspace:
+    """Growable device scratch buffer (a torch uint8 tensor)."""
+
+    def __init__(self, device):
+        self.device = device
+        self.buf = torch.empty(0, dtype=torch.uint8, device=device)
+
+    def get(self, nbytes: int) -> torch.Tensor:
+        if self.buf.numel() < nbytes:
+            self.buf = None
+            self.buf = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        return self.buf
+
+
+_ws = {}
+
+
+def _workspace(device) -> Workspace:
+    w = _ws.get(device)
+    if w is None:
+        w = _ws[device] = Workspace(device)
+    return w
+
+
+def join_eps(R: torch.Tensor, S: torch.Tensor | None, eps: float, prec: str = "bf16",
+             max_candidates: int | None = None, capacity: int | None = None, stream=None,
+             workspace: Workspace | None = None, out: tuple | None = None) -> EpsResult:
+    """eps-join: all (i, j) with canonical distance <= eps (S=None: self-join
+    of R with i < j), sorted by (i, j).  Grows the workspace and the output
+    and retries when either is too small."""
+    self_join = S is None
+    Sm = R if self_join else S
+    c = context(R.device.index)
+    ws = workspace or _workspace(R.device)
+    p = _lib.PREC[prec]
+    nR, nS, d = R.shape[0], Sm.shape[0], R.shape[1]
+    if max_candidates is None:
+        max_candidates = max(1 << 20, 4 * (nR + nS))
+    cap = capacity if capacity is not None else max(1 << 16, nR + nS)
+    for _ in range(8):
+        need = c.L.dl_join_eps_workspace(nR, nS, d, p, int(self_join), max_candidates)
+        buf = ws.get(need)
+        if out is not None and out[0].numel() >= cap:
+            oi, oj, od = out
+        else:
+            oi = torch.empty(cap, dtype=torch.int32, device=R.device)
+            oj = torch.empty(cap, dtype=torch.int32, device=R.device)
+            od = torch.empty(cap, dtype=torch.float32, device=R.device)
+        pr = _lib.dl_pairs(oi.data_ptr(), oj.data_ptr(), od.data_ptr(), cap, 0, 0, 0)
+        st = c.L.dl_join_eps(c.h, _mat(R), _mat(Sm), int(self_join), float(eps), p,
+                             ctypes.c_void_p(buf.data_ptr()), buf.numel(), ctypes.byref(pr), _stream_ptr(stream))
+        if st == _lib.DL_ERR_WORKSPACE:
+            req = c.L.dl_required_workspace(c.h)
+            max_candidates = max(2 * max_candidates, int(pr.candidates * 1.25) + 1024)
+            if req > 0 and c.L.dl_join_eps_workspace(nR, nS, d, p, int(self_join), max_candidates) < req:
+                max_candidates *= 2
+            continue
+        if st == _lib.DL_ERR_CAPACITY:
+            cap = int(pr.count)
+            out = None
+            continue
+        c.check(st)
+        m = int(pr.count)
+        return EpsResult(oi[:m], oj[:m], od[:m], m, int(pr.candidates), int(pr.ties))
+    raise RuntimeError("join_eps did not converge on workspace / capacity")
+
+
+# ---------------------------------------------------------------- top-k
+@dataclass
+class TopkResult:
+    j: torch.Tensor      # int32 (nR, k); -1 (UINT32_MAX) pads
+    dist: torch.Tensor   # float32 (nR, k); +inf pads
+    band_entries: int
+    ties: int
+
+
+def join_topk(R: torch.Tensor, S: torch.Tensor | None, k: int, exclude_self: bool = False, prec: str = "bf16",
+              band_cap: int = 0, stream=None, workspace: Workspace | None = None) -> TopkResult:
+    """k nearest rows of S (S=None: of R itself) for every row of R, by
+    canonical distance with ties to the smaller index."""
+    self_join = S is None
+    Sm = R if self_join else S
+    c = context(R.device.index)
+    ws = workspace or _workspace(R.device)
+    p = _lib.PREC[prec]
+    nR, nS, d = R.shape[0], Sm.shape[0], R.shape[1]
+    oj = torch.empty((nR, k), dtype=torch.int32, device=R.device)
+    od = torch.empty((nR, k), dtype=torch.float32, device=R.device)
+    info = _lib.dl_topk_info()
+    for _ in range(6):
+        need = c.L.dl_join_topk_workspace(nR, nS, d, p, int(self_join), k, band_cap)
+        buf = ws.get(need)
+        st = c.L.dl_join_topk(c.h, _mat(R), _mat(Sm), int(self_join), k, int(exclude_self), p, band_cap,
+                              ctypes.c_void_p(buf.data_ptr()), buf.numel(), ctypes.c_void_p(oj.data_ptr()),
+                              ctypes.c_void_p(od.data_ptr()), ctypes.byref(info), _stream_ptr(stream))
+        if st == _lib.DL_ERR_WORKSPACE:
+            band_cap = max(2 * (band_cap or 1024), 1024)
+            continue
+        c.check(st)
+        return TopkResult(oj, od, int(info.band_entries), int(info.ties))
+    raise RuntimeError("join_topk did not converge on band capacity")
+

@@ -1,0 +1,82 @@
+"""GPU parity of the top-k join against the float64 oracle: every row's k
+indices equal the oracle's, in order (ties to the smaller index)."""
+import numpy as np
+import pytest
+
+from gpu_util import assert_topk_equal, dev, host
+from paper_1812_07607_amd import ops, synth
+
+pytestmark = pytest.mark.gpu
+PRECS = ["fp32", "bf16", "fp16", "fp8"]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_mixture_top10(orc, prec):
+    """Unit-norm 1,000-centre mixture rows (sigma 0.05), d = 128, top-10."""
+    R = synth.gaussian_mixture_unit(1500, 128, 50, seed=303)
+    S = synth.gaussian_mixture_unit(6000, 128, 50, seed=303, stream=1)
+    ref_j, _, ref_dist = orc.topk(R, S, 10)
+    got = ops.join_topk(dev(R), dev(S), 10, prec=prec)
+    assert_topk_equal(got, ref_j, ref_dist, 128, "mixture/" + prec)
+    assert got.band_entries >= 1500 * 10
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_fp8_store_shape_top32(orc, prec):
+    """d = 256 queries against a store, top-32 (the FP8 workload's shape)."""
+    Q = synth.gaussian_mixture_unit(300, 256, 64, seed=404, stream=1)
+    S = synth.gaussian_mixture_unit(20000, 256, 64, seed=404)
+    ref_j, _, ref_dist = orc.topk(Q, S, 32)
+    got = ops.join_topk(dev(Q), dev(S), 32, prec=prec)
+    assert_topk_equal(got, ref_j, ref_dist, 256, "store/" + prec)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_self_exclude(orc, prec):
+    X = synth.gaussian_mixture_unit(900, 40, 9, seed=5)
+    X[10] = X[20]
+    ref_j, _, ref_dist = orc.topk(X, None, 7, exclude_self=True)
+    got = ops.join_topk(dev(X), None, 7, exclude_self=True, prec=prec)
+    assert_topk_equal(got, ref_j, ref_dist, 40, "self/" + prec)
+    ref_j, _, ref_dist = orc.topk(X, None, 7)
+    got = ops.join_topk(dev(X), None, 7, prec=prec)
+    assert_topk_equal(got, ref_j, ref_dist, 40, "self-incl/" + prec)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_ties_at_kth(orc, prec):
+    """Integer-grid rows: many equal distances at and inside the k-th."""
+    R = synth.integer_grid_rows(200, 6, levels=3, seed=6)
+    S = synth.integer_grid_rows(700, 6, levels=3, seed=6, stream=1)
+    for k in (1, 5, 16):
+        ref_j, _, ref_dist = orc.topk(R, S, k)
+        got = ops.join_topk(dev(R), dev(S), k, prec=prec)
+        assert_topk_equal(got, ref_j, ref_dist, 6, "grid k=%d/%s" % (k, prec))
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("shape", [(1, 1, 1, 1), (5, 3, 7, 10), (300, 40, 33, 64), (257, 513, 130, 3)])
+def test_ragged_and_padding(orc, prec, shape):
+    nR, nS, d, k = shape
+    R = synth.uniform_rows(nR, d, seed=nR)
+    S = synth.uniform_rows(nS, d, seed=nR, stream=1)
+    ref_j, _, ref_dist = orc.topk(R, S, k)
+    got = ops.join_topk(dev(R), dev(S), k, prec=prec)
+    assert_topk_equal(got, ref_j, ref_dist, d, "%s/%s" % (shape, prec))
+
+
+def test_small_band_capacity_retry(orc):
+    R = synth.gaussian_mixture_unit(100, 16, 2, seed=8)
+    S = synth.gaussian_mixture_unit(5000, 16, 2, seed=8, stream=1)
+    ref_j, _, ref_dist = orc.topk(R, S, 200)
+    got = ops.join_topk(dev(R), dev(S), 200, prec="fp8", band_cap=512)
+    assert_topk_equal(got, ref_j, ref_dist, 16, "k=200 fp8")
+
+
+def test_histogram_topk(orc):
+    cfg = synth.config2(0.03)
+    H = orc.hist_rgb8(cfg["patches"], 8)
+    ref_j, _, ref_dist = orc.topk(H, None, 5, exclude_self=True)
+    got = ops.join_topk(dev(H), None, 5, exclude_self=True, prec="fp16")
+    assert_topk_equal(got, ref_j, ref_dist, 512, "histograms")
+    assert got.ties == 0  # exact on the 2^-10 grid: no float64 needed
