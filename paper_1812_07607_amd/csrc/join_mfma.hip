@@ -17,13 +17,15 @@
 //
 // Layout: 512 threads = 8 waves in a 2 x 4 grid, each wave owns 128 x 64
 // outputs as 8 x 4 blocks of 16 x 16 (v_mfma_*_16x16x*), 32 f32x4
-// accumulators.  Operands stream global -> registers -> LDS (single LDS
-// stage of 2 x 256 rows x 144 bytes; the 16-byte row pad makes the 16-row
-// fragment reads conflict-free), with the next step's global loads issued
-// before the current step's MFMAs so the tile pipeline never drains between
-// tiles.  Workgroups are persistent; tiles are ordered in groups of GM row
-// tiles and dealt to the 8 XCDs in contiguous runs so that each XCD's L2
-// holds the row tiles of its group while S tiles stream past.
+// accumulators.  Operands move global -> LDS directly
+// (global_load_lds_dwordx4, no staging registers) into a two-stage ring of
+// 2 x 256 rows x 128 bytes per stage; the 16-byte slot of logical piece c of
+// row r is stored at c ^ ((r >> 1) & 7), which makes the 16-row fragment
+// reads conflict-free.  The loads of step s+1 are issued right after the
+// barrier that opens step s, so they overlap its MFMAs and epilogue, across
+// tile boundaries too.  Workgroups are persistent; tiles are ordered in
+// groups of GM row tiles and dealt to the 8 XCDs in contiguous runs so that
+// each XCD's L2 holds the row tiles of its group while S tiles stream past.
 #include "join_params.hpp"
 
 namespace dl {
@@ -34,8 +36,14 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kThreads = 512;
-constexpr int kLdsRow = kChunkBytes + 16;  // padded LDS row stride in bytes
-constexpr int kWaveM = 128, kWaveN = 64;   // outputs per wave
+constexpr int kStageBytes = kTile * kChunkBytes;  // one operand, one K-chunk
+constexpr int kWaveM = 128, kWaveN = 64;          // outputs per wave
+
+typedef __attribute__((address_space(1))) void gvoid_t;
+typedef __attribute__((address_space(3))) void lvoid_t;
+
+// LDS byte offset of logical 16-byte piece c of tile row r.
+__device__ inline int lds_off(int r, int c) { return r * kChunkBytes + ((c ^ ((r >> 1) & 7)) << 4); }
 
 enum : int { kModeEps = 0, kModeBand = 1 };
 
@@ -100,27 +108,23 @@ struct TileIter {
 };
 
 // ----------------------------------------------------- operand movement
-__device__ inline void load_regs(const CandParams& p, int64_t ti, int64_t tj, int chunk, uint4 (&ra)[4],
-                                 uint4 (&rb)[4]) {
-  const int tid = threadIdx.x;
+// One K-chunk of both operand tiles, global -> LDS.  Each wave moves rows
+// [8q, 8q+8) for q = 4 * wave + t (t < 4) of each operand with one 1 KiB
+// global_load_lds_dwordx4: lane l fills LDS slot l of that block, i.e.
+// row 8q + l/8, physical piece l%8, so it fetches logical piece
+// (l%8) ^ ((row >> 1) & 7) of that row.
+__device__ inline void issue_loads(const CandParams& p, int64_t ti, int64_t tj, int chunk, uint8_t* la, uint8_t* lb) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t koff = (int64_t)chunk * kChunkBytes;
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    const int piece = tid + kThreads * t;  // 2048 pieces of 16 B per operand
-    const int row = piece >> 3, c16 = piece & 7;
-    const int64_t off = (int64_t)chunk * kChunkBytes + c16 * 16;
-    ra[t] = *reinterpret_cast<const uint4*>(p.qa + (ti * kTile + row) * p.qld + off);
-    rb[t] = *reinterpret_cast<const uint4*>(p.qb + (tj * kTile + row) * p.qld + off);
-  }
-}
-
-__device__ inline void store_lds(uint8_t* la, uint8_t* lb, const uint4 (&ra)[4], const uint4 (&rb)[4]) {
-  const int tid = threadIdx.x;
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int piece = tid + kThreads * t;
-    const int row = piece >> 3, c16 = piece & 7;
-    *reinterpret_cast<uint4*>(la + row * kLdsRow + c16 * 16) = ra[t];
-    *reinterpret_cast<uint4*>(lb + row * kLdsRow + c16 * 16) = rb[t];
+    const int q = wave * 4 + t;
+    const int row = q * 8 + (lane >> 3);
+    const int c = (lane & 7) ^ ((row >> 1) & 7);
+    const uint8_t* ga = p.qa + (ti * kTile + row) * p.qld + koff + c * 16;
+    const uint8_t* gb = p.qb + (tj * kTile + row) * p.qld + koff + c * 16;
+    __builtin_amdgcn_global_load_lds((gvoid_t*)ga, (lvoid_t*)(la + q * 8 * kChunkBytes), 16, 0, 0);
+    __builtin_amdgcn_global_load_lds((gvoid_t*)gb, (lvoid_t*)(lb + q * 8 * kChunkBytes), 16, 0, 0);
   }
 }
 
@@ -130,8 +134,8 @@ __device__ inline void store_lds(uint8_t* la, uint8_t* lb, const uint4 (&ra)[4],
 // so the dot product is over all k of the chunk whatever order the matrix
 // core assigns to the slots.
 template <int kPrec>
-__device__ inline void mma_chunk(f32x4 (&acc)[8][4], const uint8_t* la, const uint8_t* lb, const int (&sa)[8],
-                                 const int (&sb)[4]) {
+__device__ inline void mma_chunk(f32x4 (&acc)[8][4], const uint8_t* la, const uint8_t* lb, int ra0, int rb0,
+                                 const int (&sa)[8], const int (&sb)[4]) {
   const int lane = threadIdx.x & 63;
   const int r16 = lane & 15, grp = lane >> 4;
   if constexpr (kPrec == DL_BF16 || kPrec == DL_FP16) {
@@ -140,10 +144,10 @@ __device__ inline void mma_chunk(f32x4 (&acc)[8][4], const uint8_t* la, const ui
       uint4 bq[4];
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb)
-        bq[nb] = *reinterpret_cast<const uint4*>(lb + (nb * 16 + r16) * kLdsRow + ks * 64 + grp * 16);
+        bq[nb] = *reinterpret_cast<const uint4*>(lb + lds_off(rb0 + nb * 16 + r16, ks * 4 + grp));
 #pragma unroll
       for (int mb = 0; mb < 8; ++mb) {
-        const uint4 aq = *reinterpret_cast<const uint4*>(la + (mb * 16 + r16) * kLdsRow + ks * 64 + grp * 16);
+        const uint4 aq = *reinterpret_cast<const uint4*>(la + lds_off(ra0 + mb * 16 + r16, ks * 4 + grp));
 #pragma unroll
         for (int nb = 0; nb < 4; ++nb) {
           if constexpr (kPrec == DL_BF16)
@@ -162,14 +166,16 @@ __device__ inline void mma_chunk(f32x4 (&acc)[8][4], const uint8_t* la, const ui
     i32x8 bq[4];
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb) {
-      const uint8_t* src = lb + (nb * 16 + r16) * kLdsRow + grp * 32;
-      const uint4 x0 = *reinterpret_cast<const uint4*>(src), x1 = *reinterpret_cast<const uint4*>(src + 16);
+      const int r = rb0 + nb * 16 + r16;
+      const uint4 x0 = *reinterpret_cast<const uint4*>(lb + lds_off(r, 2 * grp));
+      const uint4 x1 = *reinterpret_cast<const uint4*>(lb + lds_off(r, 2 * grp + 1));
       bq[nb] = i32x8{(int)x0.x, (int)x0.y, (int)x0.z, (int)x0.w, (int)x1.x, (int)x1.y, (int)x1.z, (int)x1.w};
     }
 #pragma unroll
     for (int mb = 0; mb < 8; ++mb) {
-      const uint8_t* src = la + (mb * 16 + r16) * kLdsRow + grp * 32;
-      const uint4 x0 = *reinterpret_cast<const uint4*>(src), x1 = *reinterpret_cast<const uint4*>(src + 16);
+      const int r = ra0 + mb * 16 + r16;
+      const uint4 x0 = *reinterpret_cast<const uint4*>(la + lds_off(r, 2 * grp));
+      const uint4 x1 = *reinterpret_cast<const uint4*>(la + lds_off(r, 2 * grp + 1));
       const i32x8 aq = {(int)x0.x, (int)x0.y, (int)x0.z, (int)x0.w, (int)x1.x, (int)x1.y, (int)x1.z, (int)x1.w};
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb)
@@ -183,10 +189,10 @@ __device__ inline void mma_chunk(f32x4 (&acc)[8][4], const uint8_t* la, const ui
       float4 bq[4];
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb)
-        bq[nb] = *reinterpret_cast<const float4*>(lb + (nb * 16 + r16) * kLdsRow + half * 64 + grp * 16);
+        bq[nb] = *reinterpret_cast<const float4*>(lb + lds_off(rb0 + nb * 16 + r16, half * 4 + grp));
 #pragma unroll
       for (int mb = 0; mb < 8; ++mb) {
-        const float4 aq = *reinterpret_cast<const float4*>(la + (mb * 16 + r16) * kLdsRow + half * 64 + grp * 16);
+        const float4 aq = *reinterpret_cast<const float4*>(la + lds_off(ra0 + mb * 16 + r16, half * 4 + grp));
 #pragma unroll
         for (int nb = 0; nb < 4; ++nb) {
           acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(aq.x, bq[nb].x, acc[mb][nb], 0, 0, 0);
@@ -288,7 +294,7 @@ __device__ inline uint32_t kth_largest_key(const uint2* e, int n, int k) {
 }
 
 // Tighten one row's band to P~_(k) - E_i and drop what falls below it.
-__device__ inline void compact_row(const CandParams& p, uint2* e, int n, float marg, float* bthr, int* bcnt) {
+__device__ __attribute__((noinline)) void compact_row(const CandParams& p, uint2* e, int n, float marg, float* bthr, int* bcnt) {
   const int lane = threadIdx.x & 63;
   float thr = *bthr;
   if (n >= p.k) {
@@ -359,8 +365,8 @@ __device__ inline void epilogue_band(const CandParams& p, int64_t ti, int64_t tj
 // ------------------------------------------------------------------ kernel
 template <int kPrec, int kMode>
 __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
-  __shared__ __attribute__((aligned(16))) uint8_t lds_a[kTile * kLdsRow];
-  __shared__ __attribute__((aligned(16))) uint8_t lds_b[kTile * kLdsRow];
+  // two stages of (A chunk, B chunk)
+  __shared__ __attribute__((aligned(1024))) uint8_t lds_ab[2][2][kStageBytes];
   __shared__ __attribute__((aligned(16))) float lds_thr[kMode == kModeBand ? kTile : 1];
   __shared__ int lds_cnt[kMode == kModeBand ? kTile : 1];
 
@@ -379,15 +385,11 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
       lds_cnt[r] = 0;
     }
   }
-  int chunk = 0;
-  uint4 ra[4], rb[4];
-  load_regs(p, ti, tj, 0, ra, rb);
+  int chunk = 0, stage = 0;
+  issue_loads(p, ti, tj, 0, lds_ab[0][0], lds_ab[0][1]);
   f32x4 acc[8][4];
   int sa[8], sb[4];
   for (;;) {
-    __syncthreads();
-    store_lds(lds_a, lds_b, ra, rb);
-    __syncthreads();
     int64_t nti = ti, ntj = tj;
     int nchunk = chunk + 1;
     bool more = true;
@@ -395,7 +397,11 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
       nchunk = 0;
       more = it.next(p, kMode, nti, ntj);
     }
-    if (more) load_regs(p, nti, ntj, nchunk, ra, rb);
+    // this step's operands are in LDS, and every wave is done with the
+    // other stage (it computed the previous step before this barrier)
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (more) issue_loads(p, nti, ntj, nchunk, lds_ab[stage ^ 1][0], lds_ab[stage ^ 1][1]);
     if (chunk == 0) {
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb) {
@@ -410,7 +416,7 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
         for (int mb = 0; mb < 8; ++mb) sa[mb] = p.sexa[ti * kTile + wm * kWaveM + mb * 16 + (lane & 15)] + 127;
       }
     }
-    mma_chunk<kPrec>(acc, lds_a + wm * kWaveM * kLdsRow, lds_b + wn * kWaveN * kLdsRow, sa, sb);
+    mma_chunk<kPrec>(acc, lds_ab[stage][0], lds_ab[stage][1], wm * kWaveM, wn * kWaveN, sa, sb);
     if (chunk == p.nchunks - 1) {
       if constexpr (kMode == kModeEps) epilogue_eps(p, ti, tj, acc);
       else epilogue_band(p, ti, tj, split, acc, lds_thr, lds_cnt);
@@ -419,6 +425,7 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
     ti = nti;
     tj = ntj;
     chunk = nchunk;
+    stage ^= 1;
   }
   if constexpr (kMode == kModeBand) {
     __syncthreads();

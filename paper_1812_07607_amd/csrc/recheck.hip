@@ -47,43 +47,60 @@ __device__ inline double beta32(double d2, int d, double xsum) {
 // ------------------------------------------------------------ eps recheck
 
 
+// A wave takes 64 candidates at a time: it computes their float32 distances
+// one after the other with all lanes (coalesced row reads), lane t keeping
+// candidate t's sum, then classifies the 64 lane-parallel and appends the
+// confirmed ones with a single atomic.
 __global__ __launch_bounds__(256) void recheck_eps_kernel(RecheckParams p) {
   const int lane = threadIdx.x & 63;
   const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
   const int64_t n = min((int64_t)*p.ccount, p.ccap);
-  for (int64_t c = gw; c < n; c += nw) {
-    const uint2 ij = p.cand[c];
-    const float* a = p.R + (int64_t)ij.x * p.ldr;
-    const float* b = p.S + (int64_t)ij.y * p.lds;
-    float s = 0.0f;
-    for (int k = lane; k < p.d; k += 64) {
-      const float t = a[k] - b[k];
-      s = fmaf(t, t, s);
-    }
-    s = wave_sumf(s);
-    const double d2 = s;
-    const double xsum = (double)p.xnR[ij.x] + (double)p.xnS[ij.y];
-    const bool ex = exact32(min(p.mlR[ij.x], p.mlS[ij.y]), xsum);
-    const double bt = ex ? 0.0 : beta32(d2, p.d, xsum);
-    const double hi = ex ? d2 : (d2 + bt) * (1.0 + 0x1p-50);
-    const double lo = ex ? d2 : (d2 - bt) * (1.0 - 0x1p-50);
-    bool in = hi <= p.T;
-    float dist = sqrtf(s);
-    if (!in && !(lo > p.T)) {  // boundary tie: canonical float64 decides
-      double d64 = 0.0;
-      if (lane == 0) d64 = canonical_d2(a, b, p.d);
-      d64 = __shfl(d64, 0, 64);
-      in = d64 <= p.T;
-      dist = (float)sqrt(d64);
-      if (lane == 0) atomicAdd(p.nties, 1ull);
-    }
-    if (in && lane == 0) {
-      const unsigned long long pos = atomicAdd(p.ocount, 1ull);
-      if (pos < (unsigned long long)p.ccap) {
-        p.keys[pos] = ((unsigned long long)ij.x << p.bj) | ij.y;
-        p.dist[pos] = dist;
+  const uint64_t lt = __lanemask_lt();
+  for (int64_t base = gw * 64; base < n; base += nw * 64) {
+    const int cnt = (int)min((int64_t)64, n - base);
+    const uint2 mine = lane < cnt ? p.cand[base + lane] : make_uint2(0, 0);
+    float mys = 0.0f;
+    for (int t = 0; t < cnt; ++t) {
+      const uint32_t ci = __shfl(mine.x, t, 64), cj = __shfl(mine.y, t, 64);
+      const float* a = p.R + (int64_t)ci * p.ldr;
+      const float* b = p.S + (int64_t)cj * p.lds;
+      float s = 0.0f;
+      for (int k = lane; k < p.d; k += 64) {
+        const float u = a[k] - b[k];
+        s = fmaf(u, u, s);
       }
+      s = wave_sumf(s);
+      if (lane == t) mys = s;
+    }
+    bool in = false, tie = false;
+    float dist = 0.0f;
+    if (lane < cnt) {
+      const double d2 = mys;
+      const double xsum = (double)p.xnR[mine.x] + (double)p.xnS[mine.y];
+      const bool ex = exact32(min(p.mlR[mine.x], p.mlS[mine.y]), xsum);
+      const double bt = ex ? 0.0 : beta32(d2, p.d, xsum);
+      const double hi = ex ? d2 : (d2 + bt) * (1.0 + 0x1p-50);
+      const double lo = ex ? d2 : (d2 - bt) * (1.0 - 0x1p-50);
+      in = hi <= p.T;
+      dist = sqrtf(mys);
+      if (!in && !(lo > p.T)) {  // boundary tie: the canonical float64 value decides
+        tie = true;
+        const double d64 = canonical_d2(p.R + (int64_t)mine.x * p.ldr, p.S + (int64_t)mine.y * p.lds, p.d);
+        in = d64 <= p.T;
+        dist = (float)sqrt(d64);
+      }
+    }
+    const uint64_t mi = __ballot(in), mt = __ballot(tie);
+    unsigned long long pos = 0;
+    if (lane == 0) {
+      if (mi) pos = atomicAdd(p.ocount, (unsigned long long)__popcll(mi));
+      if (mt) atomicAdd(p.nties, (unsigned long long)__popcll(mt));
+    }
+    pos = __shfl(pos, 0, 64) + __popcll(mi & lt);
+    if (in && pos < (unsigned long long)p.ccap) {
+      p.keys[pos] = ((unsigned long long)mine.x << p.bj) | mine.y;
+      p.dist[pos] = dist;
     }
   }
 }

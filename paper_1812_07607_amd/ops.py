@@ -152,6 +152,8 @@ def join_eps(R: torch.Tensor, S: torch.Tensor | None, eps: float, prec: str = "b
     if max_candidates is None:
         max_candidates = max(1 << 20, 4 * (nR + nS))
     cap = capacity if capacity is not None else max(1 << 16, nR + nS)
+    if out is not None and capacity is None:
+        cap = out[0].numel()
     for _ in range(8):
         need = c.L.dl_join_eps_workspace(nR, nS, d, p, int(self_join), max_candidates)
         buf = ws.get(need)
