@@ -35,6 +35,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for the CPU baseline")
     ap.add_argument("--no-fp32-compare", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-store", type=int, default=8000000, help="rows of the serving store")
+    ap.add_argument("--serve-seconds", type=float, default=6.0, help="open-loop seconds per offered rate")
     return ap.parse_args()
 
 
@@ -66,6 +69,84 @@ def cpu_baseline(H, eps, n, target_s):
     return {"value": pairs / dt / 1e9, "unit": "G distance-pairs/s", "cores": threads, "kind": "oracle",
             "sample": "eps self-join of %d seeded rows x all later rows (%d pairs, %.1f s); featurise %.2f us/patch "
                       "(not in value)" % (m, pairs, dt, t_feat * 1e6)}
+
+
+def serving(args):
+    """Resident store of 8,000,000 x 128 unit-norm rows (bf16 operands +
+    float32 norms), requests of log-uniform 1..50,000 rows, half eps-join and
+    half top-10, Poisson arrivals.  Capacity C is measured closed-loop
+    (everything submitted at once); then the offered rate is 0.5 C and 0.8 C
+    for a fixed time each; latency is submit -> result ready."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    from paper_1812_07607_amd import ops, synth
+    t0 = time.perf_counter()
+    cfg = synth.config5(args.serve_store / 8000000.0)
+    S = torch.from_numpy(cfg["S"]).cuda()
+    del cfg["S"]
+    store = ops.Store(S, "bf16")
+    pool = torch.from_numpy(synth.queries_for_store(60000, 128, 1000, seed=505, stream=1)).cuda()
+    probe = pool[:256]
+    tk = store.join_topk(probe, 10)
+    eps = float(torch.median(tk.dist[:, 9]).item())
+    t_setup = time.perf_counter() - t0
+    srv = ops.Server(store, arena_bytes=48 << 30, n_streams=3, max_batch_requests=64, max_batch_rows=1 << 17)
+    arrivals_rng = np.random.default_rng(505)
+
+    def one_run(n_req, rate, seed):
+        _, rows, is_topk = synth.request_stream(n_req, max(rate, 1e-6), seed=seed)
+        offs = arrivals_rng.integers(0, pool.shape[0] - rows.max(), size=n_req)
+        ts = synth.request_stream(n_req, max(rate, 1e-6), seed=seed)[0]
+        tickets = []
+        done = []
+        srv.reset_stats()
+
+        def waiter():
+            i = 0
+            while i < n_req:
+                while i >= len(tickets):
+                    time.sleep(0.0005)
+                done.append(srv.wait(tickets[i], fetch=False))
+                i += 1
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        start = time.perf_counter()
+        for t in range(n_req):
+            if rate > 0:
+                delay = ts[t] - (time.perf_counter() - start)
+                if delay > 0:
+                    time.sleep(delay)
+            q = pool[offs[t]:offs[t] + rows[t]]
+            tickets.append(srv.submit(q, "topk" if is_topk[t] else "eps", eps=eps, k=10, sync=False))
+        th.join()
+        st = srv.stats()
+        bad = sum(1 for r in done if r["status"] != 0)
+        return st, bad, float(rows.sum())
+
+    torch.cuda.synchronize()
+    # closed loop: all requests at once
+    st, bad, rows_c = one_run(64, 0.0, 5051)
+    cap_rps = st["completed"] / max(st["span_ms"], 1e-9) * 1e3
+    out = {"workload": "resident store %d x 128 bf16; requests log-uniform 1..50,000 rows, 50%% eps (eps=%.4g, "
+                       "median 10th-neighbour distance) / 50%% top-10" % (args.serve_store, eps),
+           "setup_s": t_setup, "capacity_rps": cap_rps,
+           "capacity": {"requests": st["completed"], "gpairs_per_s": st["pairs_done"] / st["span_ms"] * 1e-6,
+                        "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_batch": st["mean_batch_requests"],
+                        "errors": bad}}
+    for frac in (0.5, 0.8):
+        rate = frac * cap_rps
+        n_req = max(8, int(rate * args.serve_seconds))
+        st, bad, rows_o = one_run(n_req, rate, 5052 + int(frac * 10))
+        out["offered_%.1fC" % frac] = {"rate_rps": rate, "requests": st["completed"],
+                                       "gpairs_per_s": st["pairs_done"] / max(st["span_ms"], 1e-9) * 1e-6,
+                                       "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "max_ms": st["max_ms"],
+                                       "mean_batch": st["mean_batch_requests"], "errors": bad}
+    srv.close()
+    return out
 
 
 def main():
@@ -153,6 +234,11 @@ def main():
         t32 = (time.perf_counter() - t0) / k32
         res["fp32_join"] = {"value": pairs / t32 / 1e9, "ms_per_step": t32 * 1e3, "candidates": r32.candidates,
                             "same_pairs": bool(r32.count == r.count)}
+    if not args.no_serving:
+        try:
+            res["serving"] = serving(args)
+        except Exception as e:  # reported, not fatal to the main measurement
+            res["serving"] = {"error": repr(e)}
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline({"patches": cfg["patches"], "hist": hist.cpu().numpy()}, eps, n,
                                            args.cpu_seconds)

@@ -191,6 +191,114 @@ dl_status dl_join_topk(dl_ctx* ctx, dl_mat R, dl_mat S, int self_join,
                        uint32_t* out_j, float* out_dist, dl_topk_info* info,
                        void* stream);
 
+
+/* ---------------------------------------------------------------- store */
+
+/* A resident relation (the on-the-fly index join of section "Query
+ * Processing" keeps one relation resident and probes it with the other; the
+ * materialised intermediate result of section "Visual ETL").  The store
+ * borrows `base` (float32 rows, device): the caller keeps it alive and
+ * unchanged until dl_store_destroy.  The operand copy and statistics are
+ * built once into `mem` (device, caller-owned, dl_store_bytes() bytes). */
+typedef struct dl_store dl_store;
+
+size_t dl_store_bytes(int64_t n, int32_t d, dl_prec prec);
+/* Builds the store; synchronises `stream`.  DL_ERR_INVALID for bad shapes or
+ * non-finite rows, DL_ERR_WORKSPACE if mem is too small. */
+dl_status dl_store_create(dl_ctx* ctx, dl_mat base, dl_prec prec, void* mem, size_t bytes, dl_store** out,
+                          void* stream);
+void dl_store_destroy(dl_store* store);
+int64_t dl_store_rows(const dl_store* store);
+
+/* The eps-join and top-k join of R against a store (S = the store's rows,
+ * operand format = the store's).  Same semantics, outputs and errors as
+ * dl_join_eps / dl_join_topk with self_join = 0. */
+size_t dl_join_eps_store_workspace(int64_t nR, const dl_store* store, int64_t max_candidates);
+dl_status dl_join_eps_store(dl_ctx* ctx, dl_mat R, const dl_store* store, double eps, void* ws,
+                            size_t ws_bytes, dl_pairs* out, void* stream);
+size_t dl_join_topk_store_workspace(int64_t nR, const dl_store* store, int32_t k, int32_t band_cap);
+dl_status dl_join_topk_store(dl_ctx* ctx, dl_mat R, const dl_store* store, int32_t k, int32_t band_cap,
+                             void* ws, size_t ws_bytes, uint32_t* out_j, float* out_dist,
+                             dl_topk_info* info, void* stream);
+
+/* ---------------------------------------------------------------- server */
+
+/* A persistent request loop over one store.  Requests (query rows + eps or
+ * k) are queued; worker threads (one HIP stream each) admit the request at
+ * the head of the queue and every later queued request of the same mode (and
+ * k) that fits the batch limits and the free arena memory, run them as one
+ * join against the store, and publish per-request results.  Requests that
+ * arrive while batches run are admitted as streams and memory free up.  A
+ * request's result does not depend on the batch it ran in. */
+typedef struct dl_server dl_server;
+
+#define DL_MODE_EPS 0
+#define DL_MODE_TOPK 1
+
+typedef struct dl_server_config {
+  int32_t n_streams;          /* batches on the device at once (default 2, max 8) */
+  int32_t max_batch_requests; /* requests per batch (default 64)                 */
+  int64_t max_batch_rows;     /* query rows per batch (default 65536)            */
+  int64_t pairs_per_row;      /* eps output room per query row (default 64)     */
+  int32_t band_cap;           /* top-k band entries per row and split (0 = default) */
+} dl_server_config;
+
+typedef struct dl_request {
+  dl_mat query;   /* device rows, d = the store's d; borrowed until the request completes */
+  int32_t mode;   /* DL_MODE_EPS or DL_MODE_TOPK */
+  double eps;     /* eps-join radius (mode DL_MODE_EPS) */
+  int32_t k;      /* neighbours per row, 1..256 (mode DL_MODE_TOPK) */
+} dl_request;
+
+/* Result of a completed request.  Arrays are device memory inside the
+ * server's arena, valid until dl_server_release.
+ *   eps:  count pairs (i = row of the request's query, j = store row, dist),
+ *         sorted by (i, j).
+ *   top-k: j and dist are rows x k, as dl_join_topk_store. */
+typedef struct dl_result {
+  dl_status status;
+  int32_t mode;
+  int64_t rows;
+  int32_t k;
+  const uint32_t* i;
+  const uint32_t* j;
+  const float* dist;
+  int64_t count;
+  double queued_ms;   /* submit -> batch start */
+  double latency_ms;  /* submit -> result ready */
+  int64_t batch_id;
+  int32_t batch_requests;
+} dl_result;
+
+typedef struct dl_server_info {
+  int64_t submitted, completed, rejected, cancelled, batches, queued;
+  double mean_batch_requests;
+  double pairs_done;  /* sum over completed requests of rows x store rows */
+  double span_ms;     /* first submit -> last completion */
+  double p50_ms, p99_ms, max_ms;
+  size_t arena_in_use, arena_peak;
+} dl_server_info;
+
+/* Starts the workers on `device`.  `arena` (device, caller-owned) holds every
+ * in-flight batch's packed queries, workspace and results; a batch is
+ * admitted only if its footprint fits the arena's free space, and a request
+ * that cannot fit an empty arena completes with DL_ERR_OOM. */
+dl_status dl_server_create(int device, const dl_store* store, const dl_server_config* cfg, void* arena,
+                           size_t arena_bytes, dl_server** out);
+/* Queues a request; returns at once with a ticket. */
+dl_status dl_server_submit(dl_server* srv, const dl_request* req, uint64_t* ticket);
+/* Waits up to timeout_ms (< 0: forever) for a request; DL_ERR_BUSY on
+ * timeout.  out->status is the request's own status. */
+dl_status dl_server_wait(dl_server* srv, uint64_t ticket, int32_t timeout_ms, dl_result* out);
+/* Frees a completed request's result memory and its ticket. */
+dl_status dl_server_release(dl_server* srv, uint64_t ticket);
+/* Cancels a request still in the queue (DL_ERR_BUSY once it has started). */
+dl_status dl_server_cancel(dl_server* srv, uint64_t ticket);
+dl_status dl_server_stats(dl_server* srv, dl_server_info* out);
+dl_status dl_server_reset_stats(dl_server* srv);
+/* Cancels queued requests, waits for running batches, stops the workers. */
+void dl_server_destroy(dl_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

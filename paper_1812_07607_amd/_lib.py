@@ -33,6 +33,32 @@ class dl_topk_info(ctypes.Structure):
     _fields_ = [("band_entries", ctypes.c_int64), ("ties", ctypes.c_int64)]
 
 
+class dl_server_config(ctypes.Structure):
+    _fields_ = [("n_streams", ctypes.c_int32), ("max_batch_requests", ctypes.c_int32),
+                ("max_batch_rows", ctypes.c_int64), ("pairs_per_row", ctypes.c_int64), ("band_cap", ctypes.c_int32)]
+
+
+class dl_request(ctypes.Structure):
+    _fields_ = [("query", dl_mat), ("mode", ctypes.c_int32), ("eps", ctypes.c_double), ("k", ctypes.c_int32)]
+
+
+class dl_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("mode", ctypes.c_int32), ("rows", ctypes.c_int64), ("k", ctypes.c_int32),
+                ("i", ctypes.c_void_p), ("j", ctypes.c_void_p), ("dist", ctypes.c_void_p), ("count", ctypes.c_int64),
+                ("queued_ms", ctypes.c_double), ("latency_ms", ctypes.c_double), ("batch_id", ctypes.c_int64),
+                ("batch_requests", ctypes.c_int32)]
+
+
+class dl_server_info(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("rejected", ctypes.c_int64),
+                ("cancelled", ctypes.c_int64), ("batches", ctypes.c_int64), ("queued", ctypes.c_int64),
+                ("mean_batch_requests", ctypes.c_double), ("pairs_done", ctypes.c_double),
+                ("span_ms", ctypes.c_double), ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double), ("arena_in_use", ctypes.c_size_t), ("arena_peak", ctypes.c_size_t)]
+
+
+DL_MODE_EPS, DL_MODE_TOPK = 0, 1
+
 # name -> (restype, argtypes); every symbol include/dlmi.h declares
 P, i32, i64, f64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
 SIGNATURES = {
@@ -51,6 +77,22 @@ SIGNATURES = {
     "dl_join_topk_workspace": (sz, [i64, i64, i32, ctypes.c_int, ctypes.c_int, i32, i32]),
     "dl_join_topk": (ctypes.c_int, [P, dl_mat, dl_mat, ctypes.c_int, i32, ctypes.c_int, ctypes.c_int, i32, P, sz,
                                     P, P, ctypes.POINTER(dl_topk_info), P]),
+    "dl_store_bytes": (sz, [i64, i32, ctypes.c_int]),
+    "dl_store_create": (ctypes.c_int, [P, dl_mat, ctypes.c_int, P, sz, ctypes.POINTER(P), P]),
+    "dl_store_destroy": (None, [P]),
+    "dl_store_rows": (i64, [P]),
+    "dl_join_eps_store_workspace": (sz, [i64, P, i64]),
+    "dl_join_eps_store": (ctypes.c_int, [P, dl_mat, P, f64, P, sz, ctypes.POINTER(dl_pairs), P]),
+    "dl_join_topk_store_workspace": (sz, [i64, P, i32, i32]),
+    "dl_join_topk_store": (ctypes.c_int, [P, dl_mat, P, i32, i32, P, sz, P, P, ctypes.POINTER(dl_topk_info), P]),
+    "dl_server_create": (ctypes.c_int, [ctypes.c_int, P, ctypes.POINTER(dl_server_config), P, sz, ctypes.POINTER(P)]),
+    "dl_server_submit": (ctypes.c_int, [P, ctypes.POINTER(dl_request), ctypes.POINTER(ctypes.c_uint64)]),
+    "dl_server_wait": (ctypes.c_int, [P, ctypes.c_uint64, i32, ctypes.POINTER(dl_result)]),
+    "dl_server_release": (ctypes.c_int, [P, ctypes.c_uint64]),
+    "dl_server_cancel": (ctypes.c_int, [P, ctypes.c_uint64]),
+    "dl_server_stats": (ctypes.c_int, [P, ctypes.POINTER(dl_server_info)]),
+    "dl_server_reset_stats": (ctypes.c_int, [P]),
+    "dl_server_destroy": (None, [P]),
 }
 
 _lib = None

@@ -6,14 +6,15 @@
 #include <cstring>
 #include <new>
 
-#include "dl_internal.hpp"
+#include "core.hpp"
 
 namespace dl {
 // featurize.hip
 hipError_t launch_hist_rgb8(const uint8_t*, int64_t, int32_t, int32_t, int32_t, float*, hipStream_t, int);
 // prep.hip
 hipError_t launch_prep(const float*, int64_t, int32_t, int64_t, dl_prec, const Prep&, RelStats*, hipStream_t, int);
-hipError_t launch_threshold(const Prep&, int64_t, const RelStats*, int, double, float*, float*, hipStream_t);
+hipError_t launch_threshold(const Prep&, int64_t, const RelStats*, int, double, const double*, float*, float*,
+                            hipStream_t);
 }  // namespace dl
 
 #include "join_params.hpp"
@@ -52,19 +53,6 @@ struct Counters {
 static_assert(sizeof(Counters) == 96, "counter block size");
 
 // ------------------------------------------------------------ workspace
-struct Bump {
-  uint8_t* base;
-  size_t off = 0;
-  explicit Bump(void* b) : base(static_cast<uint8_t*>(b)) {}
-  template <class T>
-  T* take(int64_t count) {
-    off = (size_t)round_up((int64_t)off, 256);
-    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
-    off += (size_t)count * sizeof(T);
-    return p;
-  }
-};
-
 static Prep carve_prep(Bump& b, int64_t n, int d, dl_prec prec) {
   Prep P;
   P.npad = round_up(n < 1 ? 1 : n, kTile);
@@ -95,14 +83,17 @@ struct EpsLayout {
   size_t bytes;
 };
 
-static EpsLayout layout_eps(void* ws, int64_t nR, int64_t nS, int d, dl_prec prec, bool self, int64_t cap) {
+// s_ext: the S side (operand copy and statistics) comes from a store and is
+// not carved from the workspace.
+static EpsLayout layout_eps(void* ws, int64_t nR, int64_t nS, int d, dl_prec prec, bool self, int64_t cap,
+                            bool s_ext = false) {
   EpsLayout L;
   Bump b(ws);
   L.cnt = b.take<Counters>(1);
   L.sr = b.take<RelStats>(1);
-  L.ss = self ? L.sr : b.take<RelStats>(1);
+  L.ss = (self || s_ext) ? L.sr : b.take<RelStats>(1);
   L.pr = carve_prep(b, nR, d, prec);
-  L.ps = self ? L.pr : carve_prep(b, nS, d, prec);
+  L.ps = (self || s_ext) ? L.pr : carve_prep(b, nS, d, prec);
   L.thr = b.take<float>(L.pr.npad);
   const int64_t c = cap < 1 ? 1 : cap;
   L.cand = b.take<uint2>(c);
@@ -127,27 +118,43 @@ struct TopkLayout {
   size_t bytes;
 };
 
+// S splits for the top-k pass: enough workgroups for every CU, and a count
+// that fills the last round of workgroups well.
 static int topk_splits(int64_t nR, int64_t nS, int cu_count, int64_t* tps_out) {
   const int64_t nTR = (nR + kTile - 1) / kTile, nTS = (nS + kTile - 1) / kTile;
-  int64_t P = (2 * (int64_t)cu_count + nTR - 1) / (nTR < 1 ? 1 : nTR);
-  if (P < 1) P = 1;
-  if (P > nTS) P = nTS < 1 ? 1 : nTS;
-  int64_t tps = (nTS + P - 1) / P;
-  if (tps < 1) tps = 1;
-  P = (nTS + tps - 1) / tps;
-  if (P < 1) P = 1;
-  if (tps_out) *tps_out = tps;
-  return (int)P;
+  const int64_t rows = nTR < 1 ? 1 : nTR;
+  int64_t pmin = (int64_t)(cu_count + rows - 1) / rows;
+  if (pmin < 1) pmin = 1;
+  int64_t best = pmin, best_tps = 1;
+  double best_cost = 1e300;
+  for (int64_t P0 = pmin; P0 <= 4 * pmin; ++P0) {
+    int64_t P = P0 > nTS ? (nTS < 1 ? 1 : nTS) : P0;
+    int64_t tps = (nTS + P - 1) / P;
+    if (tps < 1) tps = 1;
+    P = (nTS + tps - 1) / tps;
+    if (P < 1) P = 1;
+    // time ~ rounds of workgroups x tiles per workgroup
+    const int64_t items = rows * P;
+    const double cost = (double)((items + cu_count - 1) / cu_count) * (double)tps;
+    if (cost < best_cost - 1e-9) {
+      best_cost = cost;
+      best = P;
+      best_tps = tps;
+    }
+  }
+  if (tps_out) *tps_out = best_tps;
+  return (int)best;
 }
 
-static TopkLayout layout_topk(void* ws, int64_t nR, int64_t nS, int d, dl_prec prec, bool self, int P, int cap) {
+static TopkLayout layout_topk(void* ws, int64_t nR, int64_t nS, int d, dl_prec prec, bool self, int P, int cap,
+                              bool s_ext = false) {
   TopkLayout L;
   Bump b(ws);
   L.cnt = b.take<Counters>(1);
   L.sr = b.take<RelStats>(1);
-  L.ss = self ? L.sr : b.take<RelStats>(1);
+  L.ss = (self || s_ext) ? L.sr : b.take<RelStats>(1);
   L.pr = carve_prep(b, nR, d, prec);
-  L.ps = self ? L.pr : carve_prep(b, nS, d, prec);
+  L.ps = (self || s_ext) ? L.pr : carve_prep(b, nS, d, prec);
   L.marg = b.take<float>(L.pr.npad);
   L.band = b.take<uint2>((nR < 1 ? 1 : nR) * (int64_t)P * cap);
   L.bcount = b.take<int>((nR < 1 ? 1 : nR) * (int64_t)P);
@@ -163,6 +170,9 @@ static int bits_for(int64_t n) {  // bits to hold values 0..n-1 (at least 1)
 
 // Largest double T with sqrt(T) <= eps (sqrt is monotone and correctly
 // rounded, so d2 <= T exactly when sqrt(d2) <= eps).
+static double threshold_from_eps(double eps);
+double eps_threshold(double eps) { return threshold_from_eps(eps); }
+
 static double threshold_from_eps(double eps) {
   if (std::isinf(eps)) return INFINITY;
   double x = eps * eps;
@@ -362,50 +372,58 @@ dl_status dl_pair_d2(dl_ctx* c, dl_mat R, dl_mat S, const uint32_t* pi, const ui
   return DL_OK;
 }
 
-size_t dl_join_eps_workspace(int64_t nR, int64_t nS, int32_t d, dl_prec prec, int self_join, int64_t max_cand) {
-  if (nR < 0 || d < 1 || d > kMaxDim || !prec_ok(prec) || max_cand < 0) return 0;
-  if (self_join) nS = nR;
-  return layout_eps(nullptr, nR, nS, d, prec, self_join != 0, max_cand).bytes;
+}  // extern "C"
+
+// ------------------------------------------------------------ join cores
+// Shared by the plain calls, the store calls and the server.
+namespace dl {
+
+static int band_cap_of(int32_t band_cap, int k) {
+  if (band_cap <= 0) band_cap = 1024;
+  band_cap = (int32_t)round_up(band_cap < 512 ? 512 : band_cap, 64);
+  if (band_cap < 2 * k + kTile) band_cap = (int32_t)round_up(2 * k + kTile, 64);
+  return band_cap;
 }
 
-dl_status dl_join_eps(dl_ctx* c, dl_mat R, dl_mat S, int self_join, double eps, dl_prec prec, void* ws,
-                      size_t ws_bytes, dl_pairs* out, void* stream) {
-  if (!c) return DL_ERR_INVALID;
-  c->err.clear();
-  c->required_ws = 0;
-  if (self_join) S = R;
-  dl_status s;
-  if ((s = check_mat(c, R, "R")) != DL_OK || (s = check_mat(c, S, "S")) != DL_OK) return s;
-  if (R.d != S.d) return fail(c, DL_ERR_INVALID, "R.d %d != S.d %d", R.d, S.d);
-  if (std::isnan(eps) || eps < 0) return fail(c, DL_ERR_INVALID, "eps must be >= 0 (got %g)", eps);
-  if (!prec_ok(prec)) return fail(c, DL_ERR_INVALID, "unknown precision %d", (int)prec);
-  if (!out || out->capacity < 0) return fail(c, DL_ERR_INVALID, "bad output struct");
-  if (out->capacity > 0 && (!out->i || !out->j || !out->dist)) return fail(c, DL_ERR_INVALID, "null output array");
+size_t eps_workspace(int64_t nR, int64_t nS, int d, dl_prec prec, bool self, bool s_ext, int64_t cap) {
+  return layout_eps(nullptr, nR, nS, d, prec, self, cap, s_ext).bytes;
+}
+
+size_t topk_workspace(int64_t nR, int64_t nS, int d, dl_prec prec, bool self, bool s_ext, int k, int band_cap,
+                      int cu) {
+  const int P = topk_splits(nR, nS, cu, nullptr);
+  return layout_topk(nullptr, nR, nS, d, prec, self, P, band_cap_of(band_cap, k), s_ext).bytes;
+}
+
+dl_status eps_core(dl_ctx* c, const EpsJob& J, void* ws, size_t ws_bytes, dl_pairs* out, hipStream_t st) {
+  const dl_mat &R = J.R, &S = J.S;
+  const bool self = J.self, sx = J.ps_ext != nullptr;
+  const dl_prec prec = J.prec;
   out->count = out->candidates = out->ties = 0;
-  const bool self = self_join != 0;
   // candidate capacity from the workspace size
-  const size_t fixed = layout_eps(nullptr, R.n, S.n, R.d, prec, self, 1).bytes;
+  const size_t fixed = layout_eps(nullptr, R.n, S.n, R.d, prec, self, 1, sx).bytes;
   if (!ws || ws_bytes < fixed) {
-    c->required_ws = layout_eps(nullptr, R.n, S.n, R.d, prec, self, 1 << 20).bytes;
+    c->required_ws = layout_eps(nullptr, R.n, S.n, R.d, prec, self, 1 << 20, sx).bytes;
     return fail(c, DL_ERR_WORKSPACE, "workspace of %zu bytes below the minimum %zu", ws_bytes, fixed);
   }
-  const size_t per = layout_eps(nullptr, R.n, S.n, R.d, prec, self, 1 << 16).bytes - fixed;
+  const size_t per = layout_eps(nullptr, R.n, S.n, R.d, prec, self, 1 << 16, sx).bytes - fixed;
   int64_t cap = (int64_t)((double)(ws_bytes - fixed) / ((double)per / (1 << 16))) - 1024;
-  while (cap > 1 && layout_eps(nullptr, R.n, S.n, R.d, prec, self, cap).bytes > ws_bytes) cap = cap * 63 / 64;
+  while (cap > 1 && layout_eps(nullptr, R.n, S.n, R.d, prec, self, cap, sx).bytes > ws_bytes) cap = cap * 63 / 64;
   if (cap < 1) cap = 1;
   if (R.n == 0 || S.n == 0) return DL_OK;
 
-  EpsLayout L = layout_eps(ws, R.n, S.n, R.d, prec, self, cap);
-  DL_HIP(c, hipSetDevice(c->device));
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  const double T = threshold_from_eps(eps);
+  EpsLayout L = layout_eps(ws, R.n, S.n, R.d, prec, self, cap, sx);
+  if (sx) {
+    L.ps = *J.ps_ext;
+    L.ss = J.ss_ext;
+  }
   hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(L.cnt),
                      (int64_t)(sizeof(Counters) / 4));
   {
     StageTimer t(c, 1, st);
     DL_HIP(c, launch_prep(R.data, R.n, R.d, R.ld, prec, L.pr, L.sr, st, c->cu_count));
-    if (!self) DL_HIP(c, launch_prep(S.data, S.n, S.d, S.ld, prec, L.ps, L.ss, st, c->cu_count));
-    DL_HIP(c, launch_threshold(L.pr, R.n, L.ss, R.d, T, L.thr, nullptr, st));
+    if (!self && !sx) DL_HIP(c, launch_prep(S.data, S.n, S.d, S.ld, prec, L.ps, L.ss, st, c->cu_count));
+    DL_HIP(c, launch_threshold(L.pr, R.n, L.ss, R.d, J.T, J.Trow, L.thr, nullptr, st));
   }
   {
     StageTimer t(c, 2, st);
@@ -436,7 +454,8 @@ dl_status dl_join_eps(dl_ctx* c, dl_mat R, dl_mat S, int self_join, double eps, 
     q.cand = L.cand; q.ccount = &L.cnt->cand; q.ccap = cap;
     q.xnR = L.pr.xnorm; q.mlR = L.pr.mlsb;
     q.xnS = L.ps.xnorm; q.mlS = L.ps.mlsb;
-    q.T = T;
+    q.T = J.T;
+    q.Trow = J.Trow;
     q.bj = bj;
     q.keys = L.k0; q.dist = L.v0; q.ocount = &L.cnt->out; q.nties = &L.cnt->ties;
     DL_HIP(c, launch_recheck_eps(q, st, c->cu_count));
@@ -447,7 +466,8 @@ dl_status dl_join_eps(dl_ctx* c, dl_mat R, dl_mat S, int self_join, double eps, 
   out->candidates = (int64_t)hc.cand;
   out->ties = (int64_t)hc.ties;
   if ((int64_t)hc.cand > cap) {
-    c->required_ws = layout_eps(nullptr, R.n, S.n, R.d, prec, self, (int64_t)hc.cand + (int64_t)hc.cand / 8 + 1024).bytes;
+    c->required_ws =
+        layout_eps(nullptr, R.n, S.n, R.d, prec, self, (int64_t)hc.cand + (int64_t)hc.cand / 8 + 1024, sx).bytes;
     return fail(c, DL_ERR_WORKSPACE, "%llu candidates exceed the workspace capacity %lld", hc.cand, (long long)cap);
   }
   const int64_t m = (int64_t)hc.out;
@@ -467,50 +487,28 @@ dl_status dl_join_eps(dl_ctx* c, dl_mat R, dl_mat S, int self_join, double eps, 
   return DL_OK;
 }
 
-size_t dl_join_topk_workspace(int64_t nR, int64_t nS, int32_t d, dl_prec prec, int self_join, int32_t k,
-                              int32_t band_cap) {
-  if (nR < 0 || nS < 0 || d < 1 || d > kMaxDim || !prec_ok(prec) || k < 1) return 0;
-  if (self_join) nS = nR;
-  if (band_cap <= 0) band_cap = 1024;
-  band_cap = (int32_t)round_up(band_cap < 512 ? 512 : band_cap, 64);
-  int cu = 256;
-  int dev;
-  hipDeviceProp_t prop;
-  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) cu = prop.multiProcessorCount;
-  const int P = topk_splits(nR, nS, cu, nullptr);
-  return layout_topk(nullptr, nR, nS, d, prec, self_join != 0, P, band_cap).bytes;
-}
-
-dl_status dl_join_topk(dl_ctx* c, dl_mat R, dl_mat S, int self_join, int32_t k, int exclude_self, dl_prec prec,
-                       int32_t band_cap, void* ws, size_t ws_bytes, uint32_t* out_j, float* out_dist,
-                       dl_topk_info* info, void* stream) {
-  if (!c) return DL_ERR_INVALID;
-  c->err.clear();
-  c->required_ws = 0;
-  if (self_join) S = R;
-  dl_status s;
-  if ((s = check_mat(c, R, "R")) != DL_OK || (s = check_mat(c, S, "S")) != DL_OK) return s;
-  if (R.d != S.d) return fail(c, DL_ERR_INVALID, "R.d %d != S.d %d", R.d, S.d);
-  if (k < 1 || k > 256) return fail(c, DL_ERR_INVALID, "k = %d outside [1, 256]", k);
-  if (!prec_ok(prec)) return fail(c, DL_ERR_INVALID, "unknown precision %d", (int)prec);
-  if (R.n > 0 && (!out_j || !out_dist)) return fail(c, DL_ERR_INVALID, "null output array");
-  if (band_cap <= 0) band_cap = 1024;
-  band_cap = (int32_t)round_up(band_cap < 512 ? 512 : band_cap, 64);
-  if (band_cap < 2 * k + kTile) band_cap = (int32_t)round_up(2 * k + kTile, 64);
+dl_status topk_core(dl_ctx* c, const TopkJob& J, void* ws, size_t ws_bytes, uint32_t* out_j, float* out_dist,
+                    dl_topk_info* info, hipStream_t st) {
+  const dl_mat &R = J.R, &S = J.S;
+  const bool self = J.self, sx = J.ps_ext != nullptr;
+  const bool excl = self && J.excl;
+  const dl_prec prec = J.prec;
+  const int k = J.k;
+  const int band_cap = band_cap_of(J.band_cap, k);
   if (info) info->band_entries = info->ties = 0;
-  const bool self = self_join != 0;
-  const bool excl = self && exclude_self;
   int64_t tps = 1;
   const int P = topk_splits(R.n, S.n, c->cu_count, &tps);
-  const size_t need = layout_topk(nullptr, R.n, S.n, R.d, prec, self, P, band_cap).bytes;
+  const size_t need = layout_topk(nullptr, R.n, S.n, R.d, prec, self, P, band_cap, sx).bytes;
   if (!ws || ws_bytes < need) {
     c->required_ws = need;
     return fail(c, DL_ERR_WORKSPACE, "workspace of %zu bytes below the %zu needed", ws_bytes, need);
   }
   if (R.n == 0) return DL_OK;
-  DL_HIP(c, hipSetDevice(c->device));
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  TopkLayout L = layout_topk(ws, R.n, S.n, R.d, prec, self, P, band_cap);
+  TopkLayout L = layout_topk(ws, R.n, S.n, R.d, prec, self, P, band_cap, sx);
+  if (sx) {
+    L.ps = *J.ps_ext;
+    L.ss = J.ss_ext;
+  }
   hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(L.cnt),
                      (int64_t)(sizeof(Counters) / 4));
   if (S.n == 0) {
@@ -521,8 +519,8 @@ dl_status dl_join_topk(dl_ctx* c, dl_mat R, dl_mat S, int self_join, int32_t k, 
   {
     StageTimer t(c, 1, st);
     DL_HIP(c, launch_prep(R.data, R.n, R.d, R.ld, prec, L.pr, L.sr, st, c->cu_count));
-    if (!self) DL_HIP(c, launch_prep(S.data, S.n, S.d, S.ld, prec, L.ps, L.ss, st, c->cu_count));
-    DL_HIP(c, launch_threshold(L.pr, R.n, L.ss, R.d, 0.0, nullptr, L.marg, st));
+    if (!self && !sx) DL_HIP(c, launch_prep(S.data, S.n, S.d, S.ld, prec, L.ps, L.ss, st, c->cu_count));
+    DL_HIP(c, launch_threshold(L.pr, R.n, L.ss, R.d, 0.0, nullptr, nullptr, L.marg, st));
   }
   if (S.n > 0) {
     StageTimer t(c, 2, st);
@@ -563,17 +561,184 @@ dl_status dl_join_topk(dl_ctx* c, dl_mat R, dl_mat S, int self_join, int32_t k, 
   }
   DL_HIP(c, readback(c, L.cnt, L.sr, L.ss, st));
   const Counters hc = *reinterpret_cast<const Counters*>(c->pinned);
-  if (dl_status bad = check_inputs(c)) return bad;
   if (info) {
     info->band_entries = (int64_t)hc.band;
     info->ties = (int64_t)hc.ties;
   }
+  if (dl_status bad = check_inputs(c)) return bad;
   if (hc.overflow || hc.too_many) {
-    c->required_ws = layout_topk(nullptr, R.n, S.n, R.d, prec, self, P, band_cap * 2).bytes;
+    c->required_ws = layout_topk(nullptr, R.n, S.n, R.d, prec, self, P, band_cap * 2, sx).bytes;
     return fail(c, DL_ERR_WORKSPACE, "top-k band exceeded its capacity (%s); retry with band_cap %d",
                 hc.overflow ? "band buffer" : "near-tie contenders", band_cap * 2);
   }
   return DL_OK;
+}
+
+size_t store_bytes(int64_t n, int d, dl_prec prec) {
+  Bump b(nullptr);
+  b.take<RelStats>(1);
+  carve_prep(b, n, d, prec);
+  return round_up((int64_t)b.off, 256);
+}
+
+}  // namespace dl
+
+// ------------------------------------------------------------ ABI: joins
+extern "C" {
+
+size_t dl_join_eps_workspace(int64_t nR, int64_t nS, int32_t d, dl_prec prec, int self_join, int64_t max_cand) {
+  if (nR < 0 || d < 1 || d > kMaxDim || !prec_ok(prec) || max_cand < 0) return 0;
+  if (self_join) nS = nR;
+  return eps_workspace(nR, nS, d, prec, self_join != 0, false, max_cand);
+}
+
+dl_status dl_join_eps(dl_ctx* c, dl_mat R, dl_mat S, int self_join, double eps, dl_prec prec, void* ws,
+                      size_t ws_bytes, dl_pairs* out, void* stream) {
+  if (!c) return DL_ERR_INVALID;
+  c->err.clear();
+  c->required_ws = 0;
+  if (self_join) S = R;
+  dl_status s;
+  if ((s = check_mat(c, R, "R")) != DL_OK || (s = check_mat(c, S, "S")) != DL_OK) return s;
+  if (R.d != S.d) return fail(c, DL_ERR_INVALID, "R.d %d != S.d %d", R.d, S.d);
+  if (std::isnan(eps) || eps < 0) return fail(c, DL_ERR_INVALID, "eps must be >= 0 (got %g)", eps);
+  if (!prec_ok(prec)) return fail(c, DL_ERR_INVALID, "unknown precision %d", (int)prec);
+  if (!out || out->capacity < 0) return fail(c, DL_ERR_INVALID, "bad output struct");
+  if (out->capacity > 0 && (!out->i || !out->j || !out->dist)) return fail(c, DL_ERR_INVALID, "null output array");
+  DL_HIP(c, hipSetDevice(c->device));
+  EpsJob J{R, S, self_join != 0, prec, nullptr, nullptr, threshold_from_eps(eps), nullptr};
+  return eps_core(c, J, ws, ws_bytes, out, static_cast<hipStream_t>(stream));
+}
+
+size_t dl_join_topk_workspace(int64_t nR, int64_t nS, int32_t d, dl_prec prec, int self_join, int32_t k,
+                              int32_t band_cap) {
+  if (nR < 0 || nS < 0 || d < 1 || d > kMaxDim || !prec_ok(prec) || k < 1) return 0;
+  if (self_join) nS = nR;
+  int cu = 256, dev;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) cu = prop.multiProcessorCount;
+  return topk_workspace(nR, nS, d, prec, self_join != 0, false, k, band_cap, cu);
+}
+
+dl_status dl_join_topk(dl_ctx* c, dl_mat R, dl_mat S, int self_join, int32_t k, int exclude_self, dl_prec prec,
+                       int32_t band_cap, void* ws, size_t ws_bytes, uint32_t* out_j, float* out_dist,
+                       dl_topk_info* info, void* stream) {
+  if (!c) return DL_ERR_INVALID;
+  c->err.clear();
+  c->required_ws = 0;
+  if (self_join) S = R;
+  dl_status s;
+  if ((s = check_mat(c, R, "R")) != DL_OK || (s = check_mat(c, S, "S")) != DL_OK) return s;
+  if (R.d != S.d) return fail(c, DL_ERR_INVALID, "R.d %d != S.d %d", R.d, S.d);
+  if (k < 1 || k > 256) return fail(c, DL_ERR_INVALID, "k = %d outside [1, 256]", k);
+  if (!prec_ok(prec)) return fail(c, DL_ERR_INVALID, "unknown precision %d", (int)prec);
+  if (R.n > 0 && (!out_j || !out_dist)) return fail(c, DL_ERR_INVALID, "null output array");
+  DL_HIP(c, hipSetDevice(c->device));
+  TopkJob J{R, S, self_join != 0, exclude_self != 0, prec, nullptr, nullptr, k, band_cap};
+  return topk_core(c, J, ws, ws_bytes, out_j, out_dist, info, static_cast<hipStream_t>(stream));
+}
+
+// ------------------------------------------------------------ ABI: store
+size_t dl_store_bytes(int64_t n, int32_t d, dl_prec prec) {
+  if (n < 0 || d < 1 || d > kMaxDim || !prec_ok(prec)) return 0;
+  return store_bytes(n, d, prec);
+}
+
+dl_status dl_store_create(dl_ctx* c, dl_mat base, dl_prec prec, void* mem, size_t bytes, dl_store** out,
+                          void* stream) {
+  if (!c) return DL_ERR_INVALID;
+  c->err.clear();
+  if (!out) return fail(c, DL_ERR_INVALID, "null output handle");
+  *out = nullptr;
+  dl_status s;
+  if ((s = check_mat(c, base, "base")) != DL_OK) return s;
+  if (!prec_ok(prec)) return fail(c, DL_ERR_INVALID, "unknown precision %d", (int)prec);
+  const size_t need = store_bytes(base.n, base.d, prec);
+  if (!mem || bytes < need) {
+    c->required_ws = need;
+    return fail(c, DL_ERR_WORKSPACE, "store memory of %zu bytes below the %zu needed", bytes, need);
+  }
+  DL_HIP(c, hipSetDevice(c->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  dl_store* S = new (std::nothrow) dl_store();
+  if (!S) return fail(c, DL_ERR_OOM, "host allocation failed");
+  Bump b(mem);
+  S->stats = b.take<RelStats>(1);
+  S->prep = carve_prep(b, base.n, base.d, prec);
+  S->base = base;
+  S->prec = prec;
+  S->device = c->device;
+  {
+    StageTimer t(c, 1, st);
+    hipError_t e = launch_prep(base.data, base.n, base.d, base.ld, prec, S->prep, S->stats, st, c->cu_count);
+    if (e != hipSuccess) {
+      delete S;
+      return fail(c, DL_ERR_DEVICE, "prep: %s", hipGetErrorString(e));
+    }
+  }
+  hipError_t e = hipMemcpyAsync(c->pinned + 12, S->stats, sizeof(RelStats), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->pinned + 20, S->stats, sizeof(RelStats), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    delete S;
+    return fail(c, DL_ERR_DEVICE, "store readback: %s", hipGetErrorString(e));
+  }
+  if (dl_status bad = check_inputs(c)) {
+    delete S;
+    return bad;
+  }
+  *out = S;
+  return DL_OK;
+}
+
+void dl_store_destroy(dl_store* s) { delete s; }
+
+int64_t dl_store_rows(const dl_store* s) { return s ? s->base.n : -1; }
+
+size_t dl_join_eps_store_workspace(int64_t nR, const dl_store* s, int64_t max_cand) {
+  if (!s || nR < 0 || max_cand < 0) return 0;
+  return eps_workspace(nR, s->base.n, s->base.d, s->prec, false, true, max_cand);
+}
+
+dl_status dl_join_eps_store(dl_ctx* c, dl_mat R, const dl_store* store, double eps, void* ws, size_t ws_bytes,
+                            dl_pairs* out, void* stream) {
+  if (!c) return DL_ERR_INVALID;
+  c->err.clear();
+  c->required_ws = 0;
+  if (!store) return fail(c, DL_ERR_INVALID, "null store");
+  dl_status s;
+  if ((s = check_mat(c, R, "R")) != DL_OK) return s;
+  if (R.d != store->base.d) return fail(c, DL_ERR_INVALID, "R.d %d != store d %d", R.d, store->base.d);
+  if (std::isnan(eps) || eps < 0) return fail(c, DL_ERR_INVALID, "eps must be >= 0 (got %g)", eps);
+  if (!out || out->capacity < 0) return fail(c, DL_ERR_INVALID, "bad output struct");
+  if (out->capacity > 0 && (!out->i || !out->j || !out->dist)) return fail(c, DL_ERR_INVALID, "null output array");
+  DL_HIP(c, hipSetDevice(c->device));
+  EpsJob J{R, store->base, false, store->prec, &store->prep, store->stats, threshold_from_eps(eps), nullptr};
+  return eps_core(c, J, ws, ws_bytes, out, static_cast<hipStream_t>(stream));
+}
+
+size_t dl_join_topk_store_workspace(int64_t nR, const dl_store* s, int32_t k, int32_t band_cap) {
+  if (!s || nR < 0 || k < 1) return 0;
+  int cu = 256, dev;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) cu = prop.multiProcessorCount;
+  return topk_workspace(nR, s->base.n, s->base.d, s->prec, false, true, k, band_cap, cu);
+}
+
+dl_status dl_join_topk_store(dl_ctx* c, dl_mat R, const dl_store* store, int32_t k, int32_t band_cap, void* ws,
+                             size_t ws_bytes, uint32_t* out_j, float* out_dist, dl_topk_info* info, void* stream) {
+  if (!c) return DL_ERR_INVALID;
+  c->err.clear();
+  c->required_ws = 0;
+  if (!store) return fail(c, DL_ERR_INVALID, "null store");
+  dl_status s;
+  if ((s = check_mat(c, R, "R")) != DL_OK) return s;
+  if (R.d != store->base.d) return fail(c, DL_ERR_INVALID, "R.d %d != store d %d", R.d, store->base.d);
+  if (k < 1 || k > 256) return fail(c, DL_ERR_INVALID, "k = %d outside [1, 256]", k);
+  if (R.n > 0 && (!out_j || !out_dist)) return fail(c, DL_ERR_INVALID, "null output array");
+  DL_HIP(c, hipSetDevice(c->device));
+  TopkJob J{R, store->base, false, false, store->prec, &store->prep, store->stats, k, band_cap};
+  return topk_core(c, J, ws, ws_bytes, out_j, out_dist, info, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -144,6 +144,21 @@ __device__ inline double canonical_d2(const float* __restrict__ a, const float* 
   return s;
 }
 
+// Carves 256-byte aligned pieces off a buffer; with a null base it only
+// counts the bytes (for workspace-size queries).
+struct Bump {
+  uint8_t* base;
+  size_t off = 0;
+  explicit Bump(void* b) : base(static_cast<uint8_t*>(b)) {}
+  template <class T>
+  T* take(int64_t count) {
+    off = (size_t)round_up((int64_t)off, 256);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += (size_t)count * sizeof(T);
+    return p;
+  }
+};
+
 // ------------------------------------------------------- error reporting
 struct Error {
   dl_status code;

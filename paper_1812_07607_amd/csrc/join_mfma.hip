@@ -42,6 +42,29 @@ constexpr int kWaveM = 128, kWaveN = 64;          // outputs per wave
 typedef __attribute__((address_space(1))) void gvoid_t;
 typedef __attribute__((address_space(3))) void lvoid_t;
 
+// 16 bytes per lane from global memory into LDS (global_load_lds_dwordx4):
+// lane l's bytes land at lds_dst + 16 l.  Issued as inline assembly so that
+// the compiler's wait-count insertion does not treat the transfer as a
+// write to the stage being read; the kernel orders it explicitly (vmcnt(0)
+// and a barrier before a stage is read or overwritten).
+__device__ inline void lds_dma16(const void* gsrc, void* lds_dst) {
+  const uint32_t m0 = __builtin_amdgcn_readfirstlane(
+      (uint32_t)reinterpret_cast<uintptr_t>((lvoid_t*)lds_dst));
+  // M0 (the LDS base of the transfer) is saved and restored around the
+  // transfer, and one wait state separates the M0 write from the LDS-DMA
+  // instruction that reads it.
+  uint32_t saved;
+  asm volatile(
+      "s_mov_b32 %0, m0\n\t"
+      "s_mov_b32 m0, %2\n\t"
+      "s_nop 0\n\t"
+      "global_load_lds_dwordx4 %1, off\n\t"
+      "s_mov_b32 m0, %0"
+      : "=&s"(saved)
+      : "v"(gsrc), "s"(m0)
+      : "memory");
+}
+
 // LDS byte offset of logical 16-byte piece c of tile row r.
 __device__ inline int lds_off(int r, int c) { return r * kChunkBytes + ((c ^ ((r >> 1) & 7)) << 4); }
 
@@ -123,8 +146,8 @@ __device__ inline void issue_loads(const CandParams& p, int64_t ti, int64_t tj, 
     const int c = (lane & 7) ^ ((row >> 1) & 7);
     const uint8_t* ga = p.qa + (ti * kTile + row) * p.qld + koff + c * 16;
     const uint8_t* gb = p.qb + (tj * kTile + row) * p.qld + koff + c * 16;
-    __builtin_amdgcn_global_load_lds((gvoid_t*)ga, (lvoid_t*)(la + q * 8 * kChunkBytes), 16, 0, 0);
-    __builtin_amdgcn_global_load_lds((gvoid_t*)gb, (lvoid_t*)(lb + q * 8 * kChunkBytes), 16, 0, 0);
+    lds_dma16(ga, la + q * 8 * kChunkBytes);
+    lds_dma16(gb, lb + q * 8 * kChunkBytes);
   }
 }
 
@@ -181,6 +204,8 @@ __device__ inline void mma_chunk(f32x4 (&acc)[8][4], const uint8_t* la, const ui
       for (int nb = 0; nb < 4; ++nb)
         acc[mb][nb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(aq, bq[nb], acc[mb][nb], 0, 0, 0, sa[mb], 0,
                                                                       sb[nb]);
+      // keep at most two 32-byte A fragments live (register pressure)
+      if (mb & 1) __builtin_amdgcn_sched_barrier(0);
     }
   } else {
     // fp32: 16x16x4; a 16-byte read gives 4 k-steps
@@ -278,29 +303,36 @@ __device__ inline float key_float(uint32_t k) {
   return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
 }
 
-// k-th largest order_key among the n entries at e (one wave).
-__device__ inline uint32_t kth_largest_key(const uint2* e, int n, int k) {
-  const int lane = threadIdx.x & 63;
-  uint32_t t = 0;
-  for (int b = 31; b >= 0; --b) {
-    const uint32_t cand = t | (1u << b);
-    int c = 0;
-    for (int s = lane; s < n; s += 64) c += order_key(__uint_as_float(e[s].x)) >= cand;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
-    if (c >= k) t = cand;
-  }
-  return t;
-}
+constexpr int kSelPerLane = 8;  // entries per lane in the k-selection subset
 
-// Tighten one row's band to P~_(k) - E_i and drop what falls below it.
-__device__ __attribute__((noinline)) void compact_row(const CandParams& p, uint2* e, int n, float marg, float* bthr, int* bcnt) {
+// Tighten one row's band and drop what falls below it (one wave).  The new
+// threshold is P~_(k) - E_i with P~_(k) the k-th largest value of the first
+// 64 * kSelPerLane entries: the k-th largest of a subset is at most the k-th
+// largest of the whole buffer, so the band stays a superset of the exact
+// one, and the selection runs on registers only.
+__device__ __attribute__((noinline)) void compact_row(const CandParams& p, uint2* e, int n, float marg,
+                                                      float* bthr, int* bcnt) {
   const int lane = threadIdx.x & 63;
   float thr = *bthr;
-  if (n >= p.k) {
-    const float pk = key_float(kth_largest_key(e, n, p.k));
-    const float nt = f32_down((double)pk - (double)marg);
-    thr = fmaxf(thr, nt);
+  const int m = min(n, 64 * kSelPerLane);
+  if (m >= p.k) {
+    uint32_t key[kSelPerLane];
+#pragma unroll
+    for (int t = 0; t < kSelPerLane; ++t) {
+      const int s = t * 64 + lane;
+      key[t] = s < m ? order_key(__uint_as_float(e[s].x)) : 0u;
+    }
+    uint32_t kk = 0;  // largest key with at least k entries >= it
+    for (int b = 31; b >= 0; --b) {
+      const uint32_t cand = kk | (1u << b);
+      int c = 0;
+#pragma unroll
+      for (int t = 0; t < kSelPerLane; ++t) c += key[t] >= cand;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+      if (c >= p.k) kk = cand;
+    }
+    thr = fmaxf(thr, f32_down((double)key_float(kk) - (double)marg));
   }
   int w = 0;
   const uint64_t lt = __lanemask_lt();
@@ -312,9 +344,9 @@ __device__ __attribute__((noinline)) void compact_row(const CandParams& p, uint2
       v = e[s];
       keep = __uint_as_float(v.x) >= thr;
     }
-    const uint64_t m = __ballot(keep);
-    if (keep) e[w + __popcll(m & lt)] = v;
-    w += __popcll(m);
+    const uint64_t mm = __ballot(keep);
+    if (keep) e[w + __popcll(mm & lt)] = v;
+    w += __popcll(mm);
   }
   if (lane == 0) {
     *bthr = thr;
@@ -323,42 +355,84 @@ __device__ __attribute__((noinline)) void compact_row(const CandParams& p, uint2
   }
 }
 
+// Band epilogue: a row-maximum test against the row's band threshold; only
+// a wave with a hit walks its outputs.  An append that takes a row's buffer
+// past cap - 256 queues the row in lds_list for tightening at the next
+// barrier (the buffer still has room for one more tile).
 __device__ inline void epilogue_band(const CandParams& p, int64_t ti, int64_t tj, int64_t split,
-                                     const f32x4 (&acc)[8][4], float* lds_thr, int* lds_cnt) {
+                                     const f32x4 (&acc)[8][4], const float* lds_thr, int* lds_cnt, int* lds_list) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave >> 2, wn = wave & 3;
   const int lrow0 = wm * kWaveM + 4 * (lane >> 4);
   const int64_t row0 = ti * kTile + lrow0;
   const int64_t col0 = tj * kTile + wn * kWaveN + (lane & 15);
+  float4 th[8];
+  bool any = false;
 #pragma unroll
   for (int mb = 0; mb < 8; ++mb) {
-    const float4 th = *reinterpret_cast<const float4*>(lds_thr + lrow0 + mb * 16);
-    const float tv[4] = {th.x, th.y, th.z, th.w};
+    th[mb] = *reinterpret_cast<const float4*>(lds_thr + lrow0 + mb * 16);
+    float m[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      m[r] = fmaxf(fmaxf(acc[mb][0][r], acc[mb][1][r]), fmaxf(acc[mb][2][r], acc[mb][3][r]));
+    any |= (m[0] >= th[mb].x) | (m[1] >= th[mb].y) | (m[2] >= th[mb].z) | (m[3] >= th[mb].w);
+  }
+  if (!__any(any)) return;
+  const int limit = p.cap - kTile;
+  const uint64_t lt = __lanemask_lt();
+  // lanes 16g..16g+15 hold the 16 columns of one row per (mb, r)
+  const uint64_t gmask = 0xffffull << (lane & 48);
+  const bool full = (ti + 1) * kTile <= p.nR && (tj + 1) * kTile <= p.nS && !(p.exclude_self && ti == tj);
+#pragma unroll
+  for (int mb = 0; mb < 8; ++mb) {
+    const float tv[4] = {th[mb].x, th[mb].y, th[mb].z, th[mb].w};
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t i = row0 + mb * 16 + r, j = col0 + nb * 16;
-        const bool v = acc[mb][nb][r] >= tv[r] && i < p.nR && j < p.nS && !(p.exclude_self && i == j);
-        if (v) {
+        bool hit = acc[mb][nb][r] >= tv[r];
+        if (!full) hit = hit && i < p.nR && j < p.nS && !(p.exclude_self && i == j);
+        const uint64_t m = __ballot(hit);
+        if (m) {
+          // one LDS atomic per row group, taken by its lowest hitting lane
+          const uint64_t gm = m & gmask;
           const int lr = lrow0 + mb * 16 + r;
-          const int pos = atomicAdd(&lds_cnt[lr], 1);
-          if (pos < p.cap)
-            p.band[((i * p.P) + split) * (int64_t)p.cap + pos] = make_uint2(__float_as_uint(acc[mb][nb][r]), (uint32_t)j);
+          const int first = gm ? __ffsll((unsigned long long)gm) - 1 : 0;
+          int base = 0;
+          if (hit && lane == first) {
+            const int cnt = __popcll(gm);
+            base = atomicAdd(&lds_cnt[lr], cnt);
+            if (base <= limit && limit < base + cnt) lds_list[1 + atomicAdd(&lds_list[0], 1)] = lr;
+          }
+          base = __shfl(base, first, 64);
+          if (hit) {
+            const int pos = base + __popcll(gm & lt);
+            if (pos < p.cap)
+              p.band[((i * p.P) + split) * (int64_t)p.cap + pos] =
+                  make_uint2(__float_as_uint(acc[mb][nb][r]), (uint32_t)j);
+          }
         }
       }
     }
   }
-  __syncthreads();
-  // rows whose buffer cannot take another full tile are tightened
-  for (int lr = wave; lr < kTile; lr += kThreads / 64) {
+}
+
+// Rows queued by the band epilogue are tightened by one wave each; called by
+// the whole workgroup right after a barrier, so lds_list[0] is uniform.
+__device__ inline void tighten_rows(const CandParams& p, int64_t ti, int64_t split, float* lds_thr, int* lds_cnt,
+                                    int* lds_list) {
+  const int nq = lds_list[0];
+  if (nq == 0) return;
+  const int wave = threadIdx.x >> 6;
+  for (int q = wave; q < nq; q += kThreads / 64) {
+    const int lr = lds_list[1 + q];
+    const int64_t i = ti * kTile + lr;
     const int n = min(lds_cnt[lr], p.cap);
-    if (n > p.cap - kTile) {
-      const int64_t i = ti * kTile + lr;
-      if (i < p.nR)
-        compact_row(p, p.band + ((i * p.P) + split) * (int64_t)p.cap, n, p.marg[i], &lds_thr[lr], &lds_cnt[lr]);
-    }
+    compact_row(p, p.band + ((i * p.P) + split) * (int64_t)p.cap, n, p.marg[i], &lds_thr[lr], &lds_cnt[lr]);
   }
+  __syncthreads();
+  if (threadIdx.x == 0) lds_list[0] = 0;
   __syncthreads();
 }
 
@@ -369,6 +443,7 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
   __shared__ __attribute__((aligned(1024))) uint8_t lds_ab[2][2][kStageBytes];
   __shared__ __attribute__((aligned(16))) float lds_thr[kMode == kModeBand ? kTile : 1];
   __shared__ int lds_cnt[kMode == kModeBand ? kTile : 1];
+  __shared__ int lds_list[kMode == kModeBand ? kTile + 1 : 1];
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave >> 2, wn = wave & 3;
@@ -384,6 +459,7 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
       lds_thr[r] = -INFINITY;
       lds_cnt[r] = 0;
     }
+    if (threadIdx.x == 0) lds_list[0] = 0;
   }
   int chunk = 0, stage = 0;
   issue_loads(p, ti, tj, 0, lds_ab[0][0], lds_ab[0][1]);
@@ -397,11 +473,13 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
       nchunk = 0;
       more = it.next(p, kMode, nti, ntj);
     }
-    // this step's operands are in LDS, and every wave is done with the
-    // other stage (it computed the previous step before this barrier)
+    // This step's operands are in LDS once this wave's loads have landed
+    // (vmcnt) and every wave has passed the barrier; the barrier also means
+    // every wave is done reading the other stage (it computed the previous
+    // step before arriving), so the next step's loads may overwrite it.
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (more) issue_loads(p, nti, ntj, nchunk, lds_ab[stage ^ 1][0], lds_ab[stage ^ 1][1]);
+    if constexpr (kMode == kModeBand) tighten_rows(p, ti, split, lds_thr, lds_cnt, lds_list);
     if (chunk == 0) {
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb) {
@@ -415,11 +493,15 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
 #pragma unroll
         for (int mb = 0; mb < 8; ++mb) sa[mb] = p.sexa[ti * kTile + wm * kWaveM + mb * 16 + (lane & 15)] + 127;
       }
+      // the initial values are in registers before the next step's
+      // transfers are queued behind them
+      __builtin_amdgcn_s_waitcnt(0);
     }
+    if (more) issue_loads(p, nti, ntj, nchunk, lds_ab[stage ^ 1][0], lds_ab[stage ^ 1][1]);
     mma_chunk<kPrec>(acc, lds_ab[stage][0], lds_ab[stage][1], wm * kWaveM, wn * kWaveN, sa, sb);
     if (chunk == p.nchunks - 1) {
       if constexpr (kMode == kModeEps) epilogue_eps(p, ti, tj, acc);
-      else epilogue_band(p, ti, tj, split, acc, lds_thr, lds_cnt);
+      else epilogue_band(p, ti, tj, split, acc, lds_thr, lds_cnt, lds_list);
     }
     if (!more) break;
     ti = nti;
@@ -429,6 +511,7 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
   }
   if constexpr (kMode == kModeBand) {
     __syncthreads();
+    tighten_rows(p, ti, split, lds_thr, lds_cnt, lds_list);
     for (int r = threadIdx.x; r < kTile; r += kThreads) {
       const int64_t i = ti * kTile + r;
       if (i < p.nR) p.bcount[i * p.P + split] = min(lds_cnt[r], p.cap);

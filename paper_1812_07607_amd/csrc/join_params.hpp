@@ -48,6 +48,7 @@ struct RecheckParams {
   const float* xnR; const int* mlR;
   const float* xnS; const int* mlS;
   double T;
+  const double* Trow;  // per-row thresholds (device) or null for T
   int bj;  // bits of j in the output key
   unsigned long long* keys; float* dist; unsigned long long* ocount;
   unsigned long long* nties;

@@ -175,8 +175,8 @@ __device__ inline double row_margin(const Prep& R, const RelStats& s, int64_t i,
 // eps mode: thr_i such that P~ >= thr_i for every pair with d2_64 <= T.
 // band mode: marg_i = E_i rounded up (the top-k band is P~ >= P~_(k) - E_i).
 __global__ __launch_bounds__(256) void threshold_kernel(Prep R, int64_t nR, const RelStats* __restrict__ S,
-                                                        int d, double T, float* __restrict__ thr,
-                                                        float* __restrict__ marg) {
+                                                        int d, double Tall, const double* __restrict__ Trow,
+                                                        float* __restrict__ thr, float* __restrict__ marg) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= R.npad) return;
   if (i >= nR) {
@@ -188,6 +188,7 @@ __global__ __launch_bounds__(256) void threshold_kernel(Prep R, int64_t nR, cons
   const double E = row_margin(R, s, i, d);
   if (marg) marg[i] = f32_up(E);
   if (thr) {
+    const double T = Trow ? Trow[i] : Tall;
     const double a2 = R.nrm2[i];
     if (isinf(T)) thr[i] = -INFINITY;
     else thr[i] = f32_down(0.5 * (a2 - T - E) - 0x1p-50 * (fabs(a2) + fabs(T) + E));
@@ -213,10 +214,10 @@ hipError_t launch_prep(const float* X, int64_t n, int32_t d, int64_t ld, dl_prec
   return hipGetLastError();
 }
 
-hipError_t launch_threshold(const Prep& R, int64_t nR, const RelStats* S, int d, double T, float* thr,
-                            float* marg, hipStream_t st) {
+hipError_t launch_threshold(const Prep& R, int64_t nR, const RelStats* S, int d, double T, const double* Trow,
+                            float* thr, float* marg, hipStream_t st) {
   const dim3 grid((unsigned)((R.npad + 255) / 256));
-  hipLaunchKernelGGL(threshold_kernel, grid, dim3(256), 0, st, R, nR, S, d, T, thr, marg);
+  hipLaunchKernelGGL(threshold_kernel, grid, dim3(256), 0, st, R, nR, S, d, T, Trow, thr, marg);
   return hipGetLastError();
 }
 

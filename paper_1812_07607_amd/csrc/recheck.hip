@@ -82,12 +82,13 @@ __global__ __launch_bounds__(256) void recheck_eps_kernel(RecheckParams p) {
       const double bt = ex ? 0.0 : beta32(d2, p.d, xsum);
       const double hi = ex ? d2 : (d2 + bt) * (1.0 + 0x1p-50);
       const double lo = ex ? d2 : (d2 - bt) * (1.0 - 0x1p-50);
-      in = hi <= p.T;
+      const double T = p.Trow ? p.Trow[mine.x] : p.T;
+      in = hi <= T;
       dist = sqrtf(mys);
-      if (!in && !(lo > p.T)) {  // boundary tie: the canonical float64 value decides
+      if (!in && !(lo > T)) {  // boundary tie: the canonical float64 value decides
         tie = true;
         const double d64 = canonical_d2(p.R + (int64_t)mine.x * p.ldr, p.S + (int64_t)mine.y * p.lds, p.d);
-        in = d64 <= p.T;
+        in = d64 <= T;
         dist = (float)sqrt(d64);
       }
     }
@@ -178,27 +179,38 @@ __global__ __launch_bounds__(64 * kSelWaves) void topk_select_kernel(SelectParam
     bt = f32_down((double)pk - (double)p.marg[i]);
   }
 
-  // (2) float32 direct-form d2 of every band entry, written over its P~
+  // (2) float32 direct-form d2 of every band entry, written over its P~:
+  // 64 entries at a time, each summed by the whole wave with coalesced row
+  // reads; lane t keeps entry t's sum.
   int nb = 0;
   for (int s = 0; s < p.P; ++s) {
     uint2* e = p.band + (i * p.P + s) * (int64_t)p.cap;
     const int n = p.bcount[i * p.P + s];
-    for (int t = lane; t < n; t += 64) {
-      uint2 v = e[t];
-      float d2 = INFINITY;
-      if (__uint_as_float(v.x) >= bt) {
-        const float* b = p.S + (int64_t)v.y * p.lds;
+    for (int base = 0; base < n; base += 64) {
+      const int cnt = min(64, n - base);
+      const uint2 v = lane < cnt ? e[base + lane] : make_uint2(0, 0);
+      const bool inband = lane < cnt && __uint_as_float(v.x) >= bt;
+      const uint64_t mb = __ballot(inband);
+      float mine = INFINITY;
+      uint64_t rest = mb;
+      while (rest) {
+        const int t = __ffsll((unsigned long long)rest) - 1;
+        rest &= rest - 1;
+        const uint32_t jt = __shfl(v.y, t, 64);
+        const float* b = p.S + (int64_t)jt * p.lds;
         float acc = 0.0f;
-        for (int q = 0; q < p.d; ++q) {
+        for (int q = lane; q < p.d; q += 64) {
           const float u = a[q] - b[q];
           acc = fmaf(u, u, acc);
         }
-        d2 = acc;
-        ++nb;
+        acc = wave_sumf(acc);
+        if (lane == t) mine = acc;
       }
-      e[t].x = __float_as_uint(d2);
+      if (lane < cnt) e[base + lane].x = __float_as_uint(mine);
+      nb += __popcll(mb);
     }
   }
+  if (lane != 0) nb = 0;
   nb = wave_sumi(nb);
   if (lane == 0) atomicAdd(p.nband, (unsigned long long)nb);
 

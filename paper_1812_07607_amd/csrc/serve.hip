@@ -1,0 +1,558 @@
+// serve.hip -- the serving loop: a resident store probed by batched requests.
+//
+// Paper: the on-the-fly index similarity join of section "Query Processing"
+// keeps one relation resident and probes it with the other; here the resident
+// relation is a dl_store (operand copy and statistics built once) and the
+// probes are requests of query rows, each an eps-join or a top-k join.
+//
+// Design.  n_streams worker threads, each with its own context and HIP
+// stream.  A worker that is idle takes the request at the head of the FIFO
+// queue plus every later queued request with the same mode (and k), up to
+// the batch limits, reserves the batch's memory from the caller's arena, and
+// runs the whole batch as one join against the store: the query rows are
+// packed into one matrix (one eps threshold per row), so many small requests
+// share one pass over the store.  If the arena cannot hold the batch it is
+// shrunk; if not even the head fits, the worker waits for memory to be
+// released (or rejects the head when nothing else holds memory).  Requests
+// that arrive while batches are on the GPU are admitted by the next worker
+// that frees up: continuous batching.  Per-pair arithmetic does not depend on
+// which rows share a batch, so a request's result is the same alone and in a
+// mix.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "core.hpp"
+
+namespace dl {
+
+static double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// First-fit allocator over byte offsets of the arena (256-byte granules).
+class ArenaAlloc {
+ public:
+  explicit ArenaAlloc(size_t size) : size_(size) {
+    if (size) free_[0] = size;
+  }
+  bool alloc(size_t bytes, size_t* off) {
+    bytes = (size_t)round_up((int64_t)(bytes ? bytes : 1), 256);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        *off = it->first;
+        const size_t rest = it->second - bytes, at = it->first + bytes;
+        free_.erase(it);
+        if (rest) free_[at] = rest;
+        used_ += bytes;
+        peak_ = std::max(peak_, used_);
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    bytes = (size_t)round_up((int64_t)(bytes ? bytes : 1), 256);
+    used_ -= bytes;
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t used() const { return used_; }
+  size_t peak() const { return peak_; }
+  size_t size() const { return size_; }
+
+ private:
+  std::map<size_t, size_t> free_;
+  size_t size_, used_ = 0, peak_ = 0;
+};
+
+struct Batch;
+
+struct Req {
+  uint64_t ticket = 0;
+  dl_request rq{};
+  int state = 0;  // 0 queued, 1 running, 2 done
+  dl_status status = DL_OK;
+  double t_submit = 0, t_start = 0, t_done = 0;
+  const uint32_t *oi = nullptr, *oj = nullptr;
+  const float* od = nullptr;
+  int64_t count = 0;
+  int64_t row_off = 0;
+  std::shared_ptr<Batch> batch;
+  bool released = false;
+};
+
+struct Batch {
+  int64_t id = 0;
+  int mode = DL_MODE_EPS, k = 0;
+  std::vector<Req*> reqs;
+  int64_t rows = 0;
+  size_t off = 0, bytes = 0;  // arena block
+  int live = 0;               // requests not yet released
+};
+
+// Device helpers for one eps batch: start of each request's pairs in the
+// (i, j)-sorted output, and batch-row -> request-row conversion of i.
+__global__ void eps_demux_starts(const uint32_t* oi, int64_t m, const int64_t* row_off, int nreq,
+                                 int64_t* starts) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r > nreq) return;
+  const int64_t key = row_off[r];
+  int64_t lo = 0, hi = m;  // first t with oi[t] >= key
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)oi[mid] < key) lo = mid + 1; else hi = mid;
+  }
+  starts[r] = lo;
+}
+
+__global__ void eps_demux_rows(uint32_t* oi, int64_t m, const int64_t* row_off, int nreq) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = oi[t];
+    int lo = 0, hi = nreq - 1;  // last r with row_off[r] <= i
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (row_off[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    oi[t] = (uint32_t)(i - row_off[lo]);
+  }
+}
+
+}  // namespace dl
+
+using namespace dl;
+
+struct dl_server {
+  const dl_store* store = nullptr;
+  dl_server_config cfg{};
+  uint8_t* arena = nullptr;
+  ArenaAlloc alloc{0};
+  int device = 0;
+  int cu = 256;
+
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Req*> queue;
+  std::map<uint64_t, Req*> reqs;
+  std::vector<std::thread> workers;
+  bool stopping = false;
+  int busy = 0;  // batches holding arena memory or running
+  uint64_t next_ticket = 1;
+  int64_t next_batch = 1;
+
+  // statistics
+  int64_t submitted = 0, completed = 0, rejected = 0, cancelled = 0, batches = 0, batch_reqs = 0;
+  double pairs_done = 0, t_first = -1, t_last = 0;
+  std::vector<double> lat;
+
+  ArenaAlloc& A() { return alloc; }
+};
+
+namespace {
+
+int64_t rows_of(const Req* r) { return r->rq.query.n; }
+
+// Bytes a batch needs: packed query rows, per-row thresholds (eps), the
+// join's workspace and its outputs.
+size_t batch_bytes(dl_server* S, int mode, int k, int64_t rows, int nreq, int64_t pair_cap, int64_t cand_cap) {
+  const dl_store* st = S->store;
+  const int d = st->base.d;
+  size_t b = (size_t)round_up(rows * (int64_t)d * 4, 256) + (size_t)round_up((nreq + 1) * 8 * 2, 256);
+  if (mode == DL_MODE_EPS) {
+    b += (size_t)round_up(rows * 8, 256);
+    b += eps_workspace(rows, st->base.n, d, st->prec, false, true, cand_cap);
+    b += (size_t)round_up(pair_cap * 4, 256) * 3;
+  } else {
+    b += topk_workspace(rows, st->base.n, d, st->prec, false, true, k, S->cfg.band_cap, S->cu);
+    b += (size_t)round_up(rows * (int64_t)k * 4, 256) * 2;
+  }
+  return b;
+}
+
+void caps_for(dl_server* S, int64_t rows, int64_t* pair_cap, int64_t* cand_cap) {
+  const int64_t ppr = S->cfg.pairs_per_row > 0 ? S->cfg.pairs_per_row : 64;
+  *pair_cap = std::max<int64_t>(1 << 16, rows * ppr);
+  *cand_cap = std::max<int64_t>(1 << 17, 2 * rows * ppr);
+}
+
+void finish(dl_server* S, Req* r, dl_status st, double t) {
+  r->status = st;
+  r->state = 2;
+  r->t_done = t;
+  ++S->completed;
+  if (st == DL_OK) {
+    S->lat.push_back(r->t_done - r->t_submit);
+    S->pairs_done += (double)rows_of(r) * (double)S->store->base.n;
+  }
+  S->t_last = t;
+}
+
+// Under the lock: form the next batch (or return null).  Requests whose
+// memory can never fit are rejected here.
+std::shared_ptr<Batch> take_batch(dl_server* S) {
+  while (!S->queue.empty()) {
+    Req* head = S->queue.front();
+    const int mode = head->rq.mode, k = head->rq.k;
+    std::vector<Req*> pick{head};
+    int64_t rows = rows_of(head);
+    for (size_t q = 1; q < S->queue.size(); ++q) {
+      Req* r = S->queue[q];
+      if ((int)pick.size() >= S->cfg.max_batch_requests) break;
+      if (r->rq.mode != mode || (mode == DL_MODE_TOPK && r->rq.k != k)) continue;
+      if (rows + rows_of(r) > S->cfg.max_batch_rows) continue;
+      pick.push_back(r);
+      rows += rows_of(r);
+    }
+    // shrink until the arena has room
+    for (;;) {
+      int64_t pc, cc;
+      caps_for(S, rows, &pc, &cc);
+      const size_t need = batch_bytes(S, mode, k, rows, (int)pick.size(), pc, cc);
+      size_t off;
+      if (S->alloc.alloc(need, &off)) {
+        auto b = std::make_shared<Batch>();
+        b->id = S->next_batch++;
+        b->mode = mode;
+        b->k = k;
+        b->reqs = pick;
+        b->rows = rows;
+        b->off = off;
+        b->bytes = need;
+        b->live = (int)pick.size();
+        for (Req* r : pick) {
+          S->queue.erase(std::find(S->queue.begin(), S->queue.end(), r));
+          r->state = 1;
+          r->batch = b;
+        }
+        return b;
+      }
+      if (pick.size() > 1) {
+        rows -= rows_of(pick.back());
+        pick.pop_back();
+        continue;
+      }
+      if (S->busy == 0 && need > S->alloc.size() - S->alloc.used()) {
+        // cannot fit even in an otherwise empty arena: reject
+        S->queue.pop_front();
+        ++S->rejected;
+        finish(S, head, DL_ERR_OOM, now_ms());
+        S->cv_done.notify_all();
+        break;  // try the next head
+      }
+      return nullptr;  // wait for memory
+    }
+  }
+  return nullptr;
+}
+
+// Runs one batch on the worker's stream (outside the lock).
+dl_status run_batch(dl_server* S, dl_ctx* ctx, hipStream_t st, Batch& b, std::string* err) {
+  const dl_store* store = S->store;
+  const int d = store->base.d;
+  uint8_t* base = S->arena + b.off;
+  Bump bump(base);
+  float* R = bump.take<float>(b.rows * (int64_t)d);
+  int64_t* row_off = bump.take<int64_t>((int64_t)b.reqs.size() + 1);
+  int64_t* starts = bump.take<int64_t>((int64_t)b.reqs.size() + 1);
+  std::vector<int64_t> hoff(b.reqs.size() + 1, 0);
+  for (size_t q = 0; q < b.reqs.size(); ++q) {
+    const dl_mat& m = b.reqs[q]->rq.query;
+    hoff[q + 1] = hoff[q] + m.n;
+    b.reqs[q]->row_off = hoff[q];
+    if (m.n > 0 && hipMemcpy2DAsync(R + hoff[q] * d, (size_t)d * 4, m.data, (size_t)m.ld * 4, (size_t)d * 4,
+                                    (size_t)m.n, hipMemcpyDeviceToDevice, st) != hipSuccess)
+      return *err = "query copy failed", DL_ERR_DEVICE;
+  }
+  if (hipMemcpyAsync(row_off, hoff.data(), hoff.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess)
+    return *err = "offset copy failed", DL_ERR_DEVICE;
+  const dl_mat Rm{R, b.rows, d, d};
+  if (b.mode == DL_MODE_TOPK) {
+    const int k = b.k;
+    const size_t ws_bytes =
+        topk_workspace(b.rows, store->base.n, d, store->prec, false, true, k, S->cfg.band_cap, S->cu);
+    void* ws = bump.take<uint8_t>((int64_t)ws_bytes);
+    uint32_t* oj = bump.take<uint32_t>(b.rows * k);
+    float* od = bump.take<float>(b.rows * k);
+    TopkJob J{Rm, store->base, false, false, store->prec, &store->prep, store->stats, k, S->cfg.band_cap};
+    dl_status s = topk_core(ctx, J, ws, ws_bytes, oj, od, nullptr, st);
+    if (s != DL_OK) return *err = dl_last_error(ctx), s;
+    for (Req* r : b.reqs) {
+      r->oj = oj + r->row_off * k;
+      r->od = od + r->row_off * k;
+      r->count = rows_of(r) * k;
+    }
+    return DL_OK;
+  }
+  // eps: one threshold per packed row
+  int64_t pc, cc;
+  caps_for(S, b.rows, &pc, &cc);
+  double* Trow = bump.take<double>(b.rows);
+  std::vector<double> hT((size_t)b.rows);
+  for (Req* r : b.reqs) std::fill_n(hT.begin() + r->row_off, rows_of(r), eps_threshold(r->rq.eps));
+  if (b.rows && hipMemcpyAsync(Trow, hT.data(), hT.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess)
+    return *err = "threshold copy failed", DL_ERR_DEVICE;
+  const size_t ws_bytes = eps_workspace(b.rows, store->base.n, d, store->prec, false, true, cc);
+  void* ws = bump.take<uint8_t>((int64_t)ws_bytes);
+  uint32_t* oi = bump.take<uint32_t>(pc);
+  uint32_t* oj = bump.take<uint32_t>(pc);
+  float* od = bump.take<float>(pc);
+  dl_pairs P{oi, oj, od, pc, 0, 0, 0};
+  EpsJob J{Rm, store->base, false, store->prec, &store->prep, store->stats, 0.0, Trow};
+  dl_status s = eps_core(ctx, J, ws, ws_bytes, &P, st);
+  if (s != DL_OK) return *err = dl_last_error(ctx), s;
+  const int nreq = (int)b.reqs.size();
+  hipLaunchKernelGGL(eps_demux_starts, dim3((nreq + 1 + 63) / 64), dim3(64), 0, st, oi, P.count, row_off, nreq,
+                     starts);
+  if (P.count > 0)
+    hipLaunchKernelGGL(eps_demux_rows, dim3((unsigned)std::min<int64_t>((P.count + 255) / 256, 4096)), dim3(256), 0,
+                       st, oi, P.count, row_off, nreq);
+  std::vector<int64_t> hs(nreq + 1);
+  if (hipMemcpyAsync(hs.data(), starts, hs.size() * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return *err = "demux failed", DL_ERR_DEVICE;
+  for (int q = 0; q < nreq; ++q) {
+    Req* r = b.reqs[q];
+    r->oi = oi + hs[q];
+    r->oj = oj + hs[q];
+    r->od = od + hs[q];
+    r->count = hs[q + 1] - hs[q];
+  }
+  return DL_OK;
+}
+
+void worker_main(dl_server* S, int idx) {
+  (void)idx;
+  if (hipSetDevice(S->device) != hipSuccess) return;
+  dl_ctx* ctx = nullptr;
+  if (dl_create(S->device, &ctx) != DL_OK) return;
+  hipStream_t st;
+  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+    dl_destroy(ctx);
+    return;
+  }
+  std::unique_lock<std::mutex> lk(S->mu);
+  for (;;) {
+    std::shared_ptr<Batch> b;
+    while (!S->stopping && !(b = take_batch(S))) S->cv_work.wait(lk);
+    if (!b) break;
+    ++S->busy;
+    ++S->batches;
+    S->batch_reqs += (int64_t)b->reqs.size();
+    const double t0 = now_ms();
+    for (Req* r : b->reqs) r->t_start = t0;
+    lk.unlock();
+    std::string err;
+    dl_status s = run_batch(S, ctx, st, *b, &err);
+    if (s == DL_OK && hipStreamSynchronize(st) != hipSuccess) s = DL_ERR_DEVICE;
+    const double t1 = now_ms();
+    lk.lock();
+    for (Req* r : b->reqs) finish(S, r, s, t1);
+    S->cv_done.notify_all();
+  }
+  lk.unlock();
+  (void)hipStreamDestroy(st);
+  dl_destroy(ctx);
+}
+
+// Under the lock: drop a batch's memory once every request is released.
+void release_req(dl_server* S, Req* r) {
+  r->released = true;
+  std::shared_ptr<Batch> b = r->batch;
+  r->batch.reset();
+  if (b && --b->live == 0) {
+    S->alloc.release(b->off, b->bytes);
+    --S->busy;
+    S->cv_work.notify_all();
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+dl_status dl_server_create(int device, const dl_store* store, const dl_server_config* cfg, void* arena,
+                           size_t arena_bytes, dl_server** out) {
+  if (!out) return DL_ERR_INVALID;
+  *out = nullptr;
+  if (!store || !arena || arena_bytes < 4096) return DL_ERR_INVALID;
+  dl_server_config c{};
+  if (cfg) c = *cfg;
+  if (c.n_streams <= 0) c.n_streams = 2;
+  if (c.n_streams > 8) c.n_streams = 8;
+  if (c.max_batch_requests <= 0) c.max_batch_requests = 64;
+  if (c.max_batch_rows <= 0) c.max_batch_rows = 1 << 16;
+  if (c.pairs_per_row <= 0) c.pairs_per_row = 64;
+  dl_server* S = new (std::nothrow) dl_server();
+  if (!S) return DL_ERR_OOM;
+  S->store = store;
+  S->cfg = c;
+  S->arena = static_cast<uint8_t*>(arena);
+  S->alloc = ArenaAlloc(arena_bytes / 256 * 256);
+  S->device = device;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) S->cu = prop.multiProcessorCount;
+  for (int w = 0; w < c.n_streams; ++w) S->workers.emplace_back(worker_main, S, w);
+  *out = S;
+  return DL_OK;
+}
+
+dl_status dl_server_submit(dl_server* S, const dl_request* rq, uint64_t* ticket) {
+  if (!S || !rq || !ticket) return DL_ERR_INVALID;
+  const dl_mat& q = rq->query;
+  if (q.n < 0 || q.d != S->store->base.d || q.ld < q.d || (q.n > 0 && !q.data)) return DL_ERR_INVALID;
+  if (rq->mode != DL_MODE_EPS && rq->mode != DL_MODE_TOPK) return DL_ERR_INVALID;
+  if (rq->mode == DL_MODE_EPS && (std::isnan(rq->eps) || rq->eps < 0)) return DL_ERR_INVALID;
+  if (rq->mode == DL_MODE_TOPK && (rq->k < 1 || rq->k > 256)) return DL_ERR_INVALID;
+  Req* r = new (std::nothrow) Req();
+  if (!r) return DL_ERR_OOM;
+  r->rq = *rq;
+  r->t_submit = now_ms();
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (S->stopping) {
+    delete r;
+    return DL_ERR_CANCELLED;
+  }
+  r->ticket = S->next_ticket++;
+  S->reqs[r->ticket] = r;
+  ++S->submitted;
+  if (S->t_first < 0) S->t_first = r->t_submit;
+  if (q.n == 0) {
+    finish(S, r, DL_OK, r->t_submit);
+  } else {
+    S->queue.push_back(r);
+    S->cv_work.notify_one();
+  }
+  *ticket = r->ticket;
+  return DL_OK;
+}
+
+dl_status dl_server_wait(dl_server* S, uint64_t ticket, int32_t timeout_ms, dl_result* out) {
+  if (!S || !out) return DL_ERR_INVALID;
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) return DL_ERR_INVALID;
+  Req* r = it->second;
+  auto done = [&] { return r->state == 2; };
+  if (timeout_ms < 0) S->cv_done.wait(lk, done);
+  else if (!S->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), done)) return DL_ERR_BUSY;
+  std::memset(out, 0, sizeof *out);
+  out->status = r->status;
+  out->mode = r->rq.mode;
+  out->rows = rows_of(r);
+  out->k = r->rq.mode == DL_MODE_TOPK ? r->rq.k : 0;
+  out->i = r->oi;
+  out->j = r->oj;
+  out->dist = r->od;
+  out->count = r->count;
+  out->queued_ms = r->t_start > 0 ? r->t_start - r->t_submit : 0.0;
+  out->latency_ms = r->t_done - r->t_submit;
+  out->batch_id = r->batch ? r->batch->id : 0;
+  out->batch_requests = r->batch ? (int32_t)r->batch->reqs.size() : 0;
+  return DL_OK;
+}
+
+dl_status dl_server_release(dl_server* S, uint64_t ticket) {
+  if (!S) return DL_ERR_INVALID;
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) return DL_ERR_INVALID;
+  Req* r = it->second;
+  if (r->state != 2) return DL_ERR_BUSY;
+  release_req(S, r);
+  S->reqs.erase(it);
+  delete r;
+  return DL_OK;
+}
+
+dl_status dl_server_cancel(dl_server* S, uint64_t ticket) {
+  if (!S) return DL_ERR_INVALID;
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) return DL_ERR_INVALID;
+  Req* r = it->second;
+  if (r->state != 0) return DL_ERR_BUSY;
+  S->queue.erase(std::find(S->queue.begin(), S->queue.end(), r));
+  ++S->cancelled;
+  finish(S, r, DL_ERR_CANCELLED, now_ms());
+  S->cv_done.notify_all();
+  return DL_OK;
+}
+
+dl_status dl_server_stats(dl_server* S, dl_server_info* out) {
+  if (!S || !out) return DL_ERR_INVALID;
+  std::lock_guard<std::mutex> lk(S->mu);
+  std::memset(out, 0, sizeof *out);
+  out->submitted = S->submitted;
+  out->completed = S->completed;
+  out->rejected = S->rejected;
+  out->cancelled = S->cancelled;
+  out->batches = S->batches;
+  out->mean_batch_requests = S->batches ? (double)S->batch_reqs / (double)S->batches : 0.0;
+  out->pairs_done = S->pairs_done;
+  out->span_ms = S->t_first >= 0 ? S->t_last - S->t_first : 0.0;
+  out->arena_in_use = S->alloc.used();
+  out->arena_peak = S->alloc.peak();
+  out->queued = (int64_t)S->queue.size();
+  if (!S->lat.empty()) {
+    std::vector<double> v = S->lat;
+    std::sort(v.begin(), v.end());
+    auto pct = [&](double q) {
+      const size_t idx = (size_t)std::min<double>((double)v.size() - 1, std::ceil(q * (double)v.size()) - 1);
+      return v[idx];
+    };
+    out->p50_ms = pct(0.50);
+    out->p99_ms = pct(0.99);
+    out->max_ms = v.back();
+  }
+  return DL_OK;
+}
+
+dl_status dl_server_reset_stats(dl_server* S) {
+  if (!S) return DL_ERR_INVALID;
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->submitted = S->completed = S->rejected = S->cancelled = S->batches = S->batch_reqs = 0;
+  S->pairs_done = 0;
+  S->t_first = -1;
+  S->t_last = 0;
+  S->lat.clear();
+  return DL_OK;
+}
+
+void dl_server_destroy(dl_server* S) {
+  if (!S) return;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stopping = true;
+    // queued requests are cancelled; running batches finish
+    for (Req* r : S->queue) finish(S, r, DL_ERR_CANCELLED, now_ms());
+    S->queue.clear();
+    S->cv_work.notify_all();
+    S->cv_done.notify_all();
+  }
+  for (auto& t : S->workers) t.join();
+  for (auto& kv : S->reqs) delete kv.second;
+  delete S;
+}
+
+}  // extern "C"

@@ -217,3 +217,177 @@ def join_topk(R: torch.Tensor, S: torch.Tensor | None, k: int, exclude_self: boo
         return TopkResult(oj, od, int(info.band_entries), int(info.ties))
     raise RuntimeError("join_topk did not converge on band capacity")
 
+
+
+# ---------------------------------------------------------------- store
+class Store:
+    """A resident relation: float32 rows (kept alive here) plus their operand
+    copy and statistics, built once on the GPU."""
+
+    def __init__(self, base: torch.Tensor, prec: str = "bf16", stream=None):
+        self.c = context(base.device.index)
+        L = self.c.L
+        self.base = base
+        self.prec = prec
+        self.n, self.d = base.shape
+        nbytes = L.dl_store_bytes(self.n, self.d, _lib.PREC[prec])
+        self.mem = torch.empty(int(nbytes), dtype=torch.uint8, device=base.device)
+        h = ctypes.c_void_p()
+        self.c.check(L.dl_store_create(self.c.h, _mat(base), _lib.PREC[prec], ctypes.c_void_p(self.mem.data_ptr()),
+                                       nbytes, ctypes.byref(h), _stream_ptr(stream)))
+        self.h = h
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                self.c.L.dl_store_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def join_eps(self, R: torch.Tensor, eps: float, max_candidates: int | None = None, stream=None,
+                 workspace: Workspace | None = None) -> EpsResult:
+        c, L = self.c, self.c.L
+        ws = workspace or _workspace(R.device)
+        nR = R.shape[0]
+        if max_candidates is None:
+            max_candidates = max(1 << 20, 64 * nR)
+        cap = max(1 << 16, 16 * nR)
+        for _ in range(10):
+            buf = ws.get(L.dl_join_eps_store_workspace(nR, self.h, max_candidates))
+            oi = torch.empty(cap, dtype=torch.int32, device=R.device)
+            oj = torch.empty(cap, dtype=torch.int32, device=R.device)
+            od = torch.empty(cap, dtype=torch.float32, device=R.device)
+            pr = _lib.dl_pairs(oi.data_ptr(), oj.data_ptr(), od.data_ptr(), cap, 0, 0, 0)
+            st = L.dl_join_eps_store(c.h, _mat(R), self.h, float(eps), ctypes.c_void_p(buf.data_ptr()), buf.numel(),
+                                     ctypes.byref(pr), _stream_ptr(stream))
+            if st == _lib.DL_ERR_WORKSPACE:
+                max_candidates = max(2 * max_candidates, int(pr.candidates * 1.25) + 1024)
+                continue
+            if st == _lib.DL_ERR_CAPACITY:
+                cap = int(pr.count)
+                continue
+            c.check(st)
+            m = int(pr.count)
+            return EpsResult(oi[:m], oj[:m], od[:m], m, int(pr.candidates), int(pr.ties))
+        raise RuntimeError("join_eps (store) did not converge")
+
+    def join_topk(self, R: torch.Tensor, k: int, band_cap: int = 0, stream=None,
+                  workspace: Workspace | None = None) -> TopkResult:
+        c, L = self.c, self.c.L
+        ws = workspace or _workspace(R.device)
+        nR = R.shape[0]
+        oj = torch.empty((nR, k), dtype=torch.int32, device=R.device)
+        od = torch.empty((nR, k), dtype=torch.float32, device=R.device)
+        info = _lib.dl_topk_info()
+        for _ in range(6):
+            buf = ws.get(L.dl_join_topk_store_workspace(nR, self.h, k, band_cap))
+            st = L.dl_join_topk_store(c.h, _mat(R), self.h, k, band_cap, ctypes.c_void_p(buf.data_ptr()), buf.numel(),
+                                      ctypes.c_void_p(oj.data_ptr()), ctypes.c_void_p(od.data_ptr()), ctypes.byref(info),
+                                      _stream_ptr(stream))
+            if st == _lib.DL_ERR_WORKSPACE:
+                band_cap = max(2 * (band_cap or 1024), 1024)
+                continue
+            c.check(st)
+            return TopkResult(oj, od, int(info.band_entries), int(info.ties))
+        raise RuntimeError("join_topk (store) did not converge")
+
+
+class _DeviceView:
+    """Zero-copy view of library-owned device memory for torch.as_tensor."""
+
+    def __init__(self, ptr, shape, typestr):
+        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": typestr, "data": (int(ptr or 0), True),
+                                         "version": 2, "strides": None}
+
+
+def _view(ptr, shape, typestr, device):
+    if int(ptr or 0) == 0 or 0 in shape:
+        dt = {"<u4": torch.int32, "<f4": torch.float32}[typestr]
+        return torch.empty(shape, dtype=dt, device=device)
+    return torch.as_tensor(_DeviceView(ptr, shape, typestr), device=device)
+
+
+class Server:
+    """Batching request loop over a Store (see dl_server_* in dlmi.h)."""
+
+    def __init__(self, store: Store, arena_bytes: int, n_streams: int = 2, max_batch_requests: int = 64,
+                 max_batch_rows: int = 1 << 16, pairs_per_row: int = 64, band_cap: int = 0):
+        self.store = store
+        self.c = store.c
+        self.L = self.c.L
+        self.device = store.base.device
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
+        cfg = _lib.dl_server_config(n_streams, max_batch_requests, max_batch_rows, pairs_per_row, band_cap)
+        h = ctypes.c_void_p()
+        st = self.L.dl_server_create(self.device.index or 0, store.h, ctypes.byref(cfg),
+                                     ctypes.c_void_p(self.arena.data_ptr()), self.arena.numel(), ctypes.byref(h))
+        if st != _lib.DL_OK:
+            raise _lib.DLError(st, "dl_server_create failed")
+        self.h = h
+        self._live = {}
+
+    def submit(self, query: torch.Tensor, mode: str, eps: float = 0.0, k: int = 10, sync: bool = True) -> int:
+        """Queue a request; `query` must be complete on the device (with
+        sync=True this call waits for the current stream) and is kept alive
+        until completion."""
+        if sync:
+            torch.cuda.current_stream().synchronize()
+        m = _lib.DL_MODE_EPS if mode == "eps" else _lib.DL_MODE_TOPK
+        rq = _lib.dl_request(_mat(query), m, float(eps), int(k))
+        t = ctypes.c_uint64()
+        st = self.L.dl_server_submit(self.h, ctypes.byref(rq), ctypes.byref(t))
+        if st != _lib.DL_OK:
+            raise _lib.DLError(st, "submit rejected")
+        self._live[t.value] = query
+        return t.value
+
+    def wait(self, ticket: int, timeout_ms: int = -1, fetch: bool = True) -> dict:
+        """Wait for a request, copy its result into torch tensors (unless
+        fetch=False), and release it."""
+        r = _lib.dl_result()
+        st = self.L.dl_server_wait(self.h, ticket, timeout_ms, ctypes.byref(r))
+        if st != _lib.DL_OK:
+            raise _lib.DLError(st, "wait failed")
+        out = {"status": r.status, "mode": "eps" if r.mode == _lib.DL_MODE_EPS else "topk", "rows": r.rows,
+               "latency_ms": r.latency_ms, "queued_ms": r.queued_ms, "batch_id": r.batch_id,
+               "batch_requests": r.batch_requests}
+        if r.status == _lib.DL_OK and r.mode == _lib.DL_MODE_EPS:
+            out["count"] = int(r.count)
+        if r.status == _lib.DL_OK and fetch:
+            if r.mode == _lib.DL_MODE_EPS:
+                n = int(r.count)
+                out["i"] = _view(r.i, (n,), "<u4", self.device).clone()
+                out["j"] = _view(r.j, (n,), "<u4", self.device).clone()
+                out["dist"] = _view(r.dist, (n,), "<f4", self.device).clone()
+                out["count"] = n
+            else:
+                out["j"] = _view(r.j, (int(r.rows), int(r.k)), "<u4", self.device).clone()
+                out["dist"] = _view(r.dist, (int(r.rows), int(r.k)), "<f4", self.device).clone()
+            torch.cuda.current_stream().synchronize()  # copies done before the memory is reused
+        self.L.dl_server_release(self.h, ticket)
+        self._live.pop(ticket, None)
+        return out
+
+    def cancel(self, ticket: int) -> bool:
+        return self.L.dl_server_cancel(self.h, ticket) == _lib.DL_OK
+
+    def stats(self) -> dict:
+        s = _lib.dl_server_info()
+        self.L.dl_server_stats(self.h, ctypes.byref(s))
+        return {f: getattr(s, f) for f, _ in s._fields_}
+
+    def reset_stats(self):
+        self.L.dl_server_reset_stats(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.dl_server_destroy(self.h)
+            self.h = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
