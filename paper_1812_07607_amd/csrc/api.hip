@@ -379,7 +379,7 @@ dl_status dl_pair_d2(dl_ctx* c, dl_mat R, dl_mat S, const uint32_t* pi, const ui
 namespace dl {
 
 static int band_cap_of(int32_t band_cap, int k) {
-  if (band_cap <= 0) band_cap = 1024;
+  if (band_cap <= 0) band_cap = 512;
   band_cap = (int32_t)round_up(band_cap < 512 ? 512 : band_cap, 64);
   if (band_cap < 2 * k + kTile) band_cap = (int32_t)round_up(2 * k + kTile, 64);
   return band_cap;

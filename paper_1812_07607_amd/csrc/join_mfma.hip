@@ -101,6 +101,16 @@ __device__ inline bool tile_of(const CandParams& p, int64_t L, int64_t& ti, int6
   return ti <= tj && tj < nT;
 }
 
+// Marks a block-uniform 64-bit value as such, so that it lives in scalar
+// registers (the uniformity analysis loses tile indices carried around the
+// persistent loop, and 64-bit vector copies of them crowd out the
+// accumulators).
+__device__ inline int64_t uniform64(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // Block-uniform iterator over this workgroup's tiles.
 struct TileIter {
   int64_t step;  // eps: logical round; band: S tile within split
@@ -112,7 +122,11 @@ struct TileIter {
         const int64_t L = step * G + slot;
         ++step;
         if (L >= p.nlogical) return false;
-        if (tile_of(p, L, ti, tj)) return true;
+        if (tile_of(p, L, ti, tj)) {
+          ti = uniform64(ti);
+          tj = uniform64(tj);
+          return true;
+        }
       }
     } else {
       // work item: consecutive items share a split (S range), so the
@@ -124,7 +138,8 @@ struct TileIter {
       const int64_t t = split * p.tps + step;
       ++step;
       if (step > p.tps || t >= p.nTS) return false;
-      tj = t;
+      ti = uniform64(ti);
+      tj = uniform64(t);
       return true;
     }
   }
@@ -138,16 +153,18 @@ struct TileIter {
 // (l%8) ^ ((row >> 1) & 7) of that row.
 __device__ inline void issue_loads(const CandParams& p, int64_t ti, int64_t tj, int chunk, uint8_t* la, uint8_t* lb) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t koff = (int64_t)chunk * kChunkBytes;
+  // wave-uniform tile bases (scalar registers) + a 32-bit in-tile offset per
+  // lane and t: few live registers, nothing worth hoisting across steps
+  const uint8_t* ga0 = p.qa + (ti * kTile) * p.qld + (int64_t)chunk * kChunkBytes;
+  const uint8_t* gb0 = p.qb + (tj * kTile) * p.qld + (int64_t)chunk * kChunkBytes;
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     const int q = wave * 4 + t;
     const int row = q * 8 + (lane >> 3);
     const int c = (lane & 7) ^ ((row >> 1) & 7);
-    const uint8_t* ga = p.qa + (ti * kTile + row) * p.qld + koff + c * 16;
-    const uint8_t* gb = p.qb + (tj * kTile + row) * p.qld + koff + c * 16;
-    lds_dma16(ga, la + q * 8 * kChunkBytes);
-    lds_dma16(gb, lb + q * 8 * kChunkBytes);
+    const uint32_t off = (uint32_t)row * (uint32_t)p.qld + (uint32_t)(c * 16);
+    lds_dma16(ga0 + off, la + q * 8 * kChunkBytes);
+    lds_dma16(gb0 + off, lb + q * 8 * kChunkBytes);
   }
 }
 
@@ -310,12 +327,14 @@ constexpr int kSelPerLane = 8;  // entries per lane in the k-selection subset
 // 64 * kSelPerLane entries: the k-th largest of a subset is at most the k-th
 // largest of the whole buffer, so the band stays a superset of the exact
 // one, and the selection runs on registers only.
-__device__ __attribute__((noinline)) void compact_row(const CandParams& p, uint2* e, int n, float marg,
-                                                      float* bthr, int* bcnt) {
+// Scalar arguments only (a reference to the kernel's parameter block would
+// force the block into scratch memory).
+__device__ inline void compact_row(uint2* e, int n, float marg, float* bthr, int* bcnt, int k,
+                                                      int cap, int* overflow) {
   const int lane = threadIdx.x & 63;
   float thr = *bthr;
   const int m = min(n, 64 * kSelPerLane);
-  if (m >= p.k) {
+  if (m >= k) {
     uint32_t key[kSelPerLane];
 #pragma unroll
     for (int t = 0; t < kSelPerLane; ++t) {
@@ -330,7 +349,7 @@ __device__ __attribute__((noinline)) void compact_row(const CandParams& p, uint2
       for (int t = 0; t < kSelPerLane; ++t) c += key[t] >= cand;
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
-      if (c >= p.k) kk = cand;
+      if (c >= k) kk = cand;
     }
     thr = fmaxf(thr, f32_down((double)key_float(kk) - (double)marg));
   }
@@ -351,67 +370,60 @@ __device__ __attribute__((noinline)) void compact_row(const CandParams& p, uint2
   if (lane == 0) {
     *bthr = thr;
     *bcnt = w;
-    if (w > p.cap - kTile) atomicOr(p.overflow, 1);
+    if (w > cap - kTile) atomicOr(overflow, 1);
   }
 }
 
-// Band epilogue: a row-maximum test against the row's band threshold; only
-// a wave with a hit walks its outputs.  An append that takes a row's buffer
-// past cap - 256 queues the row in lds_list for tightening at the next
-// barrier (the buffer still has room for one more tile).
-__device__ inline void epilogue_band(const CandParams& p, int64_t ti, int64_t tj, int64_t split,
+// Band epilogue.  For each of the wave's 32 (row block, row) slots the row
+// maximum over the four column blocks is tested against the row's band
+// threshold; only a slot with a hit walks its four outputs.  Hits of one row
+// are appended with one LDS atomic per 16-lane row group; an append that
+// takes a row's buffer past cap - 256 queues the row for tightening (the
+// buffer still has room for one more tile).
+__device__ inline void epilogue_band(const CandParams& p, int64_t ti, int64_t tj, int64_t split, bool full,
                                      const f32x4 (&acc)[8][4], const float* lds_thr, int* lds_cnt, int* lds_list) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave >> 2, wn = wave & 3;
   const int lrow0 = wm * kWaveM + 4 * (lane >> 4);
-  const int64_t row0 = ti * kTile + lrow0;
-  const int64_t col0 = tj * kTile + wn * kWaveN + (lane & 15);
-  float4 th[8];
-  bool any = false;
-#pragma unroll
-  for (int mb = 0; mb < 8; ++mb) {
-    th[mb] = *reinterpret_cast<const float4*>(lds_thr + lrow0 + mb * 16);
-    float m[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-      m[r] = fmaxf(fmaxf(acc[mb][0][r], acc[mb][1][r]), fmaxf(acc[mb][2][r], acc[mb][3][r]));
-    any |= (m[0] >= th[mb].x) | (m[1] >= th[mb].y) | (m[2] >= th[mb].z) | (m[3] >= th[mb].w);
-  }
-  if (!__any(any)) return;
+  const uint32_t row0 = (uint32_t)(ti * kTile + lrow0);
+  const uint32_t col0 = (uint32_t)(tj * kTile + wn * kWaveN + (lane & 15));
   const int limit = p.cap - kTile;
   const uint64_t lt = __lanemask_lt();
-  // lanes 16g..16g+15 hold the 16 columns of one row per (mb, r)
-  const uint64_t gmask = 0xffffull << (lane & 48);
-  const bool full = (ti + 1) * kTile <= p.nR && (tj + 1) * kTile <= p.nS && !(p.exclude_self && ti == tj);
+  const uint64_t gmask = 0xffffull << (lane & 48);  // the 16 lanes sharing this lane's row
 #pragma unroll
   for (int mb = 0; mb < 8; ++mb) {
-    const float tv[4] = {th[mb].x, th[mb].y, th[mb].z, th[mb].w};
+    const float4 th = *reinterpret_cast<const float4*>(lds_thr + lrow0 + mb * 16);
+    const float tv[4] = {th.x, th.y, th.z, th.w};
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb) {
+    for (int r = 0; r < 4; ++r) {
+      const float mx = fmaxf(fmaxf(acc[mb][0][r], acc[mb][1][r]), fmaxf(acc[mb][2][r], acc[mb][3][r]));
+      if (!__ballot(mx >= tv[r])) continue;
+      const int lr = lrow0 + mb * 16 + r;
+      const uint32_t i = row0 + mb * 16 + r;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t i = row0 + mb * 16 + r, j = col0 + nb * 16;
+      for (int nb = 0; nb < 4; ++nb) {
+        const uint32_t j = col0 + nb * 16;
         bool hit = acc[mb][nb][r] >= tv[r];
-        if (!full) hit = hit && i < p.nR && j < p.nS && !(p.exclude_self && i == j);
+        if (!full) hit = hit && i < (uint64_t)p.nR && j < (uint64_t)p.nS && !(p.exclude_self && i == j);
         const uint64_t m = __ballot(hit);
-        if (m) {
-          // one LDS atomic per row group, taken by its lowest hitting lane
-          const uint64_t gm = m & gmask;
-          const int lr = lrow0 + mb * 16 + r;
-          const int first = gm ? __ffsll((unsigned long long)gm) - 1 : 0;
-          int base = 0;
-          if (hit && lane == first) {
-            const int cnt = __popcll(gm);
-            base = atomicAdd(&lds_cnt[lr], cnt);
-            if (base <= limit && limit < base + cnt) lds_list[1 + atomicAdd(&lds_list[0], 1)] = lr;
-          }
-          base = __shfl(base, first, 64);
-          if (hit) {
-            const int pos = base + __popcll(gm & lt);
-            if (pos < p.cap)
-              p.band[((i * p.P) + split) * (int64_t)p.cap + pos] =
-                  make_uint2(__float_as_uint(acc[mb][nb][r]), (uint32_t)j);
-          }
+        if (!m) continue;
+        const uint64_t gm = m & gmask;
+        const int first = gm ? __ffsll((unsigned long long)gm) - 1 : 0;
+        int base = 0;
+        if (hit && lane == first) {
+          const int cnt = __popcll(gm);
+          base = atomicAdd(&lds_cnt[lr], cnt);
+          if (base <= limit && limit < base + cnt) lds_list[1 + atomicAdd(&lds_list[0], 1)] = lr;
+        }
+        base = __shfl(base, first, 64);
+        if (hit) {
+          const int pos = base + __popcll(gm & lt);
+          // the row's buffer address is formed here: hoisted out of the
+          // tile loop for all 32 row slots it would be spilled to scratch
+          uint32_t ii = i;
+          asm volatile("" : "+v"(ii));
+          if (pos < p.cap)
+            p.band[((int64_t)ii * p.P + split) * (int64_t)p.cap + pos] = make_uint2(__float_as_uint(acc[mb][nb][r]), j);
         }
       }
     }
@@ -419,7 +431,9 @@ __device__ inline void epilogue_band(const CandParams& p, int64_t ti, int64_t tj
 }
 
 // Rows queued by the band epilogue are tightened by one wave each; called by
-// the whole workgroup right after a barrier, so lds_list[0] is uniform.
+// the whole workgroup right after a barrier, so lds_list[0] is uniform, and
+// only at the first K-chunk of a tile, where the accumulators are dead (the
+// queued rows are still tightened before the next epilogue appends).
 __device__ inline void tighten_rows(const CandParams& p, int64_t ti, int64_t split, float* lds_thr, int* lds_cnt,
                                     int* lds_list) {
   const int nq = lds_list[0];
@@ -429,7 +443,8 @@ __device__ inline void tighten_rows(const CandParams& p, int64_t ti, int64_t spl
     const int lr = lds_list[1 + q];
     const int64_t i = ti * kTile + lr;
     const int n = min(lds_cnt[lr], p.cap);
-    compact_row(p, p.band + ((i * p.P) + split) * (int64_t)p.cap, n, p.marg[i], &lds_thr[lr], &lds_cnt[lr]);
+    compact_row(p.band + ((i * p.P) + split) * (int64_t)p.cap, n, p.marg[i], &lds_thr[lr], &lds_cnt[lr], p.k, p.cap,
+                p.overflow);
   }
   __syncthreads();
   if (threadIdx.x == 0) lds_list[0] = 0;
@@ -454,7 +469,7 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
   if constexpr (kMode == kModeBand) {
     const int64_t nb = gridDim.x;
     const int64_t w = (int64_t)(blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
-    split = w / p.nTR;
+    split = uniform64(w / p.nTR);
     for (int r = threadIdx.x; r < kTile; r += kThreads) {
       lds_thr[r] = -INFINITY;
       lds_cnt[r] = 0;
@@ -462,6 +477,7 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
     if (threadIdx.x == 0) lds_list[0] = 0;
   }
   int chunk = 0, stage = 0;
+  bool full = true;  // band mode: the tile needs no bounds or self checks
   issue_loads(p, ti, tj, 0, lds_ab[0][0], lds_ab[0][1]);
   f32x4 acc[8][4];
   int sa[8], sb[4];
@@ -479,8 +495,11 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
     // step before arriving), so the next step's loads may overwrite it.
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if constexpr (kMode == kModeBand) tighten_rows(p, ti, split, lds_thr, lds_cnt, lds_list);
     if (chunk == 0) {
+      if constexpr (kMode == kModeBand) {
+        tighten_rows(p, ti, split, lds_thr, lds_cnt, lds_list);
+        full = (ti + 1) * kTile <= p.nR && (tj + 1) * kTile <= p.nS && !(p.exclude_self && ti == tj);
+      }
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb) {
         const int64_t j = tj * kTile + wn * kWaveN + nb * 16 + (lane & 15);
@@ -501,7 +520,7 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
     mma_chunk<kPrec>(acc, lds_ab[stage][0], lds_ab[stage][1], wm * kWaveM, wn * kWaveN, sa, sb);
     if (chunk == p.nchunks - 1) {
       if constexpr (kMode == kModeEps) epilogue_eps(p, ti, tj, acc);
-      else epilogue_band(p, ti, tj, split, acc, lds_thr, lds_cnt, lds_list);
+      else epilogue_band(p, ti, tj, split, full, acc, lds_thr, lds_cnt, lds_list);
     }
     if (!more) break;
     ti = nti;

@@ -120,9 +120,13 @@ __global__ void stats_init_kernel(RelStats* rs) {
   }
 }
 
-// Maxima / minima over the real rows.  Non-negative floats order like their
-// bit patterns, so integer atomics suffice.
+// Maxima / minima over the real rows: a grid-stride pass, a wave and then a
+// workgroup reduction through LDS, and one atomic per field per workgroup.
+// Non-negative floats order like their bit patterns, so integer atomics
+// suffice.
 __global__ __launch_bounds__(256) void stats_reduce_kernel(Prep P, int64_t n, RelStats* rs) {
+  __shared__ float lf[5][4];
+  __shared__ int li[3][4];
   float hm = 0, qm = 0, rm = 0, dm = 0, xm = 0;
   int ql = kLsbNone, hl = kLsbNone, ml = kLsbNone;
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
@@ -137,15 +141,22 @@ __global__ __launch_bounds__(256) void stats_reduce_kernel(Prep P, int64_t n, Re
   }
   hm = wave_max(hm); qm = wave_max(qm); rm = wave_max(rm); dm = wave_max(dm); xm = wave_max(xm);
   ql = wave_min(ql); hl = wave_min(hl); ml = wave_min(ml);
+  const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
-    atomicMax(reinterpret_cast<unsigned*>(&rs->h_max), __float_as_uint(hm));
-    atomicMax(reinterpret_cast<unsigned*>(&rs->qnorm_max), __float_as_uint(qm));
-    atomicMax(reinterpret_cast<unsigned*>(&rs->rho_max), __float_as_uint(rm));
-    atomicMax(reinterpret_cast<unsigned*>(&rs->dh_max), __float_as_uint(dm));
-    atomicMax(reinterpret_cast<unsigned*>(&rs->xnorm_max), __float_as_uint(xm));
-    atomicMin(&rs->qlsb_min, ql);
-    atomicMin(&rs->hlsb_min, hl);
-    atomicMin(&rs->mlsb_min, ml);
+    lf[0][w] = hm; lf[1][w] = qm; lf[2][w] = rm; lf[3][w] = dm; lf[4][w] = xm;
+    li[0][w] = ql; li[1][w] = hl; li[2][w] = ml;
+  }
+  __syncthreads();
+  if (threadIdx.x < 5) {
+    const int f = threadIdx.x;
+    const float v = fmaxf(fmaxf(lf[f][0], lf[f][1]), fmaxf(lf[f][2], lf[f][3]));
+    float* dst = f == 0 ? &rs->h_max : f == 1 ? &rs->qnorm_max : f == 2 ? &rs->rho_max : f == 3 ? &rs->dh_max
+                                                                                                : &rs->xnorm_max;
+    atomicMax(reinterpret_cast<unsigned*>(dst), __float_as_uint(v));
+  } else if (threadIdx.x < 8) {
+    const int f = threadIdx.x - 5;
+    const int v = min(min(li[f][0], li[f][1]), min(li[f][2], li[f][3]));
+    atomicMin(f == 0 ? &rs->qlsb_min : f == 1 ? &rs->hlsb_min : &rs->mlsb_min, v);
   }
 }
 
@@ -207,8 +218,8 @@ hipError_t launch_prep(const float* X, int64_t n, int32_t d, int64_t ld, dl_prec
     case DL_FP8: hipLaunchKernelGGL(prep_kernel<DL_FP8>, grid, block, 0, st, X, n, d, ld, dpad, P, rs); break;
   }
   if (n > 0) {
-    int64_t blocks = (n + 255) / 256;
-    if (blocks > (int64_t)cu_count * 4) blocks = (int64_t)cu_count * 4;
+    int64_t blocks = (n + 1023) / 1024;
+    if (blocks > (int64_t)cu_count) blocks = (int64_t)cu_count;
     hipLaunchKernelGGL(stats_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, st, P, n, rs);
   }
   return hipGetLastError();

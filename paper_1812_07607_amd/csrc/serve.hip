@@ -108,8 +108,10 @@ struct Batch {
   int mode = DL_MODE_EPS, k = 0;
   std::vector<Req*> reqs;
   int64_t rows = 0;
-  size_t off = 0, bytes = 0;  // arena block
-  int live = 0;               // requests not yet released
+  size_t work_off = 0, work_bytes = 0;  // freed when the batch finishes
+  size_t out_off = 0, out_bytes = 0;    // freed when every request is released
+  bool work_held = false;
+  int live = 0;                         // requests not yet released
 };
 
 // Device helpers for one eps batch: start of each request's pairs in the
@@ -157,7 +159,7 @@ struct dl_server {
   std::map<uint64_t, Req*> reqs;
   std::vector<std::thread> workers;
   bool stopping = false;
-  int busy = 0;  // batches holding arena memory or running
+  int busy = 0;  // batches running (holding a work block)
   uint64_t next_ticket = 1;
   int64_t next_batch = 1;
 
@@ -173,21 +175,53 @@ namespace {
 
 int64_t rows_of(const Req* r) { return r->rq.query.n; }
 
-// Bytes a batch needs: packed query rows, per-row thresholds (eps), the
-// join's workspace and its outputs.
-size_t batch_bytes(dl_server* S, int mode, int k, int64_t rows, int nreq, int64_t pair_cap, int64_t cand_cap) {
+// Layout of one batch's two arena blocks.  The work block holds the packed
+// query rows, request row offsets and output starts, per-row thresholds
+// (eps) and the join's workspace; the output block holds the results.  The
+// same carving sizes the blocks (null bases) and lays them out, so a batch
+// never writes past its blocks.
+struct BatchLayout {
+  float* R = nullptr;
+  int64_t* row_off = nullptr;
+  int64_t* starts = nullptr;
+  double* Trow = nullptr;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  uint32_t *oi = nullptr, *oj = nullptr;
+  float* od = nullptr;
+  int64_t pair_cap = 0;
+  size_t work_bytes = 0, out_bytes = 0;
+};
+
+void caps_for(dl_server* S, int64_t rows, int64_t* pair_cap, int64_t* cand_cap);
+
+BatchLayout carve_batch(dl_server* S, void* work, void* outb, int mode, int k, int64_t rows, int nreq) {
   const dl_store* st = S->store;
   const int d = st->base.d;
-  size_t b = (size_t)round_up(rows * (int64_t)d * 4, 256) + (size_t)round_up((nreq + 1) * 8 * 2, 256);
+  BatchLayout L;
+  Bump b(work), o(outb);
+  L.R = b.take<float>(rows * (int64_t)d);
+  L.row_off = b.take<int64_t>((int64_t)nreq + 1);
+  L.starts = b.take<int64_t>((int64_t)nreq + 1);
   if (mode == DL_MODE_EPS) {
-    b += (size_t)round_up(rows * 8, 256);
-    b += eps_workspace(rows, st->base.n, d, st->prec, false, true, cand_cap);
-    b += (size_t)round_up(pair_cap * 4, 256) * 3;
+    int64_t pc, cc;
+    caps_for(S, rows, &pc, &cc);
+    L.pair_cap = pc;
+    L.Trow = b.take<double>(rows);
+    L.ws_bytes = eps_workspace(rows, st->base.n, d, st->prec, false, true, cc);
+    L.ws = b.take<uint8_t>((int64_t)L.ws_bytes);
+    L.oi = o.take<uint32_t>(pc);
+    L.oj = o.take<uint32_t>(pc);
+    L.od = o.take<float>(pc);
   } else {
-    b += topk_workspace(rows, st->base.n, d, st->prec, false, true, k, S->cfg.band_cap, S->cu);
-    b += (size_t)round_up(rows * (int64_t)k * 4, 256) * 2;
+    L.ws_bytes = topk_workspace(rows, st->base.n, d, st->prec, false, true, k, S->cfg.band_cap, S->cu);
+    L.ws = b.take<uint8_t>((int64_t)L.ws_bytes);
+    L.oj = o.take<uint32_t>(rows * (int64_t)k);
+    L.od = o.take<float>(rows * (int64_t)k);
   }
-  return b;
+  L.work_bytes = (size_t)round_up((int64_t)b.off, 256);
+  L.out_bytes = (size_t)round_up((int64_t)o.off, 256);
+  return L;
 }
 
 void caps_for(dl_server* S, int64_t rows, int64_t* pair_cap, int64_t* cand_cap) {
@@ -226,19 +260,25 @@ std::shared_ptr<Batch> take_batch(dl_server* S) {
     }
     // shrink until the arena has room
     for (;;) {
-      int64_t pc, cc;
-      caps_for(S, rows, &pc, &cc);
-      const size_t need = batch_bytes(S, mode, k, rows, (int)pick.size(), pc, cc);
-      size_t off;
-      if (S->alloc.alloc(need, &off)) {
+      const BatchLayout need = carve_batch(S, nullptr, nullptr, mode, k, rows, (int)pick.size());
+      size_t woff = 0, ooff = 0;
+      bool ok = S->alloc.alloc(need.work_bytes, &woff);
+      if (ok && !S->alloc.alloc(need.out_bytes, &ooff)) {
+        S->alloc.release(woff, need.work_bytes);
+        ok = false;
+      }
+      if (ok) {
         auto b = std::make_shared<Batch>();
         b->id = S->next_batch++;
         b->mode = mode;
         b->k = k;
         b->reqs = pick;
         b->rows = rows;
-        b->off = off;
-        b->bytes = need;
+        b->work_off = woff;
+        b->work_bytes = need.work_bytes;
+        b->out_off = ooff;
+        b->out_bytes = need.out_bytes;
+        b->work_held = true;
         b->live = (int)pick.size();
         for (Req* r : pick) {
           S->queue.erase(std::find(S->queue.begin(), S->queue.end(), r));
@@ -252,8 +292,10 @@ std::shared_ptr<Batch> take_batch(dl_server* S) {
         pick.pop_back();
         continue;
       }
-      if (S->busy == 0 && need > S->alloc.size() - S->alloc.used()) {
-        // cannot fit even in an otherwise empty arena: reject
+      // a request that could not fit even an empty arena is rejected; one
+      // that could waits for running batches and released results
+      if (round_up((int64_t)need.work_bytes, 256) + round_up((int64_t)need.out_bytes, 256) >
+          (int64_t)S->alloc.size()) {
         S->queue.pop_front();
         ++S->rejected;
         finish(S, head, DL_ERR_OOM, now_ms());
@@ -270,72 +312,57 @@ std::shared_ptr<Batch> take_batch(dl_server* S) {
 dl_status run_batch(dl_server* S, dl_ctx* ctx, hipStream_t st, Batch& b, std::string* err) {
   const dl_store* store = S->store;
   const int d = store->base.d;
-  uint8_t* base = S->arena + b.off;
-  Bump bump(base);
-  float* R = bump.take<float>(b.rows * (int64_t)d);
-  int64_t* row_off = bump.take<int64_t>((int64_t)b.reqs.size() + 1);
-  int64_t* starts = bump.take<int64_t>((int64_t)b.reqs.size() + 1);
-  std::vector<int64_t> hoff(b.reqs.size() + 1, 0);
-  for (size_t q = 0; q < b.reqs.size(); ++q) {
+  const int nreq = (int)b.reqs.size();
+  BatchLayout L = carve_batch(S, S->arena + b.work_off, S->arena + b.out_off, b.mode, b.k, b.rows, nreq);
+  if (L.work_bytes > b.work_bytes || L.out_bytes > b.out_bytes)
+    return *err = "batch layout exceeds its blocks", DL_ERR_OOM;
+  std::vector<int64_t> hoff(nreq + 1, 0);
+  for (int q = 0; q < nreq; ++q) {
     const dl_mat& m = b.reqs[q]->rq.query;
     hoff[q + 1] = hoff[q] + m.n;
     b.reqs[q]->row_off = hoff[q];
-    if (m.n > 0 && hipMemcpy2DAsync(R + hoff[q] * d, (size_t)d * 4, m.data, (size_t)m.ld * 4, (size_t)d * 4,
+    if (m.n > 0 && hipMemcpy2DAsync(L.R + hoff[q] * d, (size_t)d * 4, m.data, (size_t)m.ld * 4, (size_t)d * 4,
                                     (size_t)m.n, hipMemcpyDeviceToDevice, st) != hipSuccess)
       return *err = "query copy failed", DL_ERR_DEVICE;
   }
-  if (hipMemcpyAsync(row_off, hoff.data(), hoff.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess)
+  if (hipMemcpyAsync(L.row_off, hoff.data(), hoff.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess)
     return *err = "offset copy failed", DL_ERR_DEVICE;
-  const dl_mat Rm{R, b.rows, d, d};
+  const dl_mat Rm{L.R, b.rows, d, d};
   if (b.mode == DL_MODE_TOPK) {
     const int k = b.k;
-    const size_t ws_bytes =
-        topk_workspace(b.rows, store->base.n, d, store->prec, false, true, k, S->cfg.band_cap, S->cu);
-    void* ws = bump.take<uint8_t>((int64_t)ws_bytes);
-    uint32_t* oj = bump.take<uint32_t>(b.rows * k);
-    float* od = bump.take<float>(b.rows * k);
     TopkJob J{Rm, store->base, false, false, store->prec, &store->prep, store->stats, k, S->cfg.band_cap};
-    dl_status s = topk_core(ctx, J, ws, ws_bytes, oj, od, nullptr, st);
+    dl_status s = topk_core(ctx, J, L.ws, L.ws_bytes, L.oj, L.od, nullptr, st);
     if (s != DL_OK) return *err = dl_last_error(ctx), s;
     for (Req* r : b.reqs) {
-      r->oj = oj + r->row_off * k;
-      r->od = od + r->row_off * k;
+      r->oj = L.oj + r->row_off * k;
+      r->od = L.od + r->row_off * k;
       r->count = rows_of(r) * k;
     }
     return DL_OK;
   }
   // eps: one threshold per packed row
-  int64_t pc, cc;
-  caps_for(S, b.rows, &pc, &cc);
-  double* Trow = bump.take<double>(b.rows);
   std::vector<double> hT((size_t)b.rows);
   for (Req* r : b.reqs) std::fill_n(hT.begin() + r->row_off, rows_of(r), eps_threshold(r->rq.eps));
-  if (b.rows && hipMemcpyAsync(Trow, hT.data(), hT.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess)
+  if (b.rows && hipMemcpyAsync(L.Trow, hT.data(), hT.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess)
     return *err = "threshold copy failed", DL_ERR_DEVICE;
-  const size_t ws_bytes = eps_workspace(b.rows, store->base.n, d, store->prec, false, true, cc);
-  void* ws = bump.take<uint8_t>((int64_t)ws_bytes);
-  uint32_t* oi = bump.take<uint32_t>(pc);
-  uint32_t* oj = bump.take<uint32_t>(pc);
-  float* od = bump.take<float>(pc);
-  dl_pairs P{oi, oj, od, pc, 0, 0, 0};
-  EpsJob J{Rm, store->base, false, store->prec, &store->prep, store->stats, 0.0, Trow};
-  dl_status s = eps_core(ctx, J, ws, ws_bytes, &P, st);
+  dl_pairs P{L.oi, L.oj, L.od, L.pair_cap, 0, 0, 0};
+  EpsJob J{Rm, store->base, false, store->prec, &store->prep, store->stats, 0.0, L.Trow};
+  dl_status s = eps_core(ctx, J, L.ws, L.ws_bytes, &P, st);
   if (s != DL_OK) return *err = dl_last_error(ctx), s;
-  const int nreq = (int)b.reqs.size();
-  hipLaunchKernelGGL(eps_demux_starts, dim3((nreq + 1 + 63) / 64), dim3(64), 0, st, oi, P.count, row_off, nreq,
-                     starts);
+  hipLaunchKernelGGL(eps_demux_starts, dim3((nreq + 1 + 63) / 64), dim3(64), 0, st, L.oi, P.count, L.row_off, nreq,
+                     L.starts);
   if (P.count > 0)
     hipLaunchKernelGGL(eps_demux_rows, dim3((unsigned)std::min<int64_t>((P.count + 255) / 256, 4096)), dim3(256), 0,
-                       st, oi, P.count, row_off, nreq);
+                       st, L.oi, P.count, L.row_off, nreq);
   std::vector<int64_t> hs(nreq + 1);
-  if (hipMemcpyAsync(hs.data(), starts, hs.size() * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+  if (hipMemcpyAsync(hs.data(), L.starts, hs.size() * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return *err = "demux failed", DL_ERR_DEVICE;
   for (int q = 0; q < nreq; ++q) {
     Req* r = b.reqs[q];
-    r->oi = oi + hs[q];
-    r->oj = oj + hs[q];
-    r->od = od + hs[q];
+    r->oi = L.oi + hs[q];
+    r->oj = L.oj + hs[q];
+    r->od = L.od + hs[q];
     r->count = hs[q + 1] - hs[q];
   }
   return DL_OK;
@@ -368,7 +395,12 @@ void worker_main(dl_server* S, int idx) {
     const double t1 = now_ms();
     lk.lock();
     for (Req* r : b->reqs) finish(S, r, s, t1);
+    // the workspace is free as soon as the batch is done; results stay
+    S->alloc.release(b->work_off, b->work_bytes);
+    b->work_held = false;
+    --S->busy;
     S->cv_done.notify_all();
+    S->cv_work.notify_all();
   }
   lk.unlock();
   (void)hipStreamDestroy(st);
@@ -381,8 +413,7 @@ void release_req(dl_server* S, Req* r) {
   std::shared_ptr<Batch> b = r->batch;
   r->batch.reset();
   if (b && --b->live == 0) {
-    S->alloc.release(b->off, b->bytes);
-    --S->busy;
+    S->alloc.release(b->out_off, b->out_bytes);
     S->cv_work.notify_all();
   }
 }

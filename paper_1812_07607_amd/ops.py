@@ -297,7 +297,7 @@ class _DeviceView:
     """Zero-copy view of library-owned device memory for torch.as_tensor."""
 
     def __init__(self, ptr, shape, typestr):
-        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": typestr, "data": (int(ptr or 0), True),
+        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": typestr, "data": (int(ptr or 0), False),
                                          "version": 2, "strides": None}
 
 

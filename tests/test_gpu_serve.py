@@ -15,6 +15,7 @@ from paper_1812_07607_amd._lib import DL_ERR_CANCELLED, DL_ERR_OOM, DL_OK, DLErr
 pytestmark = pytest.mark.gpu
 
 D = 64
+WAIT_MS = 60000  # a request not done within a minute fails the test instead of stalling it
 
 
 @pytest.fixture(scope="module")
@@ -37,9 +38,9 @@ def test_store_joins_match_oracle(orc, store_data, prec):
     assert_eps_equal(got, ref, D, "store eps/" + prec)
 
 
-def _requests(n, seed):
+def _requests(n, seed, max_rows=400):
     rng = np.random.default_rng(seed)
-    rows = np.clip(np.rint(np.exp(rng.uniform(0, np.log(400), size=n))), 1, 400).astype(int)
+    rows = np.clip(np.rint(np.exp(rng.uniform(0, np.log(max_rows), size=n))), 1, max_rows).astype(int)
     modes = np.where(rng.random(n) < 0.5, "eps", "topk")
     qs = [synth.gaussian_mixture_unit(int(r), D, 200, seed=505, stream=100 + t) for t, r in enumerate(rows)]
     return qs, modes
@@ -63,12 +64,12 @@ def test_results_alone_equal_results_in_mix(orc, store_data):
         alone = []
         for q, m in zip(qs, modes):
             t = srv.submit(dev(q), m, eps=eps, k=10)
-            alone.append(srv.wait(t))
+            alone.append(srv.wait(t, WAIT_MS))
         assert all(r["batch_requests"] == 1 for r in alone)
         # mix: everything at once
         tq = [dev(q) for q in qs]
         tickets = [srv.submit(q, m, eps=eps, k=10) for q, m in zip(tq, modes)]
-        mixed = [srv.wait(t) for t in tickets]
+        mixed = [srv.wait(t, WAIT_MS) for t in tickets]
         assert max(r["batch_requests"] for r in mixed) > 1, "nothing was batched"
         for a, b, m in zip(alone, mixed, modes):
             assert a["status"] == DL_OK and b["status"] == DL_OK
@@ -93,34 +94,34 @@ def test_results_alone_equal_results_in_mix(orc, store_data):
 def test_memory_admission_and_rejection(orc, store_data):
     S = store_data
     st = ops.Store(dev(S), "bf16")
-    qs, modes = _requests(24, seed=4)
+    qs, modes = _requests(24, seed=4, max_rows=64)
     # an arena that holds only a few small batches at a time
     srv = ops.Server(st, arena_bytes=48 << 20, n_streams=3, max_batch_requests=4)
     try:
         tickets = [srv.submit(dev(q), m, eps=0.3, k=10) for q, m in zip(qs, modes)]
-        res = [srv.wait(t) for t in tickets]
+        res = [srv.wait(t, WAIT_MS) for t in tickets]
         assert all(r["status"] == DL_OK for r in res)
         s = srv.stats()
         assert s["arena_peak"] <= 48 << 20
         # a request that cannot fit an empty arena is rejected, not hung
         big = dev(synth.gaussian_mixture_unit(60000, D, 200, seed=505, stream=5))
         t = srv.submit(big, "topk", k=10)
-        assert srv.wait(t)["status"] == DL_ERR_OOM
+        assert srv.wait(t, WAIT_MS)["status"] == DL_ERR_OOM
         # the server still works afterwards
         t = srv.submit(dev(qs[0]), modes[0], eps=0.3, k=10)
-        assert srv.wait(t)["status"] == DL_OK
+        assert srv.wait(t, WAIT_MS)["status"] == DL_OK
     finally:
         srv.close()
 
 
 def test_cancel_and_invalid(store_data):
     st = ops.Store(dev(store_data), "bf16")
-    srv = ops.Server(st, arena_bytes=1 << 28, n_streams=1, max_batch_requests=1)
+    srv = ops.Server(st, arena_bytes=1 << 30, n_streams=1, max_batch_requests=1)
     try:
         qs = [dev(synth.gaussian_mixture_unit(2000, D, 200, seed=505, stream=200 + t)) for t in range(6)]
         tickets = [srv.submit(q, "topk", k=10) for q in qs]
         cancelled = srv.cancel(tickets[-1])
-        res = [srv.wait(t) for t in tickets]
+        res = [srv.wait(t, WAIT_MS) for t in tickets]
         if cancelled:
             assert res[-1]["status"] == DL_ERR_CANCELLED
         assert all(r["status"] == DL_OK for r in res[:-1])
@@ -129,6 +130,6 @@ def test_cancel_and_invalid(store_data):
         with pytest.raises(DLError):
             srv.submit(dev(np.zeros((3, D), np.float32)), "topk", k=0)
         t = srv.submit(dev(np.zeros((0, D), np.float32)), "eps", eps=0.1)
-        assert srv.wait(t)["status"] == DL_OK
+        assert srv.wait(t, WAIT_MS)["status"] == DL_OK
     finally:
         srv.close()
