@@ -25,6 +25,9 @@
  *     the stream reaches the end of the call's work.
  *   - No call allocates device memory except where stated: scratch memory is
  *     the caller's `ws` buffer, sized by the matching *_workspace query.
+ *     Workspaces, store memory and server arenas must be 256-byte aligned
+ *     (DL_ERR_INVALID otherwise); every allocation of hipMalloc or of the
+ *     PyTorch caching allocator is.
  *   - Errors are status codes; dl_last_error() gives a message.  No C++
  *     exception crosses this boundary.  On error, output buffers may hold
  *     partial results.

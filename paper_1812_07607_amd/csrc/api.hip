@@ -385,6 +385,15 @@ static int band_cap_of(int32_t band_cap, int k) {
   return band_cap;
 }
 
+// Entries a row's band buffer grows by before it is tightened again: often
+// enough that the running threshold follows the k-th best seen so far
+// (fewer hits per tile), rarely enough that selection does not dominate.
+static int retight_of(int k, int band_cap) {
+  int x = 4 * k < 64 ? 64 : 4 * k;
+  if (x > band_cap - kTile) x = band_cap - kTile;
+  return x;
+}
+
 size_t eps_workspace(int64_t nR, int64_t nS, int d, dl_prec prec, bool self, bool s_ext, int64_t cap) {
   return layout_eps(nullptr, nR, nS, d, prec, self, cap, s_ext).bytes;
 }
@@ -402,6 +411,7 @@ dl_status eps_core(dl_ctx* c, const EpsJob& J, void* ws, size_t ws_bytes, dl_pai
   out->count = out->candidates = out->ties = 0;
   // candidate capacity from the workspace size
   const size_t fixed = layout_eps(nullptr, R.n, S.n, R.d, prec, self, 1, sx).bytes;
+  if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(c, DL_ERR_INVALID, "workspace is not 256-byte aligned");
   if (!ws || ws_bytes < fixed) {
     c->required_ws = layout_eps(nullptr, R.n, S.n, R.d, prec, self, 1 << 20, sx).bytes;
     return fail(c, DL_ERR_WORKSPACE, "workspace of %zu bytes below the minimum %zu", ws_bytes, fixed);
@@ -499,6 +509,7 @@ dl_status topk_core(dl_ctx* c, const TopkJob& J, void* ws, size_t ws_bytes, uint
   int64_t tps = 1;
   const int P = topk_splits(R.n, S.n, c->cu_count, &tps);
   const size_t need = layout_topk(nullptr, R.n, S.n, R.d, prec, self, P, band_cap, sx).bytes;
+  if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(c, DL_ERR_INVALID, "workspace is not 256-byte aligned");
   if (!ws || ws_bytes < need) {
     c->required_ws = need;
     return fail(c, DL_ERR_WORKSPACE, "workspace of %zu bytes below the %zu needed", ws_bytes, need);
@@ -539,6 +550,7 @@ dl_status topk_core(dl_ctx* c, const TopkJob& J, void* ws, size_t ws_bytes, uint
     p.P = P;
     p.k = k;
     p.cap = band_cap;
+    p.retight = retight_of(k, band_cap);
     p.marg = L.marg;
     p.band = L.band;
     p.bcount = L.bcount;
@@ -654,6 +666,7 @@ dl_status dl_store_create(dl_ctx* c, dl_mat base, dl_prec prec, void* mem, size_
   if ((s = check_mat(c, base, "base")) != DL_OK) return s;
   if (!prec_ok(prec)) return fail(c, DL_ERR_INVALID, "unknown precision %d", (int)prec);
   const size_t need = store_bytes(base.n, base.d, prec);
+  if (reinterpret_cast<uintptr_t>(mem) & 255) return fail(c, DL_ERR_INVALID, "store memory is not 256-byte aligned");
   if (!mem || bytes < need) {
     c->required_ws = need;
     return fail(c, DL_ERR_WORKSPACE, "store memory of %zu bytes below the %zu needed", bytes, need);

@@ -5,27 +5,28 @@
 // and the closest-image query q1 of section "Queries".  The nested loop is
 // recast as a tiled product G = A B^T of the two relations' operand copies:
 // each 256 x 256 tile of pairs accumulates P~ = a.b - |b|^2/2 (the
-// accumulator starts at -h_j) over K-chunks of 128 bytes on the matrix
+// accumulator starts at -h_j) over K-steps of 128 bytes on the matrix
 // cores, and the epilogue compares P~ with one per-row float:
 //   eps mode   P~ >= thr_i  (thr_i folds |a|^2, the threshold T and the
 //              rigorous margin E_i) -> append (i, j) to the candidate list;
 //   band mode  P~ >= band_i, a running top-k band per row kept in LDS ->
 //              append (P~, j) to the row's band buffer, tightening band_i
-//              to P~_(k) - E_i whenever the buffer fills.
+//              to (a lower bound of) P~_(k) - E_i every few dozen appends.
 // Candidates are a superset of the exact result; the recheck kernels decide
 // exactly.
 //
 // Layout: 512 threads = 8 waves in a 2 x 4 grid, each wave owns 128 x 64
 // outputs as 8 x 4 blocks of 16 x 16 (v_mfma_*_16x16x*), 32 f32x4
 // accumulators.  Operands move global -> LDS directly
-// (global_load_lds_dwordx4, no staging registers) into a two-stage ring of
-// 2 x 256 rows x 128 bytes per stage; the 16-byte slot of logical piece c of
-// row r is stored at c ^ ((r >> 1) & 7), which makes the 16-row fragment
-// reads conflict-free.  The loads of step s+1 are issued right after the
-// barrier that opens step s, so they overlap its MFMAs and epilogue, across
-// tile boundaries too.  Workgroups are persistent; tiles are ordered in
-// groups of GM row tiles and dealt to the 8 XCDs in contiguous runs so that
-// each XCD's L2 holds the row tiles of its group while S tiles stream past.
+// (global_load_lds_dwordx4, no staging registers) into a 128 KiB ring of
+// two stages of 256 rows x 128 bytes per operand.  The 16-byte piece c of row r is
+// stored at a slot c ^ f(r) that makes the 16-row fragment reads
+// conflict-free.  The loader runs kStages - 1 K-steps ahead of the matrix
+// cores, across tile boundaries too; per-tile side data (h_j, thresholds,
+// E4M3 scales) travels the same way, so the loop waits only on its own
+// transfer counts.  Workgroups are persistent; tiles are ordered in groups of
+// GM row tiles and dealt to the 8 XCDs in contiguous runs so that each XCD's
+// L2 holds the row tiles of its group while S tiles stream past.
 #include "join_params.hpp"
 
 namespace dl {
@@ -36,8 +37,25 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kThreads = 512;
-constexpr int kStageBytes = kTile * kChunkBytes;  // one operand, one K-chunk
-constexpr int kWaveM = 128, kWaveN = 64;          // outputs per wave
+constexpr int kWaveM = 128, kWaveN = 64;  // outputs per wave
+constexpr int kRingBytes = 128 * 1024;   // LDS operand ring, all stages
+
+// K-step geometry.  A K-step moves kCB bytes of each of the 256 A rows and
+// 256 B rows into one stage of the ring.  128-byte steps (two stages) are
+// used for every format: E4M3 needs them (the scaled matrix instruction has
+// K = 128), and for the others they measured faster than 64-byte steps with
+// four stages, whose extra barrier per 32 matrix instructions cost more than
+// the deeper prefetch saved.  The code below handles either geometry.
+template <int kPrec>
+struct Pipe {
+  static constexpr int kCB = 128;
+  static constexpr int kSlots = kCB / 16;                         // 16-byte pieces per row
+  static constexpr int kStageBytes = kTile * kCB;                 // one operand, one step
+  static constexpr int kStages = kRingBytes / (2 * kStageBytes);  // 2 or 4
+  static constexpr int kRowsPerDma = 1024 / kCB;                  // rows per 1 KiB transfer
+  static constexpr int kDmaPerOp = kTile / kRowsPerDma / (kThreads / 64);  // per wave, per operand
+  static constexpr int kPerStep = 2 * kDmaPerOp;                  // operand transfers per wave per step
+};
 
 typedef __attribute__((address_space(1))) void gvoid_t;
 typedef __attribute__((address_space(3))) void lvoid_t;
@@ -65,8 +83,14 @@ __device__ inline void lds_dma16(const void* gsrc, void* lds_dst) {
       : "memory");
 }
 
-// LDS byte offset of logical 16-byte piece c of tile row r.
-__device__ inline int lds_off(int r, int c) { return r * kChunkBytes + ((c ^ ((r >> 1) & 7)) << 4); }
+// LDS byte offset of logical 16-byte piece c of tile row r in a stage with
+// kCB bytes per row.  The piece is stored at slot c ^ f(r), which spreads the
+// 16 rows read by one 16-lane group over all 64 banks.
+template <int kCB>
+__device__ inline int lds_off(int r, int c) {
+  if constexpr (kCB == 128) return r * 128 + ((c ^ ((r >> 1) & 7)) << 4);
+  else return r * 64 + ((c ^ ((r >> 2) & 3)) << 4);
+}
 
 enum : int { kModeEps = 0, kModeBand = 1 };
 
@@ -74,7 +98,10 @@ enum : int { kModeEps = 0, kModeBand = 1 };
 
 // ------------------------------------------------------------- tile order
 // Logical index -> (ti, tj) for the eps mode (see file comment).  Returns
-// false for the skipped lower-triangle tiles of a self-join's diagonal groups.
+// false for the skipped lower-triangle tiles of a self-join's diagonal
+// groups.  (Measured: this closed form, whose divisions by block-uniform
+// values compile to scalar code, beats carrying (group, offset) forward
+// with vector-unit 32-bit divisions.)
 __device__ inline bool tile_of(const CandParams& p, int64_t L, int64_t& ti, int64_t& tj) {
   const int64_t GM = p.GM;
   if (!p.self_join) {
@@ -111,138 +138,195 @@ __device__ inline int64_t uniform64(int64_t v) {
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-// Block-uniform iterator over this workgroup's tiles.
+// This lane's index (0..63), recomputed from the lane-count instructions at
+// every use.  Lane-derived offsets formed from it are not hoisted out of the
+// persistent loop, where they would stay live beside the 128 accumulator
+// registers and be spilled.
+__device__ inline int fresh_lane() {
+  int l;
+  asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(l));
+  return l;
+}
+
+// Block-uniform iterator over this workgroup's tiles: eps mode walks
+// logical tiles slot, slot + G, ... (G workgroups; slot = the workgroup's
+// place in the XCD dealing); band mode walks the S tiles of one (row tile,
+// split) work item, fixed at the first call.
 struct TileIter {
-  int64_t step;  // eps: logical round; band: S tile within split
-  __device__ bool next(const CandParams& p, int mode, int64_t& ti, int64_t& tj) {
+  int64_t step = 0;                              // eps: logical round
+  int64_t ti = 0, split = 0, t = 0, t_end = 0;   // band
+  __device__ bool next(const CandParams& p, int mode, int64_t& oti, int64_t& otj) {
+    const int64_t G = gridDim.x;
+    const int64_t slot = (int64_t)(blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
     if (mode == kModeEps) {
-      const int64_t G = gridDim.x;
-      const int64_t slot = (int64_t)(blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
       for (;;) {
         const int64_t L = step * G + slot;
         ++step;
         if (L >= p.nlogical) return false;
-        if (tile_of(p, L, ti, tj)) {
-          ti = uniform64(ti);
-          tj = uniform64(tj);
+        int64_t ti_, tj_;
+        if (tile_of(p, L, ti_, tj_)) {
+          oti = uniform64(ti_);
+          otj = uniform64(tj_);
           return true;
         }
       }
     } else {
-      // work item: consecutive items share a split (S range), so the
-      // concurrently running items of one XCD read the same S tiles
-      const int64_t nb = gridDim.x;
-      const int64_t w = (int64_t)(blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
-      const int64_t split = w / p.nTR;
-      ti = w % p.nTR;
-      const int64_t t = split * p.tps + step;
-      ++step;
-      if (step > p.tps || t >= p.nTS) return false;
-      ti = uniform64(ti);
-      tj = uniform64(t);
+      if (t_end == 0) {
+        // consecutive items share a split (S range), so the concurrently
+        // running items of one XCD read the same S tiles
+        split = slot / p.nTR;
+        ti = slot % p.nTR;
+        t = split * p.tps;
+        t_end = min(t + p.tps, p.nTS);
+        if (t >= t_end) t_end = -1;  // no S tiles for this workgroup
+      }
+      if (t_end < 0 || t >= t_end) return false;
+      oti = uniform64(ti);
+      otj = uniform64(t);
+      ++t;
       return true;
     }
   }
 };
 
 // ----------------------------------------------------- operand movement
-// One K-chunk of both operand tiles, global -> LDS.  Each wave moves rows
-// [8q, 8q+8) for q = 4 * wave + t (t < 4) of each operand with one 1 KiB
-// global_load_lds_dwordx4: lane l fills LDS slot l of that block, i.e.
-// row 8q + l/8, physical piece l%8, so it fetches logical piece
-// (l%8) ^ ((row >> 1) & 7) of that row.
-__device__ inline void issue_loads(const CandParams& p, int64_t ti, int64_t tj, int chunk, uint8_t* la, uint8_t* lb) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  // wave-uniform tile bases (scalar registers) + a 32-bit in-tile offset per
-  // lane and t: few live registers, nothing worth hoisting across steps
-  const uint8_t* ga0 = p.qa + (ti * kTile) * p.qld + (int64_t)chunk * kChunkBytes;
-  const uint8_t* gb0 = p.qb + (tj * kTile) * p.qld + (int64_t)chunk * kChunkBytes;
+// One K-step of both operand tiles, global -> LDS.  Each wave moves blocks
+// q = kDmaPerOp * wave + t of each operand, kRowsPerDma rows per block, with
+// one 1 KiB global_load_lds_dwordx4: lane l fills LDS slot l of the block,
+// i.e. row q * kRowsPerDma + l / kSlots, physical piece l % kSlots, so it
+// fetches the logical piece that the swizzle puts there.
+template <int kPrec>
+__device__ inline void issue_loads(const CandParams& p, int64_t ti, int64_t tj, int step, uint8_t* la, uint8_t* lb) {
+  using Q = Pipe<kPrec>;
+  // wave-uniform tile bases and LDS destinations (scalar registers) + a
+  // 32-bit in-tile offset per lane and block, recomputed from an opaque lane
+  // index at every call: hoisted out of the loop, the offsets would stay
+  // live (and be spilled) beside the accumulators
+  const int lane = fresh_lane();
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint8_t* ga0 = p.qa + (ti * kTile) * p.qld + (int64_t)step * Q::kCB;
+  const uint8_t* gb0 = p.qb + (tj * kTile) * p.qld + (int64_t)step * Q::kCB;
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int q = wave * 4 + t;
-    const int row = q * 8 + (lane >> 3);
-    const int c = (lane & 7) ^ ((row >> 1) & 7);
+  for (int t = 0; t < Q::kDmaPerOp; ++t) {
+    const int q = wave * Q::kDmaPerOp + t;
+    const int row = q * Q::kRowsPerDma + lane / Q::kSlots;
+    const int phys = lane % Q::kSlots;
+    const int c = (lds_off<Q::kCB>(row, phys) - row * Q::kCB) >> 4;  // the swizzle is an involution
     const uint32_t off = (uint32_t)row * (uint32_t)p.qld + (uint32_t)(c * 16);
-    lds_dma16(ga0 + off, la + q * 8 * kChunkBytes);
-    lds_dma16(gb0 + off, lb + q * 8 * kChunkBytes);
+    lds_dma16(ga0 + off, la + q * 1024);
+    lds_dma16(gb0 + off, lb + q * 1024);
   }
 }
 
-// ------------------------------------------------------ one K-chunk of MMA
-// Every lane reads 16-byte pieces at (row = lane % 16, byte = group * 16)
-// with group = lane / 16.  A and B use the same (lane, slot) -> k mapping,
-// so the dot product is over all k of the chunk whatever order the matrix
-// core assigns to the slots.
+// Per-tile side data moved with the first K-step of a tile, one 1 KiB
+// transfer each (256 four-byte values): h_j of the S tile, the eps
+// thresholds of the R tile, the E4M3 row scales of both.  Keeping them in
+// LDS means the loop's only global reads are these transfers, ordered by
+// the kernel's own wait counts.
+struct SideRefs {
+  float* hb;
+  float* thr;
+  int* sa;
+  int* sb;
+};
+template <int kPrec, int kMode>
+__device__ inline void issue_side(const CandParams& p, int64_t ti, int64_t tj, const SideRefs& d) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int e = 4 * fresh_lane();
+  if (wave == 0) lds_dma16(p.hb + tj * kTile + e, d.hb);
+  if constexpr (kMode == kModeEps)
+    if (wave == 1) lds_dma16(p.thr + ti * kTile + e, d.thr);
+  if constexpr (kPrec == DL_FP8) {
+    if (wave == 2) lds_dma16(p.sexa + ti * kTile + e, d.sa);
+    if (wave == 3) lds_dma16(p.sexb + tj * kTile + e, d.sb);
+  }
+}
+
+// ------------------------------------------------------- one K-step of MMA
+// Every lane reads 16-byte pieces at (row = lane % 16, piece = lane / 16 +
+// 4 * sub-step).  A and B use the same (lane, slot) -> k mapping, so the dot
+// product is over all k of the step whatever order the matrix core assigns
+// to the slots.
+//
+// Fragment reads run ahead of the matrix instructions in a rolling window:
+// the first sub-step's B and A fragments are requested up front; the second
+// sub-step's A fragment mb (and B fragment nb) is requested right after the
+// instructions that consume the register it replaces.  The LDS latency is
+// then paid about once per step instead of once per pair of A fragments,
+// with 64 fragment registers beside the 128 accumulator registers.
 template <int kPrec>
-__device__ inline void mma_chunk(f32x4 (&acc)[8][4], const uint8_t* la, const uint8_t* lb, int ra0, int rb0,
-                                 const int (&sa)[8], const int (&sb)[4]) {
+__device__ inline void mma_step(f32x4 (&acc)[8][4], const uint8_t* la, const uint8_t* lb, int ra0, int rb0,
+                                const int (&sa)[8], const int (&sb)[4]) {
+  constexpr int kCB = Pipe<kPrec>::kCB;
   const int lane = threadIdx.x & 63;
   const int r16 = lane & 15, grp = lane >> 4;
-  if constexpr (kPrec == DL_BF16 || kPrec == DL_FP16) {
-#pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-      uint4 bq[4];
-#pragma unroll
-      for (int nb = 0; nb < 4; ++nb)
-        bq[nb] = *reinterpret_cast<const uint4*>(lb + lds_off(rb0 + nb * 16 + r16, ks * 4 + grp));
-#pragma unroll
-      for (int mb = 0; mb < 8; ++mb) {
-        const uint4 aq = *reinterpret_cast<const uint4*>(la + lds_off(ra0 + mb * 16 + r16, ks * 4 + grp));
-#pragma unroll
-        for (int nb = 0; nb < 4; ++nb) {
-          if constexpr (kPrec == DL_BF16)
-            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, aq),
-                                                                  __builtin_bit_cast(bf16x8, bq[nb]),
-                                                                  acc[mb][nb], 0, 0, 0);
-          else
-            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, aq),
-                                                                 __builtin_bit_cast(f16x8, bq[nb]),
-                                                                 acc[mb][nb], 0, 0, 0);
-        }
+  auto ldA = [&](int mb, int piece) {
+    return *reinterpret_cast<const uint4*>(la + lds_off<kCB>(ra0 + mb * 16 + r16, piece));
+  };
+  auto ldB = [&](int nb, int piece) {
+    return *reinterpret_cast<const uint4*>(lb + lds_off<kCB>(rb0 + nb * 16 + r16, piece));
+  };
+  if constexpr (kPrec == DL_BF16 || kPrec == DL_FP16 || kPrec == DL_FP32) {
+    static_assert(kCB == 128, "two sub-steps of 64 bytes");
+    // one block product: 16x16x32 for the 16-bit formats, four 16x16x4 for fp32
+    auto mac = [&](f32x4& c, const uint4& x, const uint4& y) {
+      if constexpr (kPrec == DL_BF16) {
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, x), __builtin_bit_cast(bf16x8, y),
+                                                    c, 0, 0, 0);
+      } else if constexpr (kPrec == DL_FP16) {
+        c = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, x), __builtin_bit_cast(f16x8, y), c,
+                                                   0, 0, 0);
+      } else {
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(x.x), __uint_as_float(y.x), c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(x.y), __uint_as_float(y.y), c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(x.z), __uint_as_float(y.z), c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(x.w), __uint_as_float(y.w), c, 0, 0, 0);
       }
-    }
-  } else if constexpr (kPrec == DL_FP8) {
-    // 16x16x128 E4M3 with per-row E8M0 scales; each lane reads 32 bytes
-    i32x8 bq[4];
+    };
+    constexpr int kPerBlock = kPrec == DL_FP32 ? 4 : 1;  // matrix instructions per block product
+    uint4 a[8], b0[4], b1[4];
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb) {
-      const int r = rb0 + nb * 16 + r16;
-      const uint4 x0 = *reinterpret_cast<const uint4*>(lb + lds_off(r, 2 * grp));
-      const uint4 x1 = *reinterpret_cast<const uint4*>(lb + lds_off(r, 2 * grp + 1));
-      bq[nb] = i32x8{(int)x0.x, (int)x0.y, (int)x0.z, (int)x0.w, (int)x1.x, (int)x1.y, (int)x1.z, (int)x1.w};
+    for (int nb = 0; nb < 4; ++nb) b0[nb] = ldB(nb, grp);
+#pragma unroll
+    for (int mb = 0; mb < 8; ++mb) a[mb] = ldA(mb, grp);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int mb = 0; mb < 8; ++mb) {
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) mac(acc[mb][nb], a[mb], b0[nb]);
+      a[mb] = ldA(mb, 4 + grp);
+      if (mb < 4) b1[mb] = ldB(mb, 4 + grp);
+      __builtin_amdgcn_sched_group_barrier(0x008, 4 * kPerBlock, 0);  // matrix
+      if (mb < 4) __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);   // LDS reads
+      else __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
     }
 #pragma unroll
     for (int mb = 0; mb < 8; ++mb) {
-      const int r = ra0 + mb * 16 + r16;
-      const uint4 x0 = *reinterpret_cast<const uint4*>(la + lds_off(r, 2 * grp));
-      const uint4 x1 = *reinterpret_cast<const uint4*>(la + lds_off(r, 2 * grp + 1));
-      const i32x8 aq = {(int)x0.x, (int)x0.y, (int)x0.z, (int)x0.w, (int)x1.x, (int)x1.y, (int)x1.z, (int)x1.w};
 #pragma unroll
-      for (int nb = 0; nb < 4; ++nb)
-        acc[mb][nb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(aq, bq[nb], acc[mb][nb], 0, 0, 0, sa[mb], 0,
-                                                                      sb[nb]);
-      // keep at most two 32-byte A fragments live (register pressure)
-      if (mb & 1) __builtin_amdgcn_sched_barrier(0);
+      for (int nb = 0; nb < 4; ++nb) mac(acc[mb][nb], a[mb], b1[nb]);
     }
   } else {
-    // fp32: 16x16x4; a 16-byte read gives 4 k-steps
+    // E4M3, 128 bytes = 128 values per row: 16x16x128 with per-row E8M0
+    // scales; each lane reads 32 bytes per fragment; a window of four A
+    // fragments
+    auto ld8 = [&](const uint4& x0, const uint4& x1) {
+      return i32x8{(int)x0.x, (int)x0.y, (int)x0.z, (int)x0.w, (int)x1.x, (int)x1.y, (int)x1.z, (int)x1.w};
+    };
+    i32x8 b[4], a[4];
 #pragma unroll
-    for (int half = 0; half < 2; ++half) {
-      float4 bq[4];
+    for (int nb = 0; nb < 4; ++nb) b[nb] = ld8(ldB(nb, 2 * grp), ldB(nb, 2 * grp + 1));
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) a[mb] = ld8(ldA(mb, 2 * grp), ldA(mb, 2 * grp + 1));
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int mb = 0; mb < 8; ++mb) {
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb)
-        bq[nb] = *reinterpret_cast<const float4*>(lb + lds_off(rb0 + nb * 16 + r16, half * 4 + grp));
-#pragma unroll
-      for (int mb = 0; mb < 8; ++mb) {
-        const float4 aq = *reinterpret_cast<const float4*>(la + lds_off(ra0 + mb * 16 + r16, half * 4 + grp));
-#pragma unroll
-        for (int nb = 0; nb < 4; ++nb) {
-          acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(aq.x, bq[nb].x, acc[mb][nb], 0, 0, 0);
-          acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(aq.y, bq[nb].y, acc[mb][nb], 0, 0, 0);
-          acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(aq.z, bq[nb].z, acc[mb][nb], 0, 0, 0);
-          acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(aq.w, bq[nb].w, acc[mb][nb], 0, 0, 0);
-        }
-      }
+        acc[mb][nb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[mb & 3], b[nb], acc[mb][nb], 0, 0, 0,
+                                                                      sa[mb], 0, sb[nb]);
+      if (mb < 4) a[mb] = ld8(ldA(mb + 4, 2 * grp), ldA(mb + 4, 2 * grp + 1));
+      __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
+      if (mb < 4) __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
     }
   }
 }
@@ -250,66 +334,91 @@ __device__ inline void mma_chunk(f32x4 (&acc)[8][4], const uint8_t* la, const ui
 // -------------------------------------------------------------- epilogues
 // Output element (mb, nb, r) of a lane sits at tile row wm*128 + mb*16 +
 // 4*(lane/16) + r and tile column wn*64 + nb*16 + lane%16.
-__device__ inline void epilogue_eps(const CandParams& p, int64_t ti, int64_t tj, const f32x4 (&acc)[8][4]) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+constexpr int kQueue = 256;  // staged hits per wave (eps candidates or band entries)
+
+// Appends a wave's staged (i, j) candidates to the global list: one atomic
+// for the whole batch, then coalesced stores.  Positions past the list's
+// capacity are counted but not written (the caller then retries with room).
+__device__ inline void flush_eps(const CandParams& p, const uint2* q, int nq) {
+  const int lane = fresh_lane();
+  unsigned long long base = 0;
+  if (lane == 0) base = atomicAdd(p.ccount, (unsigned long long)nq);
+  base = ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(base >> 32)) << 32) |
+         __builtin_amdgcn_readfirstlane((uint32_t)base);
+  for (int s = lane; s < nq; s += 64) {
+    const unsigned long long pos = base + (unsigned long long)s;
+    if (pos < (unsigned long long)p.ccap) p.cand[pos] = q[s];
+  }
+}
+
+// Eps epilogue.  A fast test (each row's maximum over the wave's four
+// column blocks against the row threshold) lets most waves skip the tile.
+// Otherwise each (row block, row) slot with a hit forms its four hit masks
+// and stages its (i, j) in the wave's LDS queue (ballot prefix, no
+// atomics); the queue persists across tiles and goes to global memory only
+// when full and at the end.  Bounds (rows and columns left in the tile) and
+// the self-join's j > i (only on a diagonal tile) are checked in 32-bit
+// tile coordinates, and only on tiles that need them.  Returns whether this
+// wave wrote to global memory.
+__device__ inline bool epilogue_eps(const CandParams& p, int64_t ti, int64_t tj, const f32x4 (&acc)[8][4],
+                                    const float* thr_tile, uint2* q, int& nq) {
+  const int lane = fresh_lane(), wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wm = wave >> 2, wn = wave & 3;
-  const int64_t row0 = ti * kTile + wm * kWaveM + 4 * (lane >> 4);
-  const int64_t col0 = tj * kTile + wn * kWaveN + (lane & 15);
+  const int lrow0 = wm * kWaveM + 4 * (lane >> 4);
+  const int lcol0 = wn * kWaveN + (lane & 15);
   float4 th[8];
   bool any = false;
 #pragma unroll
   for (int mb = 0; mb < 8; ++mb) {
-    th[mb] = *reinterpret_cast<const float4*>(p.thr + row0 + mb * 16);
-    // row maxima over the 4 column blocks, then one compare per row
+    th[mb] = *reinterpret_cast<const float4*>(thr_tile + lrow0 + mb * 16);
     float m[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
       m[r] = fmaxf(fmaxf(acc[mb][0][r], acc[mb][1][r]), fmaxf(acc[mb][2][r], acc[mb][3][r]));
     any |= (m[0] >= th[mb].x) | (m[1] >= th[mb].y) | (m[2] >= th[mb].z) | (m[3] >= th[mb].w);
   }
-  if (!__any(any)) return;
-  // slow path: 128 hit bits per lane (bit (mb & 1) * 16 + nb * 4 + r of
-  // word mb / 2), one wave-wide atomic for the whole tile, then each lane
-  // writes its own hits.
-  uint32_t hm[4] = {0u, 0u, 0u, 0u};
+  if (!__any(any)) return false;
+  const int rrem = (int)min(p.nR - ti * kTile, (int64_t)kTile);
+  const int crem = (int)min(p.nS - tj * kTile, (int64_t)kTile);
+  const bool diag = p.self_join && ti == tj;
+  const bool full = rrem == kTile && crem == kTile && !diag;
+  const uint32_t i0 = (uint32_t)(ti * kTile), j0 = (uint32_t)(tj * kTile);
+  const uint64_t lt = __lanemask_lt();
+  bool wrote = false;
 #pragma unroll
   for (int mb = 0; mb < 8; ++mb) {
     const float tv[4] = {th[mb].x, th[mb].y, th[mb].z, th[mb].w};
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb) {
+    for (int r = 0; r < 4; ++r) {
+      const float mx = fmaxf(fmaxf(acc[mb][0][r], acc[mb][1][r]), fmaxf(acc[mb][2][r], acc[mb][3][r]));
+      if (!__ballot(mx >= tv[r])) continue;
+      const int lr = lrow0 + mb * 16 + r;
+      bool hit[4];
+      uint64_t m[4];
+      int tot = 0;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t i = row0 + mb * 16 + r, j = col0 + nb * 16;
-        const bool v = acc[mb][nb][r] >= tv[r] && i < p.nR && j < p.nS && (!p.self_join || j > i);
-        hm[mb >> 1] |= (uint32_t)v << ((mb & 1) * 16 + nb * 4 + r);
+      for (int nb = 0; nb < 4; ++nb) {
+        hit[nb] = acc[mb][nb][r] >= tv[r];
+        if (!full) {
+          const int lc = lcol0 + nb * 16;
+          hit[nb] = hit[nb] && lr < rrem && lc < crem && (!diag || lc > lr);
+        }
+        m[nb] = __ballot(hit[nb]);
+        tot += __popcll(m[nb]);
+      }
+      if (nq + tot > kQueue) {
+        flush_eps(p, q, nq);
+        nq = 0;
+        wrote = true;
+      }
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) {
+        if (hit[nb]) q[nq + __popcll(m[nb] & lt)] = make_uint2(i0 + (uint32_t)lr, j0 + (uint32_t)(lcol0 + nb * 16));
+        nq += __popcll(m[nb]);
       }
     }
   }
-  const uint32_t mine = __popc(hm[0]) + __popc(hm[1]) + __popc(hm[2]) + __popc(hm[3]);
-  uint32_t incl = mine;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(incl, o, 64);
-    if (lane >= o) incl += y;
-  }
-  const uint32_t total = __shfl(incl, 63, 64);
-  if (total == 0) return;
-  unsigned long long base = 0;
-  if (lane == 0) base = atomicAdd(p.ccount, (unsigned long long)total);
-  base = __shfl(base, 0, 64);
-  unsigned long long pos = base + incl - mine;
-#pragma unroll
-  for (int w = 0; w < 4; ++w) {
-    uint32_t bits = hm[w];
-    while (bits) {
-      const int b = __builtin_ctz(bits);
-      bits &= bits - 1;
-      const int mb = 2 * w + (b >> 4), nb = (b >> 2) & 3, r = b & 3;
-      if (pos < (unsigned long long)p.ccap)
-        p.cand[pos] = make_uint2((uint32_t)(row0 + mb * 16 + r), (uint32_t)(col0 + nb * 16));
-      ++pos;
-    }
-  }
+  return wrote;
 }
 
 __device__ inline uint32_t order_key(float f) {
@@ -321,224 +430,340 @@ __device__ inline float key_float(uint32_t k) {
 }
 
 constexpr int kSelPerLane = 8;  // entries per lane in the k-selection subset
+constexpr int kSelBits = 24;    // key bits resolved by the selection
 
 // Tighten one row's band and drop what falls below it (one wave).  The new
-// threshold is P~_(k) - E_i with P~_(k) the k-th largest value of the first
-// 64 * kSelPerLane entries: the k-th largest of a subset is at most the k-th
-// largest of the whole buffer, so the band stays a superset of the exact
-// one, and the selection runs on registers only.
+// threshold is v - E_i where v is a lower bound of the k-th largest P~ of
+// the first 64 * kSelPerLane entries (the k-th largest of a subset is at
+// most that of the whole buffer, so the band stays a superset of the exact
+// one): the largest key, resolved to its top kSelBits bits, with at least k
+// entries at or above it.  Counting uses ballots, so every step is scalar.
+// Returns the entries kept; the caller re-arms the row's trigger.
 // Scalar arguments only (a reference to the kernel's parameter block would
 // force the block into scratch memory).
-__device__ inline void compact_row(uint2* e, int n, float marg, float* bthr, int* bcnt, int k,
-                                                      int cap, int* overflow) {
+__device__ inline int compact_row(uint2* e, int n, float marg, float* bthr, int k) {
   const int lane = threadIdx.x & 63;
   float thr = *bthr;
   const int m = min(n, 64 * kSelPerLane);
+  uint2 v[kSelPerLane];
+#pragma unroll
+  for (int t = 0; t < kSelPerLane; ++t) {
+    const int s = t * 64 + lane;
+    v[t] = s < m ? e[s] : make_uint2(0xff800000u, 0);  // -inf sorts below everything kept
+  }
   if (m >= k) {
     uint32_t key[kSelPerLane];
 #pragma unroll
-    for (int t = 0; t < kSelPerLane; ++t) {
-      const int s = t * 64 + lane;
-      key[t] = s < m ? order_key(__uint_as_float(e[s].x)) : 0u;
-    }
-    uint32_t kk = 0;  // largest key with at least k entries >= it
-    for (int b = 31; b >= 0; --b) {
+    for (int t = 0; t < kSelPerLane; ++t) key[t] = (t * 64 + lane) < m ? order_key(__uint_as_float(v[t].x)) : 0u;
+    uint32_t kk = 0;  // largest prefix with at least k entries >= it
+    for (int b = 31; b >= 32 - kSelBits; --b) {
       const uint32_t cand = kk | (1u << b);
       int c = 0;
 #pragma unroll
-      for (int t = 0; t < kSelPerLane; ++t) c += key[t] >= cand;
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+      for (int t = 0; t < kSelPerLane; ++t) c += __popcll(__ballot(key[t] >= cand));
       if (c >= k) kk = cand;
     }
     thr = fmaxf(thr, f32_down((double)key_float(kk) - (double)marg));
   }
-  int w = 0;
   const uint64_t lt = __lanemask_lt();
-  for (int base = 0; base < n; base += 64) {
-    const int s = base + lane;
-    uint2 v = make_uint2(0, 0);
-    bool keep = false;
-    if (s < n) {
-      v = e[s];
-      keep = __uint_as_float(v.x) >= thr;
-    }
+  int w = 0;
+  // the first entries come from registers; later ones (a buffer larger than
+  // the subset) are read block by block before any write can reach them
+#pragma unroll
+  for (int t = 0; t < kSelPerLane; ++t) {
+    const bool keep = (t * 64 + lane) < m && __uint_as_float(v[t].x) >= thr;
     const uint64_t mm = __ballot(keep);
-    if (keep) e[w + __popcll(mm & lt)] = v;
+    if (keep) e[w + __popcll(mm & lt)] = v[t];
     w += __popcll(mm);
   }
-  if (lane == 0) {
-    *bthr = thr;
-    *bcnt = w;
-    if (w > cap - kTile) atomicOr(overflow, 1);
+  for (int base = m; base < n; base += 64) {
+    const int s = base + lane;
+    uint2 x = make_uint2(0, 0);
+    bool keep = false;
+    if (s < n) {
+      x = e[s];
+      keep = __uint_as_float(x.x) >= thr;
+    }
+    const uint64_t mm = __ballot(keep);
+    if (keep) e[w + __popcll(mm & lt)] = x;
+    w += __popcll(mm);
+  }
+  if (lane == 0) *bthr = thr;
+  return w;
+}
+
+// Per-workgroup band state in LDS: the threshold, entry count and re-tighten
+// trigger of each of the tile's rows, the queue of rows to tighten, and one
+// staging queue of hits per wave.
+struct BandLds {
+  float thr[kTile];
+  int cnt[kTile];
+  int trig[kTile];
+  int list[kTile + 1];
+  uint2 q[kThreads / 64][kQueue];  // (P~ bits, row << 8 | column in tile)
+};
+
+// Appends a wave's staged hits to their rows' band buffers: one LDS atomic
+// per hit for its slot (all 64 lanes at once), then a plain store.  A row
+// whose count passes its trigger is queued for tightening.
+__device__ inline void flush_band(const CandParams& p, int64_t ti, int64_t tj, int64_t split, BandLds& L,
+                                  const uint2* q, int nq) {
+  const int lane = threadIdx.x & 63;
+  for (int base = 0; base < nq; base += 64) {
+    const int s = base + lane;
+    if (s < nq) {
+      const uint2 h = q[s];
+      const int lr = (int)(h.y >> 8);
+      const int pos = atomicAdd(&L.cnt[lr], 1);
+      if (pos == L.trig[lr]) L.list[1 + atomicAdd(&L.list[0], 1)] = lr;
+      if (pos < p.cap) {
+        const int64_t i = ti * kTile + lr;
+        p.band[(i * p.P + split) * (int64_t)p.cap + pos] =
+            make_uint2(h.x, (uint32_t)(tj * kTile) + (h.y & 255u));
+      }
+    }
   }
 }
 
 // Band epilogue.  For each of the wave's 32 (row block, row) slots the row
 // maximum over the four column blocks is tested against the row's band
-// threshold; only a slot with a hit walks its four outputs.  Hits of one row
-// are appended with one LDS atomic per 16-lane row group; an append that
-// takes a row's buffer past cap - 256 queues the row for tightening (the
-// buffer still has room for one more tile).
-__device__ inline void epilogue_band(const CandParams& p, int64_t ti, int64_t tj, int64_t split, bool full,
-                                     const f32x4 (&acc)[8][4], const float* lds_thr, int* lds_cnt, int* lds_list) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+// threshold; only a slot with a hit forms its four hit masks and stages the
+// hits in the wave's LDS queue (ballot-prefixed, no atomics, no waits).
+// The queue is flushed when the next slot might not fit and at the end.
+// Returns whether this wave wrote to global memory.
+__device__ inline bool epilogue_band(const CandParams& p, int64_t ti, int64_t tj, int64_t split, bool full,
+                                     const f32x4 (&acc)[8][4], BandLds& L) {
+  const int lane = fresh_lane(), wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wm = wave >> 2, wn = wave & 3;
   const int lrow0 = wm * kWaveM + 4 * (lane >> 4);
-  const uint32_t row0 = (uint32_t)(ti * kTile + lrow0);
-  const uint32_t col0 = (uint32_t)(tj * kTile + wn * kWaveN + (lane & 15));
-  const int limit = p.cap - kTile;
+  const int lcol0 = wn * kWaveN + (lane & 15);
   const uint64_t lt = __lanemask_lt();
-  const uint64_t gmask = 0xffffull << (lane & 48);  // the 16 lanes sharing this lane's row
+  uint2* q = L.q[wave];
+  int nq = 0;
+  bool wrote = false;
+  // the hit tag (row << 8 | column) is formed from this opaque base: left
+  // visible, all 128 tags would be precomputed and kept across the tile loop
+  uint32_t tag0 = ((uint32_t)lrow0 << 8) | (uint32_t)lcol0;
+  asm volatile("" : "+v"(tag0));
 #pragma unroll
   for (int mb = 0; mb < 8; ++mb) {
-    const float4 th = *reinterpret_cast<const float4*>(lds_thr + lrow0 + mb * 16);
+    const float4 th = *reinterpret_cast<const float4*>(L.thr + lrow0 + mb * 16);
     const float tv[4] = {th.x, th.y, th.z, th.w};
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const float mx = fmaxf(fmaxf(acc[mb][0][r], acc[mb][1][r]), fmaxf(acc[mb][2][r], acc[mb][3][r]));
       if (!__ballot(mx >= tv[r])) continue;
       const int lr = lrow0 + mb * 16 + r;
-      const uint32_t i = row0 + mb * 16 + r;
+      bool hit[4];
+      uint64_t m[4];
+      int tot = 0;
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb) {
-        const uint32_t j = col0 + nb * 16;
-        bool hit = acc[mb][nb][r] >= tv[r];
-        if (!full) hit = hit && i < (uint64_t)p.nR && j < (uint64_t)p.nS && !(p.exclude_self && i == j);
-        const uint64_t m = __ballot(hit);
-        if (!m) continue;
-        const uint64_t gm = m & gmask;
-        const int first = gm ? __ffsll((unsigned long long)gm) - 1 : 0;
-        int base = 0;
-        if (hit && lane == first) {
-          const int cnt = __popcll(gm);
-          base = atomicAdd(&lds_cnt[lr], cnt);
-          if (base <= limit && limit < base + cnt) lds_list[1 + atomicAdd(&lds_list[0], 1)] = lr;
+        hit[nb] = acc[mb][nb][r] >= tv[r];
+        if (!full) {
+          // in-tile bounds: rows left in R and S (at most a tile) and the
+          // diagonal of a self tile, all in 32-bit
+          const int rrem = (int)min(p.nR - ti * kTile, (int64_t)kTile);
+          const int crem = (int)min(p.nS - tj * kTile, (int64_t)kTile);
+          const bool diag = p.exclude_self && ti == tj;
+          const int lc = lcol0 + nb * 16;
+          hit[nb] = hit[nb] && lr < rrem && lc < crem && !(diag && lr == lc);
         }
-        base = __shfl(base, first, 64);
-        if (hit) {
-          const int pos = base + __popcll(gm & lt);
-          // the row's buffer address is formed here: hoisted out of the
-          // tile loop for all 32 row slots it would be spilled to scratch
-          uint32_t ii = i;
-          asm volatile("" : "+v"(ii));
-          if (pos < p.cap)
-            p.band[((int64_t)ii * p.P + split) * (int64_t)p.cap + pos] = make_uint2(__float_as_uint(acc[mb][nb][r]), j);
-        }
+        m[nb] = __ballot(hit[nb]);
+        tot += __popcll(m[nb]);
+      }
+      if (nq + tot > kQueue) {
+        flush_band(p, ti, tj, split, L, q, nq);
+        nq = 0;
+        wrote = true;
+      }
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) {
+        if (hit[nb])
+          q[nq + __popcll(m[nb] & lt)] =
+              make_uint2(__float_as_uint(acc[mb][nb][r]), tag0 + (uint32_t)(((mb * 16 + r) << 8) + nb * 16));
+        nq += __popcll(m[nb]);
       }
     }
   }
+  if (nq) {
+    flush_band(p, ti, tj, split, L, q, nq);
+    wrote = true;
+  }
+  return wrote;
 }
 
-// Rows queued by the band epilogue are tightened by one wave each; called by
-// the whole workgroup right after a barrier, so lds_list[0] is uniform, and
-// only at the first K-chunk of a tile, where the accumulators are dead (the
-// queued rows are still tightened before the next epilogue appends).
-__device__ inline void tighten_rows(const CandParams& p, int64_t ti, int64_t split, float* lds_thr, int* lds_cnt,
-                                    int* lds_list) {
-  const int nq = lds_list[0];
-  if (nq == 0) return;
-  const int wave = threadIdx.x >> 6;
-  for (int q = wave; q < nq; q += kThreads / 64) {
-    const int lr = lds_list[1 + q];
+// Rows queued by the band epilogue are tightened by one wave each and their
+// triggers re-armed retight entries further on (capped at cap - 256, which
+// keeps room for one more tile); called by the whole workgroup right after a
+// barrier, so list[0] is uniform, and only at the first K-chunk of a tile,
+// where the accumulators are dead (queued rows are still tightened before
+// the next epilogue appends).
+// Returns whether any row was tightened (then the workgroup wrote to global
+// memory).
+__device__ inline bool tighten_rows(const CandParams& p, int64_t ti, int64_t split, BandLds& L) {
+  const int nq = L.list[0];
+  if (nq == 0) return false;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int limit = p.cap - kTile;
+  for (int t = wave; t < nq; t += kThreads / 64) {
+    const int lr = L.list[1 + t];
     const int64_t i = ti * kTile + lr;
-    const int n = min(lds_cnt[lr], p.cap);
-    compact_row(p.band + ((i * p.P) + split) * (int64_t)p.cap, n, p.marg[i], &lds_thr[lr], &lds_cnt[lr], p.k, p.cap,
-                p.overflow);
+    const int n = min(L.cnt[lr], p.cap);
+    const int w = compact_row(p.band + ((i * p.P) + split) * (int64_t)p.cap, n, p.marg[i], &L.thr[lr], p.k);
+    if (lane == 0) {
+      L.cnt[lr] = w;
+      L.trig[lr] = min(w + p.retight, limit);
+      if (w > limit) atomicOr(p.overflow, 1);
+    }
   }
   __syncthreads();
-  if (threadIdx.x == 0) lds_list[0] = 0;
+  if (threadIdx.x == 0) L.list[0] = 0;
   __syncthreads();
+  return true;
 }
 
 // ------------------------------------------------------------------ kernel
+// Waits until at most n vector-memory operations of this wave are
+// outstanding and all of its LDS operations are done, then joins the
+// workgroup's barrier.  n is 0 or a multiple of a step's transfers; the
+// s_waitcnt immediate packs vmcnt in bits 3:0 and 15:14 (expcnt 6:4 left at
+// its no-wait value 7, lgkmcnt 11:8 = 0).
+__device__ inline void wait_and_sync(int n) {
+  n = __builtin_amdgcn_readfirstlane(n);  // block-uniform: scalar branches
+  asm volatile("" ::: "memory");
+  if (n >= 8) __builtin_amdgcn_s_waitcnt(0x0078);
+  else if (n >= 4) __builtin_amdgcn_s_waitcnt(0x0074);
+  else __builtin_amdgcn_s_waitcnt(0x0070);
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 template <int kPrec, int kMode>
 __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
-  // two stages of (A chunk, B chunk)
-  __shared__ __attribute__((aligned(1024))) uint8_t lds_ab[2][2][kStageBytes];
-  __shared__ __attribute__((aligned(16))) float lds_thr[kMode == kModeBand ? kTile : 1];
-  __shared__ int lds_cnt[kMode == kModeBand ? kTile : 1];
-  __shared__ int lds_list[kMode == kModeBand ? kTile + 1 : 1];
+  using Q = Pipe<kPrec>;
+  static_assert(Q::kStages == 2 || Q::kStages == 4, "ring depth");
+  static_assert((Q::kStages - 2) * Q::kPerStep <= 8, "wait_and_sync covers two later steps at most");
+  constexpr bool kFp8 = kPrec == DL_FP8, kEps = kMode == kModeEps;
+  // the ring: kStages x (A step, B step)
+  __shared__ __attribute__((aligned(1024))) uint8_t lds_ab[Q::kStages][2][Q::kStageBytes];
+  // per-tile side data, three tiles deep (the loader runs at most two tiles
+  // ahead of the tile being computed)
+  __shared__ __attribute__((aligned(16))) float side_hb[3][kTile];
+  __shared__ __attribute__((aligned(16))) float side_thr[kEps ? 3 : 1][kEps ? kTile : 4];
+  __shared__ __attribute__((aligned(16))) int side_sa[kFp8 ? 3 : 1][kFp8 ? kTile : 4];
+  __shared__ __attribute__((aligned(16))) int side_sb[kFp8 ? 3 : 1][kFp8 ? kTile : 4];
+  __shared__ __attribute__((aligned(16))) uint8_t lds_band_raw[kEps ? 16 : sizeof(BandLds)];
+  BandLds& band = *reinterpret_cast<BandLds*>(lds_band_raw);
+  __shared__ __attribute__((aligned(16))) uint2 lds_eq[kEps ? kThreads / 64 : 1][kEps ? kQueue : 1];
 
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wm = wave >> 2, wn = wave & 3;
-  TileIter it{0};
+  const int nsteps = (int)(p.qld / Q::kCB);
+
+  // the compute side and the loader walk the same tile sequence, the loader
+  // up to kStages - 1 steps ahead
+  TileIter cit;
   int64_t ti, tj;
-  if (!it.next(p, kMode, ti, tj)) return;
-  int64_t split = 0;
-  if constexpr (kMode == kModeBand) {
-    const int64_t nb = gridDim.x;
-    const int64_t w = (int64_t)(blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
-    split = uniform64(w / p.nTR);
-    for (int r = threadIdx.x; r < kTile; r += kThreads) {
-      lds_thr[r] = -INFINITY;
-      lds_cnt[r] = 0;
+  if (!cit.next(p, kMode, ti, tj)) return;
+  TileIter lit = cit;
+  int64_t lti = ti, ltj = tj;
+  int lstep = 0, ltile = 0, issued = 0;
+  bool lmore = true;
+  auto issue = [&]() {
+    if (lstep == 0) {
+      const int sb = ltile % 3;
+      issue_side<kPrec, kMode>(p, lti, ltj, SideRefs{side_hb[sb], side_thr[kEps ? sb : 0], side_sa[kFp8 ? sb : 0],
+                                                      side_sb[kFp8 ? sb : 0]});
     }
-    if (threadIdx.x == 0) lds_list[0] = 0;
+    const int st = issued % Q::kStages;
+    issue_loads<kPrec>(p, lti, ltj, lstep, lds_ab[st][0], lds_ab[st][1]);
+    ++issued;
+    if (++lstep == nsteps) {
+      lstep = 0;
+      ++ltile;
+      lmore = lit.next(p, kMode, lti, ltj);
+    }
+  };
+
+  int64_t split = 0;
+  if constexpr (!kEps) {
+    split = uniform64(cit.split);
+    for (int r = threadIdx.x; r < kTile; r += kThreads) {
+      band.thr[r] = -INFINITY;
+      band.cnt[r] = 0;
+      band.trig[r] = min(p.retight, p.cap - kTile);
+    }
+    if (threadIdx.x == 0) band.list[0] = 0;
   }
-  int chunk = 0, stage = 0;
-  bool full = true;  // band mode: the tile needs no bounds or self checks
-  issue_loads(p, ti, tj, 0, lds_ab[0][0], lds_ab[0][1]);
+  for (int s = 0; s < Q::kStages - 1 && lmore; ++s) issue();
+
+  int step = 0, chunk = 0, ctile = 0;
+  int eq = 0;  // eps: candidates staged in this wave's queue
+  bool dirty = true;  // the band set-up above wrote LDS only, but be exact once
+  bool full = true;   // band mode: the tile needs no bounds or self checks
+  bool nmore = false;
+  int64_t nti = 0, ntj = 0;
   f32x4 acc[8][4];
   int sa[8], sb[4];
   for (;;) {
-    int64_t nti = ti, ntj = tj;
-    int nchunk = chunk + 1;
-    bool more = true;
-    if (nchunk == p.nchunks) {
-      nchunk = 0;
-      more = it.next(p, kMode, nti, ntj);
-    }
-    // This step's operands are in LDS once this wave's loads have landed
-    // (vmcnt) and every wave has passed the barrier; the barrier also means
-    // every wave is done reading the other stage (it computed the previous
-    // step before arriving), so the next step's loads may overwrite it.
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
+    // This step's operands are in LDS once this wave's transfers for it have
+    // landed and every wave has passed the barrier; transfers of later steps
+    // may stay in flight, unless this wave also wrote to global memory since
+    // the last full wait (stores and loads may then retire out of order).
+    // The barrier also means every wave is done with the stage computed in
+    // the previous step, so this step's new transfers may overwrite it.
+    wait_and_sync(dirty ? 0 : (issued - step - 1) * Q::kPerStep);
+    dirty = false;
+    const int sbuf = ctile % 3;
     if (chunk == 0) {
-      if constexpr (kMode == kModeBand) {
-        tighten_rows(p, ti, split, lds_thr, lds_cnt, lds_list);
+      if constexpr (!kEps) {
+        dirty |= tighten_rows(p, ti, split, band);
         full = (ti + 1) * kTile <= p.nR && (tj + 1) * kTile <= p.nS && !(p.exclude_self && ti == tj);
       }
+      const int l16 = fresh_lane() & 15;
+      const int cb = wn * kWaveN + l16, rb = wm * kWaveM + l16;
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb) {
-        const int64_t j = tj * kTile + wn * kWaveN + nb * 16 + (lane & 15);
-        const float init = -p.hb[j];
+        const float init = -side_hb[sbuf][cb + nb * 16];
 #pragma unroll
         for (int mb = 0; mb < 8; ++mb) acc[mb][nb] = f32x4{init, init, init, init};
-        if constexpr (kPrec == DL_FP8) sb[nb] = p.sexb[j] + 127;
+        if constexpr (kFp8) sb[nb] = side_sb[sbuf][cb + nb * 16] + 127;
       }
-      if constexpr (kPrec == DL_FP8) {
+      if constexpr (kFp8) {
 #pragma unroll
-        for (int mb = 0; mb < 8; ++mb) sa[mb] = p.sexa[ti * kTile + wm * kWaveM + mb * 16 + (lane & 15)] + 127;
+        for (int mb = 0; mb < 8; ++mb) sa[mb] = side_sa[sbuf][rb + mb * 16] + 127;
       }
-      // the initial values are in registers before the next step's
-      // transfers are queued behind them
-      __builtin_amdgcn_s_waitcnt(0);
+      nmore = cit.next(p, kMode, nti, ntj);
     }
-    if (more) issue_loads(p, nti, ntj, nchunk, lds_ab[stage ^ 1][0], lds_ab[stage ^ 1][1]);
-    mma_chunk<kPrec>(acc, lds_ab[stage][0], lds_ab[stage][1], wm * kWaveM, wn * kWaveN, sa, sb);
-    if (chunk == p.nchunks - 1) {
-      if constexpr (kMode == kModeEps) epilogue_eps(p, ti, tj, acc);
-      else epilogue_band(p, ti, tj, split, full, acc, lds_thr, lds_cnt, lds_list);
+    if (lmore) issue();
+    const int st = step % Q::kStages;
+    mma_step<kPrec>(acc, lds_ab[st][0], lds_ab[st][1], wm * kWaveM, wn * kWaveN, sa, sb);
+    if (chunk == nsteps - 1) {
+      if constexpr (kEps) dirty |= epilogue_eps(p, ti, tj, acc, side_thr[kEps ? sbuf : 0], lds_eq[kEps ? wave : 0], eq);
+      else dirty |= epilogue_band(p, ti, tj, split, full, acc, band);
     }
-    if (!more) break;
-    ti = nti;
-    tj = ntj;
-    chunk = nchunk;
-    stage ^= 1;
+    ++step;
+    if (++chunk == nsteps) {
+      if (!nmore) break;
+      chunk = 0;
+      ti = nti;
+      tj = ntj;
+      ++ctile;
+    }
   }
-  if constexpr (kMode == kModeBand) {
+  if constexpr (kEps) {
+    if (eq) flush_eps(p, lds_eq[wave], eq);
+  } else {
     __syncthreads();
-    tighten_rows(p, ti, split, lds_thr, lds_cnt, lds_list);
+    tighten_rows(p, ti, split, band);
     for (int r = threadIdx.x; r < kTile; r += kThreads) {
       const int64_t i = ti * kTile + r;
-      if (i < p.nR) p.bcount[i * p.P + split] = min(lds_cnt[r], p.cap);
+      if (i < p.nR) p.bcount[i * p.P + split] = min(band.cnt[r], p.cap);
     }
   }
 }
 
-// ------------------------------------------------------------ host launch
 template <int kMode>
 static hipError_t launch_mode(dl_prec prec, const CandParams& p, dim3 grid, hipStream_t st) {
   switch (prec) {

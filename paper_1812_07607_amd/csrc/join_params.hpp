@@ -33,6 +33,7 @@ struct CandParams {
   int64_t tps;         // S tiles per split
   int k;
   int cap;             // band entries per (row, split)
+  int retight;         // entries appended to a row between tightenings
   const float* marg;   // E_i per R row
   uint2* band;         // (P~ bits, j): [(row * P + split) * cap + slot]
   int* bcount;         // [row * P + split]

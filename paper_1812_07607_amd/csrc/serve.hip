@@ -426,7 +426,7 @@ dl_status dl_server_create(int device, const dl_store* store, const dl_server_co
                            size_t arena_bytes, dl_server** out) {
   if (!out) return DL_ERR_INVALID;
   *out = nullptr;
-  if (!store || !arena || arena_bytes < 4096) return DL_ERR_INVALID;
+  if (!store || !arena || arena_bytes < 4096 || (reinterpret_cast<uintptr_t>(arena) & 255)) return DL_ERR_INVALID;
   dl_server_config c{};
   if (cfg) c = *cfg;
   if (c.n_streams <= 0) c.n_streams = 2;

@@ -10,7 +10,7 @@ import torch
 
 from gpu_util import assert_eps_equal, dev, host
 from paper_1812_07607_amd import ops, synth
-from paper_1812_07607_amd._lib import DLError
+from paper_1812_07607_amd._lib import DL_ERR_INVALID, DLError
 
 pytestmark = pytest.mark.gpu
 PRECS = ["fp32", "bf16", "fp16", "fp8"]
@@ -191,3 +191,20 @@ def test_full_size_histogram_self_join_sampled_rows(orc):
     assert np.all(gi < gj)
     key = gi * (1 << 20) + gj
     assert np.all(np.diff(key) > 0)
+
+
+class _Misaligned(ops.Workspace):
+    """A workspace whose buffer starts 16 bytes past an allocation."""
+
+    def get(self, nbytes):
+        return super().get(int(nbytes) + 256)[16:]
+
+
+def test_rejects_misaligned_workspace():
+    R = dev(synth.uniform_rows(300, 64, seed=11))
+    with pytest.raises(DLError) as e:
+        ops.join_eps(R, None, 0.5, "bf16", workspace=_Misaligned(R.device))
+    assert e.value.status == DL_ERR_INVALID
+    with pytest.raises(DLError) as e:
+        ops.join_topk(R, R, 5, prec="bf16", workspace=_Misaligned(R.device))
+    assert e.value.status == DL_ERR_INVALID
