@@ -48,6 +48,11 @@ KERNEL_SOURCES = ["paper_1812_07607_amd/csrc/join_mfma.hip", "paper_1812_07607_a
 TRAFFIC_SUMMARY = "profiles/cand_kernel_fp16_selfjoin_100k_traffic.txt"
 
 
+def progress(msg):
+    """A progress line on stderr (stdout carries only the result line)."""
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
 def kernel_hash():
     import hashlib
     h = hashlib.sha256()
@@ -165,6 +170,7 @@ def serving(args):
 
     torch.cuda.synchronize()
     # closed loop: all requests at once
+    progress("serving: store ready (%.1f s); closed-loop capacity run" % t_setup)
     st, bad, rows_c = one_run(64, 0.0, 5051)
     cap_rps = st["completed"] / max(st["span_ms"], 1e-9) * 1e3
     out = {"workload": "resident store %d x 128 bf16; requests log-uniform 1..50,000 rows, 50%% eps (eps=%.4g, "
@@ -176,6 +182,7 @@ def serving(args):
     for frac in (0.5, 0.8):
         rate = frac * cap_rps
         n_req = max(8, int(rate * args.serve_seconds))
+        progress("serving: open loop at %.2f x capacity" % frac)
         st, bad, rows_o = one_run(n_req, rate, 5052 + int(frac * 10))
         out["offered_%.1fC" % frac] = {"rate_rps": rate, "requests": st["completed"],
                                        "gpairs_per_s": st["pairs_done"] / max(st["span_ms"], 1e-9) * 1e-6,
@@ -219,6 +226,7 @@ def main():
         ops.featurize_rgb8(patches, 8, out=hist)
         return ops.join_eps(hist, None, eps, prec, workspace=ws, out=out)
 
+    progress("setup done (eps %.6g); warm-up and %d timed steps" % (eps, args.steps))
     r = step(args.prec)
     cap = max(r.count * 2, 1 << 16)
     out = (torch.empty(cap, dtype=torch.int32, device="cuda"), torch.empty(cap, dtype=torch.int32, device="cuda"),
@@ -265,6 +273,7 @@ def main():
         "stages_ms_per_step": {k: v[0] / max(args.steps, 1) for k, v in stages.items() if v[1]},
         "roofline": roof,
     }
+    progress("timed steps: %.3f ms/step" % ms_step)
     if not args.no_fp32_compare and args.prec != "fp32":
         # the plain fp32 GPU join on the same input, for comparison
         step("fp32", out)
@@ -283,6 +292,7 @@ def main():
         except Exception as e:  # reported, not fatal to the main measurement
             res["serving"] = {"error": repr(e)}
     if not args.no_cpu_baseline:
+        progress("cpu baseline (oracle, about %.0f s)" % args.cpu_seconds)
         res["cpu_baseline"] = cpu_baseline({"patches": cfg["patches"], "hist": hist.cpu().numpy()}, eps, n,
                                            args.cpu_seconds)
     print(json.dumps(res))
