@@ -525,13 +525,17 @@ __device__ inline void flush_band(const CandParams& p, int64_t ti, int64_t tj, i
   }
 }
 
-// Band epilogue.  For each of the wave's 32 (row block, row) slots the row
-// maximum over the four column blocks is tested against the row's band
-// threshold; only a slot with a hit forms its four hit masks and stages the
-// hits in the wave's LDS queue (ballot-prefixed, no atomics, no waits).
-// The queue is flushed when the next slot might not fit and at the end.
-// Returns whether this wave wrote to global memory.
-__device__ inline bool epilogue_band(const CandParams& p, int64_t ti, int64_t tj, int64_t split, bool full,
+// Band epilogue.  Each of the wave's 128 outputs per lane is compared with
+// its row's band threshold; the 64-lane hit mask of each (row block, row,
+// column block) is a single ballot, and only a nonzero mask stages its hits
+// in the wave's LDS queue (ballot prefix, no atomics, no waits).  The queue
+// is flushed when the next (row block, row) slot might not fit and at the
+// end.  A full tile
+// (the common case) carries no bounds or diagonal code; a partial or
+// self-diagonal tile checks rows and columns left in the tile in 32-bit tile
+// coordinates.  Returns whether this wave wrote to global memory.
+template <bool kFull>
+__device__ inline bool epilogue_band(const CandParams& p, int64_t ti, int64_t tj, int64_t split,
                                      const f32x4 (&acc)[8][4], BandLds& L) {
   const int lane = fresh_lane(), wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wm = wave >> 2, wn = wave & 3;
@@ -545,44 +549,45 @@ __device__ inline bool epilogue_band(const CandParams& p, int64_t ti, int64_t tj
   // visible, all 128 tags would be precomputed and kept across the tile loop
   uint32_t tag0 = ((uint32_t)lrow0 << 8) | (uint32_t)lcol0;
   asm volatile("" : "+v"(tag0));
+  int rrem = kTile, crem = kTile;
+  bool diag = false;
+  if constexpr (!kFull) {
+    rrem = (int)min(p.nR - ti * kTile, (int64_t)kTile);
+    crem = (int)min(p.nS - tj * kTile, (int64_t)kTile);
+    diag = p.exclude_self && ti == tj;
+  }
 #pragma unroll
   for (int mb = 0; mb < 8; ++mb) {
     const float4 th = *reinterpret_cast<const float4*>(L.thr + lrow0 + mb * 16);
     const float tv[4] = {th.x, th.y, th.z, th.w};
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const float mx = fmaxf(fmaxf(acc[mb][0][r], acc[mb][1][r]), fmaxf(acc[mb][2][r], acc[mb][3][r]));
-      if (!__ballot(mx >= tv[r])) continue;
-      const int lr = lrow0 + mb * 16 + r;
       bool hit[4];
       uint64_t m[4];
-      int tot = 0;
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb) {
         hit[nb] = acc[mb][nb][r] >= tv[r];
-        if (!full) {
-          // in-tile bounds: rows left in R and S (at most a tile) and the
-          // diagonal of a self tile, all in 32-bit
-          const int rrem = (int)min(p.nR - ti * kTile, (int64_t)kTile);
-          const int crem = (int)min(p.nS - tj * kTile, (int64_t)kTile);
-          const bool diag = p.exclude_self && ti == tj;
-          const int lc = lcol0 + nb * 16;
+        if constexpr (!kFull) {
+          const int lr = lrow0 + mb * 16 + r, lc = lcol0 + nb * 16;
           hit[nb] = hit[nb] && lr < rrem && lc < crem && !(diag && lr == lc);
         }
         m[nb] = __ballot(hit[nb]);
-        tot += __popcll(m[nb]);
       }
-      if (nq + tot > kQueue) {
+      if (!(m[0] | m[1] | m[2] | m[3])) continue;
+      // one capacity check per slot keeps the flush code at 32 sites
+      if (nq + __popcll(m[0]) + __popcll(m[1]) + __popcll(m[2]) + __popcll(m[3]) > kQueue) {
         flush_band(p, ti, tj, split, L, q, nq);
         nq = 0;
         wrote = true;
       }
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb) {
-        if (hit[nb])
-          q[nq + __popcll(m[nb] & lt)] =
-              make_uint2(__float_as_uint(acc[mb][nb][r]), tag0 + (uint32_t)(((mb * 16 + r) << 8) + nb * 16));
-        nq += __popcll(m[nb]);
+        if (m[nb]) {
+          if (hit[nb])
+            q[nq + __popcll(m[nb] & lt)] =
+                make_uint2(__float_as_uint(acc[mb][nb][r]), tag0 + (uint32_t)(((mb * 16 + r) << 8) + nb * 16));
+          nq += __popcll(m[nb]);
+        }
       }
     }
   }
@@ -741,7 +746,8 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
     mma_step<kPrec>(acc, lds_ab[st][0], lds_ab[st][1], wm * kWaveM, wn * kWaveN, sa, sb);
     if (chunk == nsteps - 1) {
       if constexpr (kEps) dirty |= epilogue_eps(p, ti, tj, acc, side_thr[kEps ? sbuf : 0], lds_eq[kEps ? wave : 0], eq);
-      else dirty |= epilogue_band(p, ti, tj, split, full, acc, band);
+      else if (full) dirty |= epilogue_band<true>(p, ti, tj, split, acc, band);
+      else dirty |= epilogue_band<false>(p, ti, tj, split, acc, band);
     }
     ++step;
     if (++chunk == nsteps) {
