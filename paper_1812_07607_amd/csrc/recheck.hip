@@ -140,6 +140,7 @@ hipError_t launch_pair_d2(const float* R, int64_t ldr, int64_t nR, const float* 
 // ------------------------------------------------------------ top-k select
 constexpr int kSelMax = 512;  // contenders per row held in LDS
 constexpr int kSelWaves = 4;
+constexpr int kSelRegs = 8;   // band entries per lane held in registers (unions up to 512)
 
 
 
@@ -148,118 +149,254 @@ __device__ inline uint32_t ord_f(float f) {
   return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
+// float32 direct-form d2 of rows a and b, summed by one lane in increasing
+// k (any order stays within the bound beta).  The query row a is the same
+// for the whole wave.
+__device__ inline float lane_d2(const float* a, const float* b, int d, bool vec4) {
+  float acc = 0.0f;
+  int q = 0;
+  if (vec4) {
+    for (; q + 4 <= d; q += 4) {
+      const float4 x = *reinterpret_cast<const float4*>(a + q);
+      const float4 y = *reinterpret_cast<const float4*>(b + q);
+      float u = x.x - y.x;
+      acc = fmaf(u, u, acc);
+      u = x.y - y.y;
+      acc = fmaf(u, u, acc);
+      u = x.z - y.z;
+      acc = fmaf(u, u, acc);
+      u = x.w - y.w;
+      acc = fmaf(u, u, acc);
+    }
+  }
+  for (; q < d; ++q) {
+    const float u = a[q] - b[q];
+    acc = fmaf(u, u, acc);
+  }
+  return acc;
+}
+
+// One wave per row.  Counting over the row's band entries uses ballots
+// (scalar popcounts, no shuffle chains); distances are computed one entry
+// per lane; the k nearest are emitted by rank, since the (key, j) pairs of a
+// row are distinct.
 __global__ __launch_bounds__(64 * kSelWaves) void topk_select_kernel(SelectParams p) {
   __shared__ float s_d2[kSelWaves][kSelMax];
   __shared__ uint32_t s_j[kSelWaves][kSelMax];
   __shared__ double s_key[kSelWaves][kSelMax];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t i = (int64_t)blockIdx.x * kSelWaves + wave;
   if (i >= p.nR) return;
   const float* a = p.R + i * p.ldr;
   const int k = p.k;
-
-  // (1) k-th largest P~ over the union of the row's split buffers
-  auto count_ge = [&](uint32_t cand) {
+  const uint64_t lt = __lanemask_lt();
+  // number of entries of the row whose first word w satisfies pred(w)
+  auto count = [&](auto pred) {
     int c = 0;
     for (int s = 0; s < p.P; ++s) {
       const uint2* e = p.band + (i * p.P + s) * (int64_t)p.cap;
       const int n = p.bcount[i * p.P + s];
-      for (int t = lane; t < n; t += 64) c += ord_f(__uint_as_float(e[t].x)) >= cand;
+      for (int base = 0; base < n; base += 64) {
+        const int t = base + lane;
+        c += __popcll(__ballot(t < n && pred(e[t].x)));
+      }
     }
-    return wave_sumi(c);
+    return c;
   };
+
   int total = 0;
   for (int s = 0; s < p.P; ++s) total += p.bcount[i * p.P + s];
-  float bt = -INFINITY;
-  if (total >= k) {
-    uint32_t t = 0;
-    for (int b = 31; b >= 0; --b)
-      if (count_ge(t | (1u << b)) >= k) t |= 1u << b;
-    const float pk = __uint_as_float((t & 0x80000000u) ? (t & 0x7fffffffu) : ~t);
-    bt = f32_down((double)pk - (double)p.marg[i]);
-  }
-
-  // (2) float32 direct-form d2 of every band entry, written over its P~:
-  // 64 entries at a time, each summed by the whole wave with coalesced row
-  // reads; lane t keeps entry t's sum.
-  int nb = 0;
-  for (int s = 0; s < p.P; ++s) {
-    uint2* e = p.band + (i * p.P + s) * (int64_t)p.cap;
-    const int n = p.bcount[i * p.P + s];
-    for (int base = 0; base < n; base += 64) {
-      const int cnt = min(64, n - base);
-      const uint2 v = lane < cnt ? e[base + lane] : make_uint2(0, 0);
-      const bool inband = lane < cnt && __uint_as_float(v.x) >= bt;
-      const uint64_t mb = __ballot(inband);
-      float mine = INFINITY;
-      uint64_t rest = mb;
-      while (rest) {
-        const int t = __ffsll((unsigned long long)rest) - 1;
-        rest &= rest - 1;
-        const uint32_t jt = __shfl(v.y, t, 64);
-        const float* b = p.S + (int64_t)jt * p.lds;
-        float acc = 0.0f;
-        for (int q = lane; q < p.d; q += 64) {
-          const float u = a[q] - b[q];
-          acc = fmaf(u, u, acc);
-        }
-        acc = wave_sumf(acc);
-        if (lane == t) mine = acc;
-      }
-      if (lane < cnt) e[base + lane].x = __float_as_uint(mine);
-      nb += __popcll(mb);
-    }
-  }
-  if (lane != 0) nb = 0;
-  nb = wave_sumi(nb);
-  if (lane == 0) atomicAdd(p.nband, (unsigned long long)nb);
-
-  // (3) per-row bound beta(d2) = c1 d2 + c0 (monotone); D_k = k-th smallest d2
   const double xsum = (double)p.xnR[i] + (double)p.sS->xnorm_max;
   const bool ex = exact32(min(p.mlR[i], p.sS->mlsb_min), xsum);
   const double c1 = ex ? 0.0 : 2.0 * gamma_n((double)p.d + 2.0, 0x1p-24);
   const double c0 = ex ? 0.0 : ((double)p.d + 2.0) * 0x1p-148 + ((double)p.d + 4.0) * 0x1p-52 * xsum * xsum;
-  auto count_lt = [&](uint64_t lim) {  // entries with d2 bits < lim
-    int c = 0;
-    for (int s = 0; s < p.P; ++s) {
-      const uint2* e = p.band + (i * p.P + s) * (int64_t)p.cap;
-      const int n = p.bcount[i * p.P + s];
-      for (int t = lane; t < n; t += 64) c += (uint64_t)e[t].x < lim;
-    }
-    return wave_sumi(c);
-  };
-  uint64_t dk = 0;  // bits of the k-th smallest d2 (non-negative floats order as integers)
-  for (int b = 31; b >= 0; --b)
-    if (count_lt(dk + (1ull << b)) < k) dk += 1ull << b;
-  const double Dk = dk >= 0x7f800000ull ? INFINITY : (double)__uint_as_float((uint32_t)dk);
-  // entries with d2 - beta > D_k + beta(D_k) cannot be among the k nearest
-  double cut = INFINITY;
-  if (!isinf(Dk)) cut = (Dk * (1.0 + c1) + 2.0 * c0) / (1.0 - c1) * (1.0 + 0x1p-50);
-
-  // (4) contenders into LDS
+  const bool vec4 = ((reinterpret_cast<uintptr_t>(p.S) | reinterpret_cast<uintptr_t>(a)) & 15) == 0 &&
+                    (p.lds & 3) == 0;
   float* cd = s_d2[wave];
   uint32_t* cj = s_j[wave];
   double* ck = s_key[wave];
-  int nc = 0;
-  const uint64_t lt = __lanemask_lt();
-  for (int s = 0; s < p.P; ++s) {
-    const uint2* e = p.band + (i * p.P + s) * (int64_t)p.cap;
-    const int n = p.bcount[i * p.P + s];
-    for (int base = 0; base < n; base += 64) {
-      const int t = base + lane;
-      uint2 v = make_uint2(0x7f800000u, 0);
-      if (t < n) v = e[t];
-      const float d2 = __uint_as_float(v.x);
-      const bool keep = t < n && !isinf(d2) && (double)d2 <= cut;
-      const uint64_t m = __ballot(keep);
-      const int pos = nc + __popcll(m & lt);
-      if (keep && pos < kSelMax) {
-        cd[pos] = d2;
-        cj[pos] = v.y;
+  int nc = 0, nb = 0;
+  // entries with d2 - beta > D_k + beta(D_k) cannot be among the k nearest
+  auto cut_of = [&](uint64_t dk) {
+    const double Dk = dk >= 0x7f800000ull ? INFINITY : (double)__uint_as_float((uint32_t)dk);
+    return isinf(Dk) ? INFINITY : (Dk * (1.0 + c1) + 2.0 * c0) / (1.0 - c1) * (1.0 + 0x1p-50);
+  };
+  // Stage into LDS, compactly, the union's entries with P~ >= floor (up to
+  // 64 * kSelRegs of them); returns how many there are.
+  uint2* st = reinterpret_cast<uint2*>(ck);
+  auto stage = [&](float floor) {
+    int g = 0;
+    for (int s = 0; s < p.P; ++s) {
+      const uint2* e = p.band + (i * p.P + s) * (int64_t)p.cap;
+      const int n = p.bcount[i * p.P + s];
+      for (int base = 0; base < n; base += 64) {
+        const int t = base + lane;
+        const uint2 v = t < n ? e[t] : make_uint2(0, 0);
+        const bool in = t < n && __uint_as_float(v.x) >= floor;
+        const uint64_t m = __ballot(in);
+        const int pos = g + __popcll(m & lt);
+        if (in && pos < 64 * kSelRegs) st[pos] = v;
+        g += __popcll(m);
       }
-      nc += __popcll(m);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    return g;
+  };
+  // k-th largest P~ of the staged entries, minus the margin (the band
+  // threshold they imply), by ballot counts over registers
+  auto band_of = [&](const uint32_t (&key)[kSelRegs], int cnt) {
+    if (cnt < k) return -INFINITY;
+    const int nr = (cnt + 63) / 64;
+    uint32_t t = 0;
+    for (int b = 31; b >= 0; --b) {
+      const uint32_t cand = t | (1u << b);
+      int c = 0;
+#pragma unroll
+      for (int r = 0; r < kSelRegs; ++r)
+        if (r < nr) c += __popcll(__ballot(key[r] >= cand));
+      if (c >= k) t = cand;
+    }
+    const float pk = __uint_as_float((t & 0x80000000u) ? (t & 0x7fffffffu) : ~t);
+    return f32_down((double)pk - (double)p.marg[i]);
+  };
+  auto load_keys = [&](uint32_t (&key)[kSelRegs], uint32_t (&jv)[kSelRegs], int cnt) {
+#pragma unroll
+    for (int r = 0; r < kSelRegs; ++r) {
+      const int gi = r * 64 + lane;
+      const uint2 v = gi < cnt ? st[gi] : make_uint2(0xff800000u, 0xffffffffu);
+      key[r] = gi < cnt ? ord_f(__uint_as_float(v.x)) : 0u;
+      jv[r] = v.y;
+    }
+  };
+  uint32_t key[kSelRegs], jv[kSelRegs];
+  // A union too large for the registers is first filtered with the band of
+  // its first entries: any lower bound of its k-th largest P~ keeps the
+  // whole exact band, so the entries above it carry the same answer.
+  int kept = stage(-INFINITY);
+  if (kept > 64 * kSelRegs) {
+    load_keys(key, jv, 64 * kSelRegs);
+    kept = stage(band_of(key, 64 * kSelRegs));
+  }
+  if (kept <= 64 * kSelRegs) {
+    // the (filtered) union in registers: both order statistics are ballot
+    // counts over registers
+    const int total = kept;
+    load_keys(key, jv, total);
+#pragma unroll
+    for (int r = 0; r < kSelRegs; ++r) {
+      const int gi = r * 64 + lane;
+      const uint2 v = gi < total ? st[gi] : make_uint2(0xff800000u, 0xffffffffu);
+      key[r] = gi < total ? ord_f(__uint_as_float(v.x)) : 0u;
+      jv[r] = v.y;
+    }
+    const int nr = (total + 63) / 64;  // register slots in use (block-uniform)
+    // (1) k-th largest P~ over the union
+    const float bt = band_of(key, total);
+    // (2) float32 direct-form d2 of the entries in the band (+inf for the
+    // others; all-ones bits, which no count below includes, for the slots
+    // past the union)
+    const uint32_t kbt = ord_f(bt);
+    uint32_t d2b[kSelRegs];
+#pragma unroll
+    for (int r = 0; r < kSelRegs; ++r) {
+      d2b[r] = r * 64 + lane < total ? 0x7f800000u : 0xffffffffu;
+      if (r < nr) {
+        const bool inband = r * 64 + lane < total && key[r] >= kbt;
+        if (inband) d2b[r] = __float_as_uint(lane_d2(a, p.S + (int64_t)jv[r] * p.lds, p.d, vec4));
+        nb += __popcll(__ballot(inband));
+      }
+    }
+    // (3) D_k = k-th smallest d2 (non-negative floats order as integers)
+    uint64_t dk = 0;
+    for (int b = 31; b >= 0; --b) {
+      const uint64_t lim = dk + (1ull << b);
+      int c = 0;
+#pragma unroll
+      for (int r = 0; r < kSelRegs; ++r)
+        if (r < nr) c += __popcll(__ballot((uint64_t)d2b[r] < lim));
+      if (c < k) dk = lim;
+    }
+    const double cut = cut_of(dk);
+    // (4) contenders into LDS
+#pragma unroll
+    for (int r = 0; r < kSelRegs; ++r) {
+      if (r < nr) {
+        const float d2 = __uint_as_float(d2b[r]);
+        const bool keep = !isinf(d2) && (double)d2 <= cut;
+        const uint64_t m = __ballot(keep);
+        const int pos = nc + __popcll(m & lt);
+        if (keep && pos < kSelMax) {
+          cd[pos] = d2;
+          cj[pos] = jv[r];
+        }
+        nc += __popcll(m);
+      }
+    }
+  } else {
+    // a large union: the same steps over the split buffers in memory
+    auto count = [&](auto pred) {
+      int c = 0;
+      for (int s = 0; s < p.P; ++s) {
+        const uint2* e = p.band + (i * p.P + s) * (int64_t)p.cap;
+        const int n = p.bcount[i * p.P + s];
+        for (int base = 0; base < n; base += 64) {
+          const int t = base + lane;
+          c += __popcll(__ballot(t < n && pred(e[t].x)));
+        }
+      }
+      return c;
+    };
+    float bt = -INFINITY;
+    if (total >= k) {
+      uint32_t t = 0;
+      for (int b = 31; b >= 0; --b) {
+        const uint32_t cand = t | (1u << b);
+        if (count([&](uint32_t w) { return ord_f(__uint_as_float(w)) >= cand; }) >= k) t = cand;
+      }
+      const float pk = __uint_as_float((t & 0x80000000u) ? (t & 0x7fffffffu) : ~t);
+      bt = f32_down((double)pk - (double)p.marg[i]);
+    }
+    for (int s = 0; s < p.P; ++s) {
+      uint2* e = p.band + (i * p.P + s) * (int64_t)p.cap;
+      const int n = p.bcount[i * p.P + s];
+      for (int base = 0; base < n; base += 64) {
+        const int t = base + lane;
+        const uint2 v = t < n ? e[t] : make_uint2(0, 0);
+        const bool inband = t < n && __uint_as_float(v.x) >= bt;
+        float d2 = INFINITY;
+        if (inband) d2 = lane_d2(a, p.S + (int64_t)v.y * p.lds, p.d, vec4);
+        if (t < n) e[t].x = __float_as_uint(d2);
+        nb += __popcll(__ballot(inband));
+      }
+    }
+    uint64_t dk = 0;
+    for (int b = 31; b >= 0; --b) {
+      const uint64_t lim = dk + (1ull << b);
+      if (count([&](uint32_t w) { return (uint64_t)w < lim; }) < k) dk = lim;
+    }
+    const double cut = cut_of(dk);
+    for (int s = 0; s < p.P; ++s) {
+      const uint2* e = p.band + (i * p.P + s) * (int64_t)p.cap;
+      const int n = p.bcount[i * p.P + s];
+      for (int base = 0; base < n; base += 64) {
+        const int t = base + lane;
+        uint2 v = make_uint2(0x7f800000u, 0);
+        if (t < n) v = e[t];
+        const float d2 = __uint_as_float(v.x);
+        const bool keep = t < n && !isinf(d2) && (double)d2 <= cut;
+        const uint64_t m = __ballot(keep);
+        const int pos = nc + __popcll(m & lt);
+        if (keep && pos < kSelMax) {
+          cd[pos] = d2;
+          cj[pos] = v.y;
+        }
+        nc += __popcll(m);
+      }
     }
   }
+  if (lane == 0) atomicAdd(p.nband, (unsigned long long)nb);
   if (nc > kSelMax) {
     if (lane == 0) atomicOr(p.too_many, 1);
     for (int t = lane; t < k; t += 64) {
@@ -295,30 +432,23 @@ __global__ __launch_bounds__(64 * kSelWaves) void topk_select_kernel(SelectParam
   __builtin_amdgcn_s_waitcnt(0);
   __builtin_amdgcn_wave_barrier();
 
-  // (6) k rounds of (key, j) argmin
-  for (int r = 0; r < k; ++r) {
-    double bk = INFINITY;
-    uint32_t bj = 0xffffffffu;
-    int bpos = -1;
-    for (int t = lane; t < nc; t += 64) {
-      const double kk = ck[t];
-      const uint32_t jj = cj[t];
-      if (kk < bk || (kk == bk && jj < bj)) { bk = kk; bj = jj; bpos = t; }
+  // (6) each contender's rank in (key, j) order is its output slot
+  for (int t = lane; t < nc; t += 64) {
+    const double kt = ck[t];
+    const uint32_t jt = cj[t];
+    int rank = 0;
+    for (int u = 0; u < nc; ++u) {
+      const double ku = ck[u];
+      rank += ku < kt || (ku == kt && cj[u] < jt);
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ok = __shfl_xor(bk, o, 64);
-      const uint32_t oj = __shfl_xor(bj, o, 64);
-      const int op = __shfl_xor(bpos, o, 64);
-      if (ok < bk || (ok == bk && oj < bj)) { bk = ok; bj = oj; bpos = op; }
+    if (rank < k) {
+      p.out_j[i * k + rank] = jt;
+      p.out_dist[i * k + rank] = kt == (double)cd[t] ? sqrtf(cd[t]) : (float)sqrt(kt);
     }
-    if (lane == 0) {
-      p.out_j[i * k + r] = bpos >= 0 ? bj : 0xffffffffu;
-      p.out_dist[i * k + r] = bpos >= 0 ? (bk == (double)cd[bpos] ? sqrtf(cd[bpos]) : (float)sqrt(bk)) : INFINITY;
-      if (bpos >= 0) ck[bpos] = INFINITY, cj[bpos] = 0xffffffffu;
-    }
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_wave_barrier();
+  }
+  for (int r = nc + lane; r < k; r += 64) {
+    p.out_j[i * k + r] = 0xffffffffu;
+    p.out_dist[i * k + r] = INFINITY;
   }
 }
 
