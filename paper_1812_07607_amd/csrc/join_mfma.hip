@@ -195,6 +195,12 @@ struct TileIter {
 // one 1 KiB global_load_lds_dwordx4: lane l fills LDS slot l of the block,
 // i.e. row q * kRowsPerDma + l / kSlots, physical piece l % kSlots, so it
 // fetches the logical piece that the swizzle puts there.
+// Waves that issue the operand transfers.  Waves w and w + 4 share a SIMD;
+// with 4 issuing waves each SIMD keeps one wave free of transfers, which
+// can feed the matrix core while its partner waits on the vector-memory
+// queue.
+constexpr int kDmaWaves = 4;
+
 template <int kPrec>
 __device__ inline void issue_loads(const CandParams& p, int64_t ti, int64_t tj, int step, uint8_t* la, uint8_t* lb) {
   using Q = Pipe<kPrec>;
@@ -204,11 +210,13 @@ __device__ inline void issue_loads(const CandParams& p, int64_t ti, int64_t tj, 
   // live (and be spilled) beside the accumulators
   const int lane = fresh_lane();
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (wave >= kDmaWaves) return;
+  constexpr int kPer = kTile / Q::kRowsPerDma / kDmaWaves;  // blocks per issuing wave and operand
   const uint8_t* ga0 = p.qa + (ti * kTile) * p.qld + (int64_t)step * Q::kCB;
   const uint8_t* gb0 = p.qb + (tj * kTile) * p.qld + (int64_t)step * Q::kCB;
 #pragma unroll
-  for (int t = 0; t < Q::kDmaPerOp; ++t) {
-    const int q = wave * Q::kDmaPerOp + t;
+  for (int t = 0; t < kPer; ++t) {
+    const int q = wave * kPer + t;
     const int row = q * Q::kRowsPerDma + lane / Q::kSlots;
     const int phys = lane % Q::kSlots;
     const int c = (lds_off<Q::kCB>(row, phys) - row * Q::kCB) >> 4;  // the swizzle is an involution
@@ -231,14 +239,15 @@ struct SideRefs {
 };
 template <int kPrec, int kMode>
 __device__ inline void issue_side(const CandParams& p, int64_t ti, int64_t tj, const SideRefs& d) {
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // by the waves that issue no operand transfers, if there are such
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) - (kDmaWaves < 8 ? kDmaWaves : 0);
   const int e = 4 * fresh_lane();
-  if (wave == 0) lds_dma16(p.hb + tj * kTile + e, d.hb);
+  if (w == 0) lds_dma16(p.hb + tj * kTile + e, d.hb);
   if constexpr (kMode == kModeEps)
-    if (wave == 1) lds_dma16(p.thr + ti * kTile + e, d.thr);
+    if (w == 1) lds_dma16(p.thr + ti * kTile + e, d.thr);
   if constexpr (kPrec == DL_FP8) {
-    if (wave == 2) lds_dma16(p.sexa + ti * kTile + e, d.sa);
-    if (wave == 3) lds_dma16(p.sexb + tj * kTile + e, d.sb);
+    if (w == 2) lds_dma16(p.sexa + ti * kTile + e, d.sa);
+    if (w == 3) lds_dma16(p.sexb + tj * kTile + e, d.sb);
   }
 }
 
