@@ -102,8 +102,43 @@ enum : int { kModeEps = 0, kModeBand = 1 };
 // groups.  (Measured: this closed form, whose divisions by block-uniform
 // values compile to scalar code, beats carrying (group, offset) forward
 // with vector-unit 32-bit divisions.)
+// Division of a 32-bit block-uniform n by an invariant d through a
+// multiply-high and shifts (Granlund and Montgomery, "Division by Invariant
+// Integers using Multiplication", PLDI 1994): q = (t + ((n - t) >> s1)) >> s2
+// with t = mulhi(m, n); m, s1, s2 come from the host (div_magic).
+__device__ inline uint32_t udiv32(uint32_t n, uint32_t m, uint32_t s1, uint32_t s2) {
+  const uint32_t t = __umulhi(n, m);
+  return (t + ((n - t) >> s1)) >> s2;
+}
+
 __device__ inline bool tile_of(const CandParams& p, int64_t L, int64_t& ti, int64_t& tj) {
   const int64_t GM = p.GM;
+  if (p.small32) {
+    // every index below fits 32 bits: scalar multiply-high divisions
+    const uint32_t l = (uint32_t)L, gmax = (uint32_t)GM;
+    uint32_t g, rem;
+    if (!p.self_join) {
+      g = udiv32(l, p.dv_grp_m, p.dv_grp_s1, p.dv_grp_s2);
+      rem = l - g * (gmax * (uint32_t)p.nTS);
+    } else {
+      const int64_t nT = p.nTR;
+      int64_t lo = 0, hi = p.ngroups - 1;
+      while (lo < hi) {  // largest g with prefix(g) <= L
+        const int64_t mid = (lo + hi + 1) >> 1;
+        const int64_t pre = GM * (mid * nT - GM * mid * (mid - 1) / 2);
+        if (pre <= L) lo = mid; else hi = mid - 1;
+      }
+      g = (uint32_t)lo;
+      rem = (uint32_t)(L - GM * ((int64_t)g * nT - GM * (int64_t)g * (g - 1) / 2));
+    }
+    const bool last = (int64_t)g == p.ngroups - 1;
+    const uint32_t gm = last ? (uint32_t)(p.nTR - (int64_t)g * GM) : gmax;
+    const uint32_t q = last ? udiv32(rem, p.dv_gl_m, p.dv_gl_s1, p.dv_gl_s2) : udiv32(rem, p.dv_gm_m, p.dv_gm_s1, p.dv_gm_s2);
+    const int64_t g0 = (int64_t)g * GM;
+    tj = (p.self_join ? g0 : 0) + (int64_t)q;
+    ti = g0 + (int64_t)(rem - q * gm);
+    return !p.self_join || (ti <= tj && tj < p.nTR);
+  }
   if (!p.self_join) {
     const int64_t g = L / (GM * p.nTS);
     const int64_t rem = L - g * GM * p.nTS;
@@ -675,13 +710,16 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
   const int wm = wave >> 2, wn = wave & 3;
   const int nsteps = (int)(p.qld / Q::kCB);
 
-  // the compute side and the loader walk the same tile sequence, the loader
-  // up to kStages - 1 steps ahead
-  TileIter cit;
+  // The loader walks the tile sequence one K-step ahead of the matrix
+  // cores; the compute side takes its tiles from the loader: the step issued
+  // during a tile's last K-step is the next tile's first (one tile_of per
+  // tile instead of two).
+  static_assert(Q::kStages == 2, "the compute side follows the loader one step behind");
+  TileIter lit;
   int64_t ti, tj;
-  if (!cit.next(p, kMode, ti, tj)) return;
-  TileIter lit = cit;
-  int64_t lti = ti, ltj = tj;
+  if (!lit.next(p, kMode, ti, tj)) return;
+  int64_t lti = ti, ltj = tj;  // tile of the loader's next step
+  int64_t iti = ti, itj = tj;  // tile of the step issued last
   int lstep = 0, ltile = 0, issued = 0;
   bool lmore = true;
   auto issue = [&]() {
@@ -692,6 +730,8 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
     }
     const int st = issued % Q::kStages;
     issue_loads<kPrec>(p, lti, ltj, lstep, lds_ab[st][0], lds_ab[st][1]);
+    iti = lti;
+    itj = ltj;
     ++issued;
     if (++lstep == nsteps) {
       lstep = 0;
@@ -702,7 +742,7 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
 
   int64_t split = 0;
   if constexpr (!kEps) {
-    split = uniform64(cit.split);
+    split = uniform64(lit.split);
     for (int r = threadIdx.x; r < kTile; r += kThreads) {
       band.thr[r] = -INFINITY;
       band.cnt[r] = 0;
@@ -716,8 +756,6 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
   int eq = 0;  // eps: candidates staged in this wave's queue
   bool dirty = true;  // the band set-up above wrote LDS only, but be exact once
   bool full = true;   // band mode: the tile needs no bounds or self checks
-  bool nmore = false;
-  int64_t nti = 0, ntj = 0;
   f32x4 acc[8][4];
   int sa[8], sb[4];
   for (;;) {
@@ -748,8 +786,8 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
 #pragma unroll
         for (int mb = 0; mb < 8; ++mb) sa[mb] = side_sa[sbuf][rb + mb * 16] + 127;
       }
-      nmore = cit.next(p, kMode, nti, ntj);
     }
+    const bool more = lmore;  // a step follows this one
     if (lmore) issue();
     const int st = step % Q::kStages;
     mma_step<kPrec>(acc, lds_ab[st][0], lds_ab[st][1], wm * kWaveM, wn * kWaveN, sa, sb);
@@ -760,10 +798,10 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
     }
     ++step;
     if (++chunk == nsteps) {
-      if (!nmore) break;
+      if (!more) break;
       chunk = 0;
-      ti = nti;
-      tj = ntj;
+      ti = iti;  // the step just issued opens the next tile
+      tj = itj;
       ++ctile;
     }
   }
@@ -799,6 +837,17 @@ static int group_rows(int64_t qld, int64_t nTR) {
   return (int)gm;
 }
 
+// Multiplier and shifts for udiv32 by d >= 1 (Granlund and Montgomery):
+// l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1, s1 = min(l, 1),
+// s2 = max(l - 1, 0); exact for every 32-bit dividend.
+static void div_magic(uint32_t d, uint32_t& m, uint32_t& s1, uint32_t& s2) {
+  uint32_t l = 0;
+  while (l < 32 && (1ull << l) < d) ++l;
+  m = (uint32_t)(((((1ull << l) - d) << 32) / d) + 1);
+  s1 = l < 1 ? l : 1;
+  s2 = l > 1 ? l - 1 : 0;
+}
+
 hipError_t launch_cand_eps(dl_prec prec, CandParams p, hipStream_t st, int cu_count) {
   p.nTR = (p.nR + kTile - 1) / kTile;
   p.nTS = (p.nS + kTile - 1) / kTile;
@@ -810,6 +859,15 @@ hipError_t launch_cand_eps(dl_prec prec, CandParams p, hipStream_t st, int cu_co
     p.nlogical = (int64_t)p.GM * (g * p.nTR - (int64_t)p.GM * g * (g - 1) / 2);
   } else {
     p.nlogical = p.nTR * p.nTS;
+  }
+  // logical indices, offsets and group sizes all below 2^32 - 2^24 (room for
+  // the rounds past the end): 32-bit tile-order arithmetic
+  p.small32 = p.nlogical + 8 * (int64_t)cu_count < (1ll << 32) - (1ll << 24) &&
+              (int64_t)p.GM * (p.self_join ? p.nTR : p.nTS) < (1ll << 31);
+  if (p.small32) {
+    div_magic((uint32_t)(p.GM * p.nTS), p.dv_grp_m, p.dv_grp_s1, p.dv_grp_s2);
+    div_magic((uint32_t)p.GM, p.dv_gm_m, p.dv_gm_s1, p.dv_gm_s2);
+    div_magic((uint32_t)(p.nTR - (p.ngroups - 1) * p.GM), p.dv_gl_m, p.dv_gl_s1, p.dv_gl_s2);
   }
   int64_t G = cu_count;  // one 512-thread workgroup per CU
   const int64_t need = (p.nlogical + 7) / 8 * 8;

@@ -23,6 +23,12 @@ struct CandParams {
   int GM;              // row tiles per group
   int64_t ngroups;
   int64_t nlogical;    // logical tiles incl. skipped ones
+  // 32-bit division by the tile-order divisors (valid when small32): the
+  // group size GM * nTS, GM, and the last group's height
+  int small32;
+  uint32_t dv_grp_m, dv_grp_s1, dv_grp_s2;
+  uint32_t dv_gm_m, dv_gm_s1, dv_gm_s2;
+  uint32_t dv_gl_m, dv_gl_s1, dv_gl_s2;
   // eps mode
   const float* thr;    // per R row (npadR)
   unsigned long long* ccount;  // candidate counter
