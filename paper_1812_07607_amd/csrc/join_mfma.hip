@@ -298,9 +298,14 @@ __device__ inline void issue_side(const CandParams& p, int64_t ti, int64_t tj, c
 // instructions that consume the register it replaces.  The LDS latency is
 // then paid about once per step instead of once per pair of A fragments,
 // with 64 fragment registers beside the 128 accumulator registers.
-template <int kPrec>
+//
+// kFirst (a tile's first K-step): the first instruction of each block reads
+// its C operand from init[nb] (the block's initial value -h_j, one register
+// quad per column block) and writes the accumulator, so no per-tile copy of
+// the initial values into the 128 accumulator registers is needed.
+template <int kPrec, bool kFirst>
 __device__ inline void mma_step(f32x4 (&acc)[8][4], const uint8_t* la, const uint8_t* lb, int ra0, int rb0,
-                                const int (&sa)[8], const int (&sb)[4]) {
+                                const int (&sa)[8], const int (&sb)[4], const f32x4 (&init)[4]) {
   constexpr int kCB = Pipe<kPrec>::kCB;
   const int lane = threadIdx.x & 63;
   const int r16 = lane & 15, grp = lane >> 4;
@@ -313,15 +318,16 @@ __device__ inline void mma_step(f32x4 (&acc)[8][4], const uint8_t* la, const uin
   if constexpr (kPrec == DL_BF16 || kPrec == DL_FP16 || kPrec == DL_FP32) {
     static_assert(kCB == 128, "two sub-steps of 64 bytes");
     // one block product: 16x16x32 for the 16-bit formats, four 16x16x4 for fp32
-    auto mac = [&](f32x4& c, const uint4& x, const uint4& y) {
+    // c = c0 + x.y (c0 = c, or the initial value on a tile's first sub-step)
+    auto mac = [&](f32x4& c, const f32x4& c0, const uint4& x, const uint4& y) {
       if constexpr (kPrec == DL_BF16) {
         c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, x), __builtin_bit_cast(bf16x8, y),
-                                                    c, 0, 0, 0);
+                                                    c0, 0, 0, 0);
       } else if constexpr (kPrec == DL_FP16) {
-        c = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, x), __builtin_bit_cast(f16x8, y), c,
+        c = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, x), __builtin_bit_cast(f16x8, y), c0,
                                                    0, 0, 0);
       } else {
-        c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(x.x), __uint_as_float(y.x), c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(x.x), __uint_as_float(y.x), c0, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(x.y), __uint_as_float(y.y), c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(x.z), __uint_as_float(y.z), c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(x.w), __uint_as_float(y.w), c, 0, 0, 0);
@@ -337,7 +343,7 @@ __device__ inline void mma_step(f32x4 (&acc)[8][4], const uint8_t* la, const uin
 #pragma unroll
     for (int mb = 0; mb < 8; ++mb) {
 #pragma unroll
-      for (int nb = 0; nb < 4; ++nb) mac(acc[mb][nb], a[mb], b0[nb]);
+      for (int nb = 0; nb < 4; ++nb) mac(acc[mb][nb], kFirst ? init[nb] : acc[mb][nb], a[mb], b0[nb]);
       a[mb] = ldA(mb, 4 + grp);
       if (mb < 4) b1[mb] = ldB(mb, 4 + grp);
       __builtin_amdgcn_sched_group_barrier(0x008, 4 * kPerBlock, 0);  // matrix
@@ -347,7 +353,7 @@ __device__ inline void mma_step(f32x4 (&acc)[8][4], const uint8_t* la, const uin
 #pragma unroll
     for (int mb = 0; mb < 8; ++mb) {
 #pragma unroll
-      for (int nb = 0; nb < 4; ++nb) mac(acc[mb][nb], a[mb], b1[nb]);
+      for (int nb = 0; nb < 4; ++nb) mac(acc[mb][nb], acc[mb][nb], a[mb], b1[nb]);
     }
   } else {
     // E4M3, 128 bytes = 128 values per row: 16x16x128 with per-row E8M0
@@ -366,7 +372,8 @@ __device__ inline void mma_step(f32x4 (&acc)[8][4], const uint8_t* la, const uin
     for (int mb = 0; mb < 8; ++mb) {
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb)
-        acc[mb][nb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[mb & 3], b[nb], acc[mb][nb], 0, 0, 0,
+        acc[mb][nb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[mb & 3], b[nb],
+                                                                      kFirst ? init[nb] : acc[mb][nb], 0, 0, 0,
                                                                       sa[mb], 0, sb[nb]);
       if (mb < 4) a[mb] = ld8(ldA(mb + 4, 2 * grp), ldA(mb + 4, 2 * grp + 1));
       __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
@@ -768,6 +775,7 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
     wait_and_sync(dirty ? 0 : (issued - step - 1) * Q::kPerStep);
     dirty = false;
     const int sbuf = ctile % 3;
+    const bool more = lmore;  // a step follows this one
     if (chunk == 0) {
       if constexpr (!kEps) {
         dirty |= tighten_rows(p, ti, split, band);
@@ -775,22 +783,34 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
       }
       const int l16 = fresh_lane() & 15;
       const int cb = wn * kWaveN + l16, rb = wm * kWaveM + l16;
+      f32x4 init[4];
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb) {
-        const float init = -side_hb[sbuf][cb + nb * 16];
+        const float h0 = -side_hb[sbuf][cb + nb * 16];
+        init[nb] = f32x4{h0, h0, h0, h0};
+        // band mode keeps the copy into the accumulators (measured: reading
+        // C from init on its first step spills in band mode)
+        if constexpr (!kEps) {
 #pragma unroll
-        for (int mb = 0; mb < 8; ++mb) acc[mb][nb] = f32x4{init, init, init, init};
+          for (int mb = 0; mb < 8; ++mb) acc[mb][nb] = init[nb];
+        }
         if constexpr (kFp8) sb[nb] = side_sb[sbuf][cb + nb * 16] + 127;
       }
       if constexpr (kFp8) {
 #pragma unroll
         for (int mb = 0; mb < 8; ++mb) sa[mb] = side_sa[sbuf][rb + mb * 16] + 127;
       }
+      if constexpr (kEps) {
+        if (lmore) issue();
+        const int st = step % Q::kStages;
+        mma_step<kPrec, true>(acc, lds_ab[st][0], lds_ab[st][1], wm * kWaveM, wn * kWaveN, sa, sb, init);
+      }
     }
-    const bool more = lmore;  // a step follows this one
-    if (lmore) issue();
-    const int st = step % Q::kStages;
-    mma_step<kPrec>(acc, lds_ab[st][0], lds_ab[st][1], wm * kWaveM, wn * kWaveN, sa, sb);
+    if (!kEps || chunk != 0) {
+      if (lmore) issue();
+      const int st = step % Q::kStages;
+      mma_step<kPrec, false>(acc, lds_ab[st][0], lds_ab[st][1], wm * kWaveM, wn * kWaveN, sa, sb, acc[0]);
+    }
     if (chunk == nsteps - 1) {
       if constexpr (kEps) dirty |= epilogue_eps(p, ti, tj, acc, side_thr[kEps ? sbuf : 0], lds_eq[kEps ? wave : 0], eq);
       else if (full) dirty |= epilogue_band<true>(p, ti, tj, split, acc, band);
