@@ -80,3 +80,15 @@ def test_histogram_topk(orc):
     got = ops.join_topk(dev(H), None, 5, exclude_self=True, prec="fp16")
     assert_topk_equal(got, ref_j, ref_dist, 512, "histograms")
     assert got.ties == 0  # exact on the 2^-10 grid: no float64 needed
+
+
+@pytest.mark.parametrize("k", [10, 64])
+def test_many_splits_large_union(orc, k):
+    """Few query rows against a long S: the work is split over hundreds of S
+    ranges, so a row's union of band buffers holds thousands of entries (k =
+    10: it is filtered down to registers; k = 64: it stays in memory)."""
+    R = synth.gaussian_mixture_unit(50, 32, 40, seed=31)
+    S = synth.gaussian_mixture_unit(60000, 32, 40, seed=31, stream=1)
+    ref_j, _, ref_dist = orc.topk(R, S, k)
+    got = ops.join_topk(dev(R), dev(S), k, prec="bf16")
+    assert_topk_equal(got, ref_j, ref_dist, 32, "splits k=%d" % k)
