@@ -13,7 +13,7 @@ namespace dl {
 hipError_t launch_hist_rgb8(const uint8_t*, int64_t, int32_t, int32_t, int32_t, float*, hipStream_t, int);
 // prep.hip
 hipError_t launch_prep(const float*, int64_t, int32_t, int64_t, dl_prec, const Prep&, RelStats*, hipStream_t, int);
-hipError_t launch_threshold(const Prep&, int64_t, const RelStats*, int, double, const double*, float*, float*,
+hipError_t launch_threshold(const Prep&, int64_t, const RelStats*, int, double, const double*, float*, float*, int*,
                             hipStream_t);
 }  // namespace dl
 
@@ -76,7 +76,9 @@ struct EpsLayout {
   RelStats *sr, *ss;
   Counters* cnt;
   float* thr;
+  int* pex;
   uint2* cand;
+  float* candp;
   unsigned long long *k0, *k1;
   float *v0, *v1;
   uint32_t *hist, *scan;
@@ -95,8 +97,10 @@ static EpsLayout layout_eps(void* ws, int64_t nR, int64_t nS, int d, dl_prec pre
   L.pr = carve_prep(b, nR, d, prec);
   L.ps = (self || s_ext) ? L.pr : carve_prep(b, nS, d, prec);
   L.thr = b.take<float>(L.pr.npad);
+  L.pex = b.take<int>(L.pr.npad);
   const int64_t c = cap < 1 ? 1 : cap;
   L.cand = b.take<uint2>(c);
+  L.candp = b.take<float>(c);
   L.k0 = b.take<unsigned long long>(c);
   L.k1 = b.take<unsigned long long>(c);
   L.v0 = b.take<float>(c);
@@ -433,7 +437,7 @@ dl_status eps_core(dl_ctx* c, const EpsJob& J, void* ws, size_t ws_bytes, dl_pai
     StageTimer t(c, 1, st);
     DL_HIP(c, launch_prep(R.data, R.n, R.d, R.ld, prec, L.pr, L.sr, st, c->cu_count));
     if (!self && !sx) DL_HIP(c, launch_prep(S.data, S.n, S.d, S.ld, prec, L.ps, L.ss, st, c->cu_count));
-    DL_HIP(c, launch_threshold(L.pr, R.n, L.ss, R.d, J.T, J.Trow, L.thr, nullptr, st));
+    DL_HIP(c, launch_threshold(L.pr, R.n, L.ss, R.d, J.T, J.Trow, L.thr, nullptr, L.pex, st));
   }
   {
     StageTimer t(c, 2, st);
@@ -451,6 +455,7 @@ dl_status eps_core(dl_ctx* c, const EpsJob& J, void* ws, size_t ws_bytes, dl_pai
     p.thr = L.thr;
     p.ccount = &L.cnt->cand;
     p.cand = L.cand;
+    p.candp = prec == DL_FP8 ? nullptr : L.candp;  // E4M3 stages no P~ (LDS budget)
     p.ccap = cap;
     DL_HIP(c, launch_cand_eps(prec, p, st, c->cu_count));
   }
@@ -462,6 +467,9 @@ dl_status eps_core(dl_ctx* c, const EpsJob& J, void* ws, size_t ws_bytes, dl_pai
     q.S = S.data; q.lds = S.ld;
     q.d = R.d;
     q.cand = L.cand; q.ccount = &L.cnt->cand; q.ccap = cap;
+    q.candp = prec == DL_FP8 ? nullptr : L.candp;
+    q.pexR = L.pex;
+    q.nrm2R = L.pr.nrm2;
     q.xnR = L.pr.xnorm; q.mlR = L.pr.mlsb;
     q.xnS = L.ps.xnorm; q.mlS = L.ps.mlsb;
     q.T = J.T;
@@ -531,7 +539,7 @@ dl_status topk_core(dl_ctx* c, const TopkJob& J, void* ws, size_t ws_bytes, uint
     StageTimer t(c, 1, st);
     DL_HIP(c, launch_prep(R.data, R.n, R.d, R.ld, prec, L.pr, L.sr, st, c->cu_count));
     if (!self && !sx) DL_HIP(c, launch_prep(S.data, S.n, S.d, S.ld, prec, L.ps, L.ss, st, c->cu_count));
-    DL_HIP(c, launch_threshold(L.pr, R.n, L.ss, R.d, 0.0, nullptr, nullptr, L.marg, st));
+    DL_HIP(c, launch_threshold(L.pr, R.n, L.ss, R.d, 0.0, nullptr, nullptr, L.marg, nullptr, st));
   }
   if (S.n > 0) {
     StageTimer t(c, 2, st);

@@ -390,7 +390,9 @@ constexpr int kQueue = 256;  // staged hits per wave (eps candidates or band ent
 // Appends a wave's staged (i, j) candidates to the global list: one atomic
 // for the whole batch, then coalesced stores.  Positions past the list's
 // capacity are counted but not written (the caller then retries with room).
-__device__ inline void flush_eps(const CandParams& p, const uint2* q, int nq) {
+// With kP, each record's P~ (qp, staged beside q) goes to p.candp too.
+template <bool kP>
+__device__ inline void flush_eps(const CandParams& p, const uint2* q, const uint32_t* qp, int nq) {
   const int lane = fresh_lane();
   unsigned long long base = 0;
   if (lane == 0) base = atomicAdd(p.ccount, (unsigned long long)nq);
@@ -398,7 +400,11 @@ __device__ inline void flush_eps(const CandParams& p, const uint2* q, int nq) {
          __builtin_amdgcn_readfirstlane((uint32_t)base);
   for (int s = lane; s < nq; s += 64) {
     const unsigned long long pos = base + (unsigned long long)s;
-    if (pos < (unsigned long long)p.ccap) p.cand[pos] = q[s];
+    if (pos < (unsigned long long)p.ccap) {
+      p.cand[pos] = q[s];
+      if constexpr (kP)
+        if (p.candp) p.candp[pos] = __uint_as_float(qp[s]);
+    }
   }
 }
 
@@ -409,10 +415,12 @@ __device__ inline void flush_eps(const CandParams& p, const uint2* q, int nq) {
 // atomics); the queue persists across tiles and goes to global memory only
 // when full and at the end.  Bounds (rows and columns left in the tile) and
 // the self-join's j > i (only on a diagonal tile) are checked in 32-bit
-// tile coordinates, and only on tiles that need them.  Returns whether this
-// wave wrote to global memory.
+// tile coordinates, and only on tiles that need them.  With kP each
+// record's P~ is staged too (qp).  Returns whether this wave wrote to global
+// memory.
+template <bool kP>
 __device__ inline bool epilogue_eps(const CandParams& p, int64_t ti, int64_t tj, const f32x4 (&acc)[8][4],
-                                    const float* thr_tile, uint2* q, int& nq) {
+                                    const float* thr_tile, uint2* q, uint32_t* qp, int& nq) {
   const int lane = fresh_lane(), wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wm = wave >> 2, wn = wave & 3;
   const int lrow0 = wm * kWaveM + 4 * (lane >> 4);
@@ -458,13 +466,17 @@ __device__ inline bool epilogue_eps(const CandParams& p, int64_t ti, int64_t tj,
         tot += __popcll(m[nb]);
       }
       if (nq + tot > kQueue) {
-        flush_eps(p, q, nq);
+        flush_eps<kP>(p, q, qp, nq);
         nq = 0;
         wrote = true;
       }
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb) {
-        if (hit[nb]) q[nq + __popcll(m[nb] & lt)] = make_uint2(i0 + (uint32_t)lr, j0 + (uint32_t)(lcol0 + nb * 16));
+        if (hit[nb]) {
+          const int at = nq + __popcll(m[nb] & lt);
+          q[at] = make_uint2(i0 + (uint32_t)lr, j0 + (uint32_t)(lcol0 + nb * 16));
+          if constexpr (kP) qp[at] = __float_as_uint(acc[mb][nb][r]);
+        }
         nq += __popcll(m[nb]);
       }
     }
@@ -712,6 +724,9 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
   __shared__ __attribute__((aligned(16))) uint8_t lds_band_raw[kEps ? 16 : sizeof(BandLds)];
   BandLds& band = *reinterpret_cast<BandLds*>(lds_band_raw);
   __shared__ __attribute__((aligned(16))) uint2 lds_eq[kEps ? kThreads / 64 : 1][kEps ? kQueue : 1];
+  // eps, except E4M3 (LDS budget): the staged candidates' P~
+  constexpr bool kStageP = kEps && !kFp8;
+  __shared__ uint32_t lds_eqp[kStageP ? kThreads / 64 : 1][kStageP ? kQueue : 1];
 
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wm = wave >> 2, wn = wave & 3;
@@ -812,7 +827,9 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
       mma_step<kPrec, false>(acc, lds_ab[st][0], lds_ab[st][1], wm * kWaveM, wn * kWaveN, sa, sb, acc[0]);
     }
     if (chunk == nsteps - 1) {
-      if constexpr (kEps) dirty |= epilogue_eps(p, ti, tj, acc, side_thr[kEps ? sbuf : 0], lds_eq[kEps ? wave : 0], eq);
+      if constexpr (kEps)
+        dirty |= epilogue_eps<kStageP>(p, ti, tj, acc, side_thr[kEps ? sbuf : 0], lds_eq[kEps ? wave : 0],
+                                       lds_eqp[kStageP ? wave : 0], eq);
       else if (full) dirty |= epilogue_band<true>(p, ti, tj, split, acc, band);
       else dirty |= epilogue_band<false>(p, ti, tj, split, acc, band);
     }
@@ -826,7 +843,7 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
     }
   }
   if constexpr (kEps) {
-    if (eq) flush_eps(p, lds_eq[wave], eq);
+    if (eq) flush_eps<kStageP>(p, lds_eq[wave], lds_eqp[kStageP ? wave : 0], eq);
   } else {
     __syncthreads();
     tighten_rows(p, ti, split, band);

@@ -33,6 +33,7 @@ struct CandParams {
   const float* thr;    // per R row (npadR)
   unsigned long long* ccount;  // candidate counter
   uint2* cand;         // (i, j) records
+  float* candp;        // P~ of each record (null: not kept)
   int64_t ccap;
   // band mode
   int P;               // S splits
@@ -52,6 +53,9 @@ struct RecheckParams {
   const float* S; int64_t lds;
   int d;
   const uint2* cand; const unsigned long long* ccount; int64_t ccap;
+  const float* candp;   // P~ of each candidate, or null
+  const int* pexR;      // per R row: the candidate pass computed P~ exactly
+  const double* nrm2R;  // |a|^2 per R row (float64)
   const float* xnR; const int* mlR;
   const float* xnS; const int* mlS;
   double T;

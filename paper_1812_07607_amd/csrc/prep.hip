@@ -168,7 +168,10 @@ __global__ __launch_bounds__(256) void stats_reduce_kernel(Prep P, int64_t n, Re
 //   operands      |q~_i| max rho_j + rho_i max|q~_j| + rho_i max rho_j;
 //   init          max | |b|^2/2 - h_j |;
 //   float64       (d+4) 2^-52 ((|a| + max|b|)^2 + |a|^2).
-__device__ inline double row_margin(const Prep& R, const RelStats& s, int64_t i, int d) {
+// pass_exact (optional): set when the candidate pass computes P~ for row i
+// exactly, i.e. P~ = a.b - |b|^2/2 for every b of S: operand copies equal to
+// the rows (rho = 0), h exact and an exact accumulation.
+__device__ inline double row_margin(const Prep& R, const RelStats& s, int64_t i, int d, bool* pass_exact = nullptr) {
   const double qa = R.qnorm[i], ra = R.rho[i];
   const int ql = R.qlsb[i];
   const int prod = (ql >= kLsbNone || s.qlsb_min >= kLsbNone) ? kLsbNone : ql + s.qlsb_min;
@@ -178,6 +181,15 @@ __device__ inline double row_margin(const Prep& R, const RelStats& s, int64_t i,
                            : 2.0 * gamma_n((double)d + 2.0, 0x1p-24) * ((double)s.h_max + qa * s.qnorm_max) +
                                  ((double)d + 1.0) * 0x1p-126;
   const double opnd = qa * s.rho_max + ra * s.qnorm_max + ra * s.rho_max;
+  if (pass_exact) {
+    // h_j = |b_j|^2 / 2 exactly for every b of S: S on the grid 2^m with
+    // |b|^2 <= 2^(2m+24) (its squares and sums are exact in float32 and
+    // float64 alike); dh itself always carries the float64 sum's bound
+    const bool h_exact = s.mlsb_min >= kLsbNone ||
+                         (2 * s.mlsb_min >= -126 &&
+                          (double)s.xnorm_max * (double)s.xnorm_max <= ldexp(1.0, 2 * s.mlsb_min + 24));
+    *pass_exact = exact && ra == 0.0 && s.rho_max == 0.0f && h_exact;
+  }
   const double xa = R.xnorm[i], xs = s.xnorm_max;
   const double canon = ((double)d + 4.0) * 0x1p-52 * ((xa + xs) * (xa + xs) + R.nrm2[i]);
   return (2.0 * (acc + opnd + (double)s.dh_max) + canon) * (1.0 + 0x1p-40);
@@ -187,16 +199,20 @@ __device__ inline double row_margin(const Prep& R, const RelStats& s, int64_t i,
 // band mode: marg_i = E_i rounded up (the top-k band is P~ >= P~_(k) - E_i).
 __global__ __launch_bounds__(256) void threshold_kernel(Prep R, int64_t nR, const RelStats* __restrict__ S,
                                                         int d, double Tall, const double* __restrict__ Trow,
-                                                        float* __restrict__ thr, float* __restrict__ marg) {
+                                                        float* __restrict__ thr, float* __restrict__ marg,
+                                                        int* __restrict__ pex) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= R.npad) return;
   if (i >= nR) {
     if (thr) thr[i] = INFINITY;
     if (marg) marg[i] = 0.0f;
+    if (pex) pex[i] = 0;
     return;
   }
   const RelStats s = *S;
-  const double E = row_margin(R, s, i, d);
+  bool px = false;
+  const double E = row_margin(R, s, i, d, &px);
+  if (pex) pex[i] = px ? 1 : 0;
   if (marg) marg[i] = f32_up(E);
   if (thr) {
     const double T = Trow ? Trow[i] : Tall;
@@ -226,9 +242,9 @@ hipError_t launch_prep(const float* X, int64_t n, int32_t d, int64_t ld, dl_prec
 }
 
 hipError_t launch_threshold(const Prep& R, int64_t nR, const RelStats* S, int d, double T, const double* Trow,
-                            float* thr, float* marg, hipStream_t st) {
+                            float* thr, float* marg, int* pex, hipStream_t st) {
   const dim3 grid((unsigned)((R.npad + 255) / 256));
-  hipLaunchKernelGGL(threshold_kernel, grid, dim3(256), 0, st, R, nR, S, d, T, Trow, thr, marg);
+  hipLaunchKernelGGL(threshold_kernel, grid, dim3(256), 0, st, R, nR, S, d, T, Trow, thr, marg, pex);
   return hipGetLastError();
 }
 

@@ -49,59 +49,99 @@ __device__ inline double beta32(double d2, int d, double xsum) {
 
 // A wave takes 64 candidates at a time: it computes their float32 distances
 // one after the other with all lanes (coalesced row reads), lane t keeping
-// candidate t's sum, then classifies the 64 lane-parallel and appends the
-// confirmed ones with a single atomic.
+// candidate t's sum, then classifies the 64 lane-parallel; the confirmed
+// ones of kRecheckChunks such batches are appended with a single atomic (one
+// counter serves the whole grid, so its atomics are kept few).  A candidate
+// whose P~ the matrix-core pass computed exactly (pexR) and whose float32
+// form is exact (the lowest-set-bit certificate) needs no row reads: then
+// d2 = |a|^2 - 2 P~ exactly (P~ = a.b - |b|^2/2), evaluated in float64
+// without rounding.
+constexpr int kRecheckChunks = 4;  // 64-candidate chunks per wave and output atomic
+
 __global__ __launch_bounds__(256) void recheck_eps_kernel(RecheckParams p) {
   const int lane = threadIdx.x & 63;
   const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
   const int64_t n = min((int64_t)*p.ccount, p.ccap);
   const uint64_t lt = __lanemask_lt();
-  for (int64_t base = gw * 64; base < n; base += nw * 64) {
-    const int cnt = (int)min((int64_t)64, n - base);
-    const uint2 mine = lane < cnt ? p.cand[base + lane] : make_uint2(0, 0);
-    float mys = 0.0f;
-    for (int t = 0; t < cnt; ++t) {
-      const uint32_t ci = __shfl(mine.x, t, 64), cj = __shfl(mine.y, t, 64);
-      const float* a = p.R + (int64_t)ci * p.ldr;
-      const float* b = p.S + (int64_t)cj * p.lds;
-      float s = 0.0f;
-      for (int k = lane; k < p.d; k += 64) {
-        const float u = a[k] - b[k];
-        s = fmaf(u, u, s);
+  constexpr int64_t kSpan = 64 * kRecheckChunks;
+  for (int64_t base0 = gw * kSpan; base0 < n; base0 += nw * kSpan) {
+    bool in[kRecheckChunks], tie[kRecheckChunks];
+    float dist[kRecheckChunks];
+    uint2 mine[kRecheckChunks];
+#pragma unroll
+    for (int c = 0; c < kRecheckChunks; ++c) {
+      const int64_t base = base0 + c * 64;
+      const int cnt = (int)max((int64_t)0, min((int64_t)64, n - base));
+      mine[c] = lane < cnt ? p.cand[base + lane] : make_uint2(0, 0);
+      float mys = 0.0f;
+      bool quick = false;  // d2 from P~ (see above)
+      if (lane < cnt && p.candp && p.pexR[mine[c].x]) {
+        const double xs = (double)p.xnR[mine[c].x] + (double)p.xnS[mine[c].y];
+        if (exact32(min(p.mlR[mine[c].x], p.mlS[mine[c].y]), xs)) {
+          quick = true;
+          mys = (float)(p.nrm2R[mine[c].x] - 2.0 * (double)p.candp[base + lane]);
+        }
       }
-      s = wave_sumf(s);
-      if (lane == t) mys = s;
-    }
-    bool in = false, tie = false;
-    float dist = 0.0f;
-    if (lane < cnt) {
-      const double d2 = mys;
-      const double xsum = (double)p.xnR[mine.x] + (double)p.xnS[mine.y];
-      const bool ex = exact32(min(p.mlR[mine.x], p.mlS[mine.y]), xsum);
-      const double bt = ex ? 0.0 : beta32(d2, p.d, xsum);
-      const double hi = ex ? d2 : (d2 + bt) * (1.0 + 0x1p-50);
-      const double lo = ex ? d2 : (d2 - bt) * (1.0 - 0x1p-50);
-      const double T = p.Trow ? p.Trow[mine.x] : p.T;
-      in = hi <= T;
-      dist = sqrtf(mys);
-      if (!in && !(lo > T)) {  // boundary tie: the canonical float64 value decides
-        tie = true;
-        const double d64 = canonical_d2(p.R + (int64_t)mine.x * p.ldr, p.S + (int64_t)mine.y * p.lds, p.d);
-        in = d64 <= T;
-        dist = (float)sqrt(d64);
+      const uint64_t slow = __ballot(lane < cnt && !quick);
+      for (uint64_t rest = slow; rest; rest &= rest - 1) {
+        const int t = __ffsll((unsigned long long)rest) - 1;
+        const uint32_t ci = __shfl(mine[c].x, t, 64), cj = __shfl(mine[c].y, t, 64);
+        const float* a = p.R + (int64_t)ci * p.ldr;
+        const float* b = p.S + (int64_t)cj * p.lds;
+        float s = 0.0f;
+        for (int k = lane; k < p.d; k += 64) {
+          const float u = a[k] - b[k];
+          s = fmaf(u, u, s);
+        }
+        s = wave_sumf(s);
+        if (lane == t) mys = s;
+      }
+      in[c] = false;
+      tie[c] = false;
+      dist[c] = 0.0f;
+      if (lane < cnt) {
+        const double d2 = mys;
+        const double xsum = (double)p.xnR[mine[c].x] + (double)p.xnS[mine[c].y];
+        const bool ex = exact32(min(p.mlR[mine[c].x], p.mlS[mine[c].y]), xsum);
+        const double bt = ex ? 0.0 : beta32(d2, p.d, xsum);
+        const double hi = ex ? d2 : (d2 + bt) * (1.0 + 0x1p-50);
+        const double lo = ex ? d2 : (d2 - bt) * (1.0 - 0x1p-50);
+        const double T = p.Trow ? p.Trow[mine[c].x] : p.T;
+        in[c] = hi <= T;
+        dist[c] = sqrtf(mys);
+        if (!in[c] && !(lo > T)) {  // boundary tie: the canonical float64 value decides
+          tie[c] = true;
+          const double d64 = canonical_d2(p.R + (int64_t)mine[c].x * p.ldr, p.S + (int64_t)mine[c].y * p.lds, p.d);
+          in[c] = d64 <= T;
+          dist[c] = (float)sqrt(d64);
+        }
       }
     }
-    const uint64_t mi = __ballot(in), mt = __ballot(tie);
+    // one atomic for the whole span
+    uint64_t mi[kRecheckChunks];
+    int total = 0, nt = 0;
+#pragma unroll
+    for (int c = 0; c < kRecheckChunks; ++c) {
+      mi[c] = __ballot(in[c]);
+      total += __popcll(mi[c]);
+      nt += __popcll(__ballot(tie[c]));
+    }
+    if (total == 0 && nt == 0) continue;
     unsigned long long pos = 0;
     if (lane == 0) {
-      if (mi) pos = atomicAdd(p.ocount, (unsigned long long)__popcll(mi));
-      if (mt) atomicAdd(p.nties, (unsigned long long)__popcll(mt));
+      if (total) pos = atomicAdd(p.ocount, (unsigned long long)total);
+      if (nt) atomicAdd(p.nties, (unsigned long long)nt);
     }
-    pos = __shfl(pos, 0, 64) + __popcll(mi & lt);
-    if (in && pos < (unsigned long long)p.ccap) {
-      p.keys[pos] = ((unsigned long long)mine.x << p.bj) | mine.y;
-      p.dist[pos] = dist;
+    pos = __shfl(pos, 0, 64);
+#pragma unroll
+    for (int c = 0; c < kRecheckChunks; ++c) {
+      const unsigned long long at = pos + __popcll(mi[c] & lt);
+      if (in[c] && at < (unsigned long long)p.ccap) {
+        p.keys[at] = ((unsigned long long)mine[c].x << p.bj) | mine[c].y;
+        p.dist[at] = dist[c];
+      }
+      pos += __popcll(mi[c]);
     }
   }
 }
