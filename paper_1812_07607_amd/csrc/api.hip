@@ -382,20 +382,31 @@ dl_status dl_pair_d2(dl_ctx* c, dl_mat R, dl_mat S, const uint32_t* pi, const ui
 // Shared by the plain calls, the store calls and the server.
 namespace dl {
 
-static int band_cap_of(int32_t band_cap, int k) {
-  if (band_cap <= 0) band_cap = 512;
-  band_cap = (int32_t)round_up(band_cap < 512 ? 512 : band_cap, 64);
+// Band entries per (row, split).  A workgroup that runs through more than
+// two S tiles defers tightening (rows are tightened in batches, one per
+// wave), which needs room for two more tiles above the trigger ceiling, so
+// its default buffer is twice as large.
+static bool band_defers(int band_cap, int k, int64_t tps) { return tps > 2 && band_cap >= 2 * k + 2 * kTile; }
+
+static int band_cap_of(int32_t band_cap, int k, int64_t tps) {
+  if (band_cap <= 0) band_cap = tps > 2 ? 1024 : 512;
+  band_cap = (int32_t)round_up(band_cap, 64);
   if (band_cap < 2 * k + kTile) band_cap = (int32_t)round_up(2 * k + kTile, 64);
   return band_cap;
+}
+
+// Highest count a row's trigger may be armed at: one tile (two when
+// tightening is deferred) below the buffer's end.
+static int band_limit_of(int band_cap, int k, int64_t tps) {
+  return band_cap - (band_defers(band_cap, k, tps) ? 2 : 1) * kTile;
 }
 
 // Entries a row's band buffer grows by before it is tightened again: often
 // enough that the running threshold follows the k-th best seen so far
 // (fewer hits per tile), rarely enough that selection does not dominate.
-static int retight_of(int k, int band_cap) {
+static int retight_of(int k, int limit) {
   int x = 4 * k < 64 ? 64 : 4 * k;
-  if (x > band_cap - kTile) x = band_cap - kTile;
-  return x;
+  return x > limit ? limit : x;
 }
 
 size_t eps_workspace(int64_t nR, int64_t nS, int d, dl_prec prec, bool self, bool s_ext, int64_t cap) {
@@ -404,8 +415,9 @@ size_t eps_workspace(int64_t nR, int64_t nS, int d, dl_prec prec, bool self, boo
 
 size_t topk_workspace(int64_t nR, int64_t nS, int d, dl_prec prec, bool self, bool s_ext, int k, int band_cap,
                       int cu) {
-  const int P = topk_splits(nR, nS, cu, nullptr);
-  return layout_topk(nullptr, nR, nS, d, prec, self, P, band_cap_of(band_cap, k), s_ext).bytes;
+  int64_t tps = 1;
+  const int P = topk_splits(nR, nS, cu, &tps);
+  return layout_topk(nullptr, nR, nS, d, prec, self, P, band_cap_of(band_cap, k, tps), s_ext).bytes;
 }
 
 dl_status eps_core(dl_ctx* c, const EpsJob& J, void* ws, size_t ws_bytes, dl_pairs* out, hipStream_t st) {
@@ -512,10 +524,10 @@ dl_status topk_core(dl_ctx* c, const TopkJob& J, void* ws, size_t ws_bytes, uint
   const bool excl = self && J.excl;
   const dl_prec prec = J.prec;
   const int k = J.k;
-  const int band_cap = band_cap_of(J.band_cap, k);
   if (info) info->band_entries = info->ties = 0;
   int64_t tps = 1;
   const int P = topk_splits(R.n, S.n, c->cu_count, &tps);
+  const int band_cap = band_cap_of(J.band_cap, k, tps);
   const size_t need = layout_topk(nullptr, R.n, S.n, R.d, prec, self, P, band_cap, sx).bytes;
   if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(c, DL_ERR_INVALID, "workspace is not 256-byte aligned");
   if (!ws || ws_bytes < need) {
@@ -558,7 +570,9 @@ dl_status topk_core(dl_ctx* c, const TopkJob& J, void* ws, size_t ws_bytes, uint
     p.P = P;
     p.k = k;
     p.cap = band_cap;
-    p.retight = retight_of(k, band_cap);
+    p.limit = band_limit_of(band_cap, k, tps);
+    p.batch = band_defers(band_cap, k, tps) ? 8 : 1;  // one row per wave of the workgroup
+    p.retight = retight_of(k, p.limit);
     p.marg = L.marg;
     p.band = L.band;
     p.bcount = L.bcount;

@@ -563,6 +563,7 @@ struct BandLds {
   int cnt[kTile];
   int trig[kTile];
   int list[kTile + 1];
+  int urgent;  // a row came within two tiles of the buffer's end
   uint2 q[kThreads / 64][kQueue];  // (P~ bits, row << 8 | column in tile)
 };
 
@@ -579,6 +580,7 @@ __device__ inline void flush_band(const CandParams& p, int64_t ti, int64_t tj, i
       const int lr = (int)(h.y >> 8);
       const int pos = atomicAdd(&L.cnt[lr], 1);
       if (pos == L.trig[lr]) L.list[1 + atomicAdd(&L.list[0], 1)] = lr;
+      if (pos == p.limit) L.urgent = 1;
       if (pos < p.cap) {
         const int64_t i = ti * kTile + lr;
         p.band[(i * p.P + split) * (int64_t)p.cap + pos] =
@@ -662,18 +664,23 @@ __device__ inline bool epilogue_band(const CandParams& p, int64_t ti, int64_t tj
 }
 
 // Rows queued by the band epilogue are tightened by one wave each and their
-// triggers re-armed retight entries further on (capped at cap - 256, which
-// keeps room for one more tile); called by the whole workgroup right after a
-// barrier, so list[0] is uniform, and only at the first K-chunk of a tile,
-// where the accumulators are dead (queued rows are still tightened before
-// the next epilogue appends).
+// triggers re-armed retight entries further on (capped at limit).  A round
+// waits until batch rows are queued, unless some row has reached limit
+// entries.  The host sets limit = cap - 256 when every queued row is
+// tightened at once (batch 1), else cap - 512: a tile adds at most 256
+// entries to a row, so every row still has room for one more tile when the
+// round runs.  Called
+// by the whole workgroup right after a barrier, so list[0] and urgent are
+// uniform, and only at the first K-chunk of a tile, where the accumulators
+// are dead; at the end of the workgroup's tiles every queued row is
+// tightened (drain).
 // Returns whether any row was tightened (then the workgroup wrote to global
 // memory).
-__device__ inline bool tighten_rows(const CandParams& p, int64_t ti, int64_t split, BandLds& L) {
+__device__ inline bool tighten_rows(const CandParams& p, int64_t ti, int64_t split, BandLds& L, bool drain) {
   const int nq = L.list[0];
-  if (nq == 0) return false;
+  if (nq == 0 || (!drain && nq < p.batch && !L.urgent)) return false;
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int limit = p.cap - kTile;
+  const int limit = p.limit;
   for (int t = wave; t < nq; t += kThreads / 64) {
     const int lr = L.list[1 + t];
     const int64_t i = ti * kTile + lr;
@@ -686,7 +693,10 @@ __device__ inline bool tighten_rows(const CandParams& p, int64_t ti, int64_t spl
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) L.list[0] = 0;
+  if (threadIdx.x == 0) {
+    L.list[0] = 0;
+    L.urgent = 0;
+  }
   __syncthreads();
   return true;
 }
@@ -768,9 +778,12 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
     for (int r = threadIdx.x; r < kTile; r += kThreads) {
       band.thr[r] = -INFINITY;
       band.cnt[r] = 0;
-      band.trig[r] = min(p.retight, p.cap - kTile);
+      band.trig[r] = p.retight;
     }
-    if (threadIdx.x == 0) band.list[0] = 0;
+    if (threadIdx.x == 0) {
+      band.list[0] = 0;
+      band.urgent = 0;
+    }
   }
   for (int s = 0; s < Q::kStages - 1 && lmore; ++s) issue();
 
@@ -793,7 +806,7 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
     const bool more = lmore;  // a step follows this one
     if (chunk == 0) {
       if constexpr (!kEps) {
-        dirty |= tighten_rows(p, ti, split, band);
+        dirty |= tighten_rows(p, ti, split, band, false);
         full = (ti + 1) * kTile <= p.nR && (tj + 1) * kTile <= p.nS && !(p.exclude_self && ti == tj);
       }
       const int l16 = fresh_lane() & 15;
@@ -846,7 +859,7 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
     if (eq) flush_eps<kStageP>(p, lds_eq[wave], lds_eqp[kStageP ? wave : 0], eq);
   } else {
     __syncthreads();
-    tighten_rows(p, ti, split, band);
+    tighten_rows(p, ti, split, band, true);
     for (int r = threadIdx.x; r < kTile; r += kThreads) {
       const int64_t i = ti * kTile + r;
       if (i < p.nR) p.bcount[i * p.P + split] = min(band.cnt[r], p.cap);

@@ -41,6 +41,8 @@ struct CandParams {
   int k;
   int cap;             // band entries per (row, split)
   int retight;         // entries appended to a row between tightenings
+  int limit;           // highest trigger; a count reaching it forces a round
+  int batch;           // queued rows that start a tightening round
   const float* marg;   // E_i per R row
   uint2* band;         // (P~ bits, j): [(row * P + split) * cap + slot]
   int* bcount;         // [row * P + split]
