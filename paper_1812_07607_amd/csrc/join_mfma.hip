@@ -495,13 +495,43 @@ __device__ inline float key_float(uint32_t k) {
 constexpr int kSelPerLane = 8;  // entries per lane in the k-selection subset
 constexpr int kSelBits = 24;    // key bits resolved by the selection
 
+// Wave-wide comparison masks straight from the vector compare (lane l's bit
+// is set when its comparison holds; inactive lanes read 0).  Written with
+// the compare builtins rather than a ballot of a bool, which the compiler
+// lowers through a per-lane 0/1 value and a second compare.
+constexpr int kCmpUGE = 35;  // unsigned >=
+constexpr int kCmpOGE = 3;   // ordered >= (false for NaN)
+__device__ inline uint64_t mask_ge(uint32_t a, uint32_t b) { return __builtin_amdgcn_uicmp(a, b, kCmpUGE); }
+__device__ inline uint64_t mask_ge(float a, float b) { return __builtin_amdgcn_fcmpf(a, b, kCmpOGE); }
+// lanes below n (n uniform)
+__device__ inline uint64_t lanes_below(int n) {
+  return n >= 64 ? ~0ull : n <= 0 ? 0ull : (1ull << n) - 1ull;
+}
+
+// Largest key prefix (top kSelBits bits) with at least k of the first
+// 64 * kT keys at or above it: one bit per step, each step a few compares
+// whose masks are counted on the scalar unit.
+template <int kT>
+__device__ inline uint32_t kth_key(const uint32_t (&key)[kSelPerLane], int k) {
+  uint32_t kk = 0;
+  for (int b = 31; b >= 32 - kSelBits; --b) {
+    const uint32_t cand = kk | (1u << b);
+    int c = 0;
+#pragma unroll
+    for (int t = 0; t < kT; ++t) c += __popcll(mask_ge(key[t], cand));
+    if (c >= k) kk = cand;
+  }
+  return kk;
+}
+
 // Tighten one row's band and drop what falls below it (one wave).  The new
 // threshold is v - E_i where v is a lower bound of the k-th largest P~ of
 // the first 64 * kSelPerLane entries (the k-th largest of a subset is at
 // most that of the whole buffer, so the band stays a superset of the exact
 // one): the largest key, resolved to its top kSelBits bits, with at least k
-// entries at or above it.  Counting uses ballots, so every step is scalar.
-// Returns the entries kept; the caller re-arms the row's trigger.
+// entries at or above it.  Counting uses compare masks, so every step is
+// scalar; only the blocks of 64 that hold entries are counted.  n is
+// uniform.  Returns the entries kept; the caller re-arms the row's trigger.
 // Scalar arguments only (a reference to the kernel's parameter block would
 // force the block into scratch memory).
 __device__ inline int compact_row(uint2* e, int n, float marg, float* bthr, int k) {
@@ -518,37 +548,26 @@ __device__ inline int compact_row(uint2* e, int n, float marg, float* bthr, int 
     uint32_t key[kSelPerLane];
 #pragma unroll
     for (int t = 0; t < kSelPerLane; ++t) key[t] = (t * 64 + lane) < m ? order_key(__uint_as_float(v[t].x)) : 0u;
-    uint32_t kk = 0;  // largest prefix with at least k entries >= it
-    for (int b = 31; b >= 32 - kSelBits; --b) {
-      const uint32_t cand = kk | (1u << b);
-      int c = 0;
-#pragma unroll
-      for (int t = 0; t < kSelPerLane; ++t) c += __popcll(__ballot(key[t] >= cand));
-      if (c >= k) kk = cand;
-    }
+    const int tm = (m + 63) >> 6;
+    const uint32_t kk = tm <= 2 ? kth_key<2>(key, k) : tm <= 4 ? kth_key<4>(key, k) : kth_key<8>(key, k);
     thr = fmaxf(thr, f32_down((double)key_float(kk) - (double)marg));
   }
-  const uint64_t lt = __lanemask_lt();
+  const uint64_t lt = __lanemask_lt(), lbit = 1ull << lane;
   int w = 0;
   // the first entries come from registers; later ones (a buffer larger than
   // the subset) are read block by block before any write can reach them
 #pragma unroll
   for (int t = 0; t < kSelPerLane; ++t) {
-    const bool keep = (t * 64 + lane) < m && __uint_as_float(v[t].x) >= thr;
-    const uint64_t mm = __ballot(keep);
-    if (keep) e[w + __popcll(mm & lt)] = v[t];
+    if (t * 64 >= m) break;
+    const uint64_t mm = mask_ge(__uint_as_float(v[t].x), thr) & lanes_below(m - t * 64);
+    if (mm & lbit) e[w + __popcll(mm & lt)] = v[t];
     w += __popcll(mm);
   }
   for (int base = m; base < n; base += 64) {
     const int s = base + lane;
-    uint2 x = make_uint2(0, 0);
-    bool keep = false;
-    if (s < n) {
-      x = e[s];
-      keep = __uint_as_float(x.x) >= thr;
-    }
-    const uint64_t mm = __ballot(keep);
-    if (keep) e[w + __popcll(mm & lt)] = x;
+    const uint2 x = s < n ? e[s] : make_uint2(0xff800000u, 0);
+    const uint64_t mm = mask_ge(__uint_as_float(x.x), thr) & lanes_below(n - base);
+    if (mm & lbit) e[w + __popcll(mm & lt)] = x;
     w += __popcll(mm);
   }
   if (lane == 0) *bthr = thr;
@@ -606,7 +625,7 @@ __device__ inline bool epilogue_band(const CandParams& p, int64_t ti, int64_t tj
   const int wm = wave >> 2, wn = wave & 3;
   const int lrow0 = wm * kWaveM + 4 * (lane >> 4);
   const int lcol0 = wn * kWaveN + (lane & 15);
-  const uint64_t lt = __lanemask_lt();
+  const uint64_t lt = __lanemask_lt(), lbit = lt + 1;
   uint2* q = L.q[wave];
   int nq = 0;
   bool wrote = false;
@@ -627,16 +646,14 @@ __device__ inline bool epilogue_band(const CandParams& p, int64_t ti, int64_t tj
     const float tv[4] = {th.x, th.y, th.z, th.w};
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      bool hit[4];
       uint64_t m[4];
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb) {
-        hit[nb] = acc[mb][nb][r] >= tv[r];
+        m[nb] = mask_ge(acc[mb][nb][r], tv[r]);
         if constexpr (!kFull) {
           const int lr = lrow0 + mb * 16 + r, lc = lcol0 + nb * 16;
-          hit[nb] = hit[nb] && lr < rrem && lc < crem && !(diag && lr == lc);
+          m[nb] &= __builtin_amdgcn_ballot_w64(lr < rrem && lc < crem && !(diag && lr == lc));
         }
-        m[nb] = __ballot(hit[nb]);
       }
       if (!(m[0] | m[1] | m[2] | m[3])) continue;
       // one capacity check per slot keeps the flush code at 32 sites
@@ -648,7 +665,7 @@ __device__ inline bool epilogue_band(const CandParams& p, int64_t ti, int64_t tj
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb) {
         if (m[nb]) {
-          if (hit[nb])
+          if (m[nb] & lbit)
             q[nq + __popcll(m[nb] & lt)] =
                 make_uint2(__float_as_uint(acc[mb][nb][r]), tag0 + (uint32_t)(((mb * 16 + r) << 8) + nb * 16));
           nq += __popcll(m[nb]);
@@ -677,14 +694,16 @@ __device__ inline bool epilogue_band(const CandParams& p, int64_t ti, int64_t tj
 // Returns whether any row was tightened (then the workgroup wrote to global
 // memory).
 __device__ inline bool tighten_rows(const CandParams& p, int64_t ti, int64_t split, BandLds& L, bool drain) {
-  const int nq = L.list[0];
-  if (nq == 0 || (!drain && nq < p.batch && !L.urgent)) return false;
+  // LDS values that are the same in every lane are read into scalars, so
+  // that the loops below are uniform
+  const int nq = __builtin_amdgcn_readfirstlane(L.list[0]);
+  if (nq == 0 || (!drain && nq < p.batch && !__builtin_amdgcn_readfirstlane(L.urgent))) return false;
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int limit = p.limit;
   for (int t = wave; t < nq; t += kThreads / 64) {
-    const int lr = L.list[1 + t];
+    const int lr = __builtin_amdgcn_readfirstlane(L.list[1 + t]);
     const int64_t i = ti * kTile + lr;
-    const int n = min(L.cnt[lr], p.cap);
+    const int n = __builtin_amdgcn_readfirstlane(min(L.cnt[lr], p.cap));
     const int w = compact_row(p.band + ((i * p.P) + split) * (int64_t)p.cap, n, p.marg[i], &L.thr[lr], p.k);
     if (lane == 0) {
       L.cnt[lr] = w;
