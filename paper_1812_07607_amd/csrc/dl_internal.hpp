@@ -58,6 +58,21 @@ inline int64_t dpad_of(int d, dl_prec p) {
 // of Numerical Algorithms, Lemma 3.1).
 __host__ __device__ inline double gamma_n(double n, double u) { return n * u / (1.0 - n * u); }
 
+// Wave-wide comparison masks straight from the vector compare (lane l's bit
+// is set when its comparison holds; inactive lanes read 0).  Written with
+// the compare builtins rather than a ballot of a bool, which the compiler
+// lowers through a per-lane 0/1 value and a second compare.
+constexpr int kCmpUGE = 35;  // unsigned >=
+constexpr int kCmpOGE = 3;   // ordered >= (false for NaN)
+constexpr int kCmpULT = 36;  // unsigned <
+__device__ inline uint64_t mask_ge(uint32_t a, uint32_t b) { return __builtin_amdgcn_uicmp(a, b, kCmpUGE); }
+__device__ inline uint64_t mask_ge(float a, float b) { return __builtin_amdgcn_fcmpf(a, b, kCmpOGE); }
+__device__ inline uint64_t mask_lt(uint64_t a, uint64_t b) { return __builtin_amdgcn_uicmpl(a, b, kCmpULT); }
+// lanes below n (n uniform)
+__device__ inline uint64_t lanes_below(int n) {
+  return n >= 64 ? ~0ull : n <= 0 ? 0ull : (1ull << n) - 1ull;
+}
+
 // float nearest to x from above / below (x finite or +-inf).
 __device__ inline float f32_up(double x) {
   float f = (float)x;

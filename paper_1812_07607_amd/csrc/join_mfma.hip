@@ -426,7 +426,7 @@ __device__ inline bool epilogue_eps(const CandParams& p, int64_t ti, int64_t tj,
   const int lrow0 = wm * kWaveM + 4 * (lane >> 4);
   const int lcol0 = wn * kWaveN + (lane & 15);
   float4 th[8];
-  bool any = false;
+  uint64_t any = 0;
 #pragma unroll
   for (int mb = 0; mb < 8; ++mb) {
     th[mb] = *reinterpret_cast<const float4*>(thr_tile + lrow0 + mb * 16);
@@ -434,15 +434,15 @@ __device__ inline bool epilogue_eps(const CandParams& p, int64_t ti, int64_t tj,
 #pragma unroll
     for (int r = 0; r < 4; ++r)
       m[r] = fmaxf(fmaxf(acc[mb][0][r], acc[mb][1][r]), fmaxf(acc[mb][2][r], acc[mb][3][r]));
-    any |= (m[0] >= th[mb].x) | (m[1] >= th[mb].y) | (m[2] >= th[mb].z) | (m[3] >= th[mb].w);
+    any |= mask_ge(m[0], th[mb].x) | mask_ge(m[1], th[mb].y) | mask_ge(m[2], th[mb].z) | mask_ge(m[3], th[mb].w);
   }
-  if (!__any(any)) return false;
+  if (!any) return false;
   const int rrem = (int)min(p.nR - ti * kTile, (int64_t)kTile);
   const int crem = (int)min(p.nS - tj * kTile, (int64_t)kTile);
   const bool diag = p.self_join && ti == tj;
   const bool full = rrem == kTile && crem == kTile && !diag;
   const uint32_t i0 = (uint32_t)(ti * kTile), j0 = (uint32_t)(tj * kTile);
-  const uint64_t lt = __lanemask_lt();
+  const uint64_t lt = __lanemask_lt(), lbit = lt + 1;
   bool wrote = false;
 #pragma unroll
   for (int mb = 0; mb < 8; ++mb) {
@@ -450,19 +450,17 @@ __device__ inline bool epilogue_eps(const CandParams& p, int64_t ti, int64_t tj,
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const float mx = fmaxf(fmaxf(acc[mb][0][r], acc[mb][1][r]), fmaxf(acc[mb][2][r], acc[mb][3][r]));
-      if (!__ballot(mx >= tv[r])) continue;
+      if (!mask_ge(mx, tv[r])) continue;
       const int lr = lrow0 + mb * 16 + r;
-      bool hit[4];
       uint64_t m[4];
       int tot = 0;
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb) {
-        hit[nb] = acc[mb][nb][r] >= tv[r];
+        m[nb] = mask_ge(acc[mb][nb][r], tv[r]);
         if (!full) {
           const int lc = lcol0 + nb * 16;
-          hit[nb] = hit[nb] && lr < rrem && lc < crem && (!diag || lc > lr);
+          m[nb] &= __builtin_amdgcn_ballot_w64(lr < rrem && lc < crem && (!diag || lc > lr));
         }
-        m[nb] = __ballot(hit[nb]);
         tot += __popcll(m[nb]);
       }
       if (nq + tot > kQueue) {
@@ -472,7 +470,7 @@ __device__ inline bool epilogue_eps(const CandParams& p, int64_t ti, int64_t tj,
       }
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb) {
-        if (hit[nb]) {
+        if (m[nb] & lbit) {
           const int at = nq + __popcll(m[nb] & lt);
           q[at] = make_uint2(i0 + (uint32_t)lr, j0 + (uint32_t)(lcol0 + nb * 16));
           if constexpr (kP) qp[at] = __float_as_uint(acc[mb][nb][r]);
@@ -494,19 +492,6 @@ __device__ inline float key_float(uint32_t k) {
 
 constexpr int kSelPerLane = 8;  // entries per lane in the k-selection subset
 constexpr int kSelBits = 24;    // key bits resolved by the selection
-
-// Wave-wide comparison masks straight from the vector compare (lane l's bit
-// is set when its comparison holds; inactive lanes read 0).  Written with
-// the compare builtins rather than a ballot of a bool, which the compiler
-// lowers through a per-lane 0/1 value and a second compare.
-constexpr int kCmpUGE = 35;  // unsigned >=
-constexpr int kCmpOGE = 3;   // ordered >= (false for NaN)
-__device__ inline uint64_t mask_ge(uint32_t a, uint32_t b) { return __builtin_amdgcn_uicmp(a, b, kCmpUGE); }
-__device__ inline uint64_t mask_ge(float a, float b) { return __builtin_amdgcn_fcmpf(a, b, kCmpOGE); }
-// lanes below n (n uniform)
-__device__ inline uint64_t lanes_below(int n) {
-  return n >= 64 ? ~0ull : n <= 0 ? 0ull : (1ull << n) - 1ull;
-}
 
 // Largest key prefix (top kSelBits bits) with at least k of the first
 // 64 * kT keys at or above it: one bit per step, each step a few compares

@@ -295,7 +295,7 @@ __global__ __launch_bounds__(64 * kSelWaves) void topk_select_kernel(SelectParam
       int c = 0;
 #pragma unroll
       for (int r = 0; r < kSelRegs; ++r)
-        if (r < nr) c += __popcll(__ballot(key[r] >= cand));
+        if (r < nr) c += __popcll(mask_ge(key[r], cand));
       if (c >= k) t = cand;
     }
     const float pk = __uint_as_float((t & 0x80000000u) ? (t & 0x7fffffffu) : ~t);
@@ -355,7 +355,7 @@ __global__ __launch_bounds__(64 * kSelWaves) void topk_select_kernel(SelectParam
       int c = 0;
 #pragma unroll
       for (int r = 0; r < kSelRegs; ++r)
-        if (r < nr) c += __popcll(__ballot((uint64_t)d2b[r] < lim));
+        if (r < nr) c += __popcll(mask_lt((uint64_t)d2b[r], lim));
       if (c < k) dk = lim;
     }
     const double cut = cut_of(dk);
