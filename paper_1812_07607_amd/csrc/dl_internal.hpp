@@ -65,9 +65,18 @@ __host__ __device__ inline double gamma_n(double n, double u) { return n * u / (
 constexpr int kCmpUGE = 35;  // unsigned >=
 constexpr int kCmpOGE = 3;   // ordered >= (false for NaN)
 constexpr int kCmpULT = 36;  // unsigned <
+constexpr int kCmpUGE_F = 11;  // unordered or >=
 __device__ inline uint64_t mask_ge(uint32_t a, uint32_t b) { return __builtin_amdgcn_uicmp(a, b, kCmpUGE); }
 __device__ inline uint64_t mask_ge(float a, float b) { return __builtin_amdgcn_fcmpf(a, b, kCmpOGE); }
 __device__ inline uint64_t mask_lt(uint64_t a, uint64_t b) { return __builtin_amdgcn_uicmpl(a, b, kCmpULT); }
+// a >= b or either is NaN: a pre-test that passes whatever a NaN hides
+__device__ inline uint64_t mask_uge(float a, float b) { return __builtin_amdgcn_fcmpf(a, b, kCmpUGE_F); }
+// Largest of four floats, NaN if any is NaN (two three-input maximum
+// instructions; the NaN-ignoring fmaxf costs two more per call here, to
+// quiet signalling NaNs the matrix cores never produce)
+__device__ inline float max4_nan(float a, float b, float c, float d) {
+  return __builtin_elementwise_maximum(__builtin_elementwise_maximum(a, b), __builtin_elementwise_maximum(c, d));
+}
 // lanes below n (n uniform)
 __device__ inline uint64_t lanes_below(int n) {
   return n >= 64 ? ~0ull : n <= 0 ? 0ull : (1ull << n) - 1ull;

@@ -65,9 +65,11 @@ typedef __attribute__((address_space(3))) void lvoid_t;
 // the compiler's wait-count insertion does not treat the transfer as a
 // write to the stage being read; the kernel orders it explicitly (vmcnt(0)
 // and a barrier before a stage is read or overwritten).
-__device__ inline void lds_dma16(const void* gsrc, void* lds_dst) {
-  const uint32_t m0 = __builtin_amdgcn_readfirstlane(
-      (uint32_t)reinterpret_cast<uintptr_t>((lvoid_t*)lds_dst));
+__device__ inline uint32_t lds_addr(const void* lds_ptr) {
+  return __builtin_amdgcn_readfirstlane((uint32_t)reinterpret_cast<uintptr_t>((const lvoid_t*)lds_ptr));
+}
+// the same with the LDS destination given as a wave-uniform LDS address
+__device__ inline void lds_dma16_at(const void* gsrc, uint32_t m0) {
   // M0 (the LDS base of the transfer) is saved and restored around the
   // transfer, and one wait state separates the M0 write from the LDS-DMA
   // instruction that reads it.
@@ -82,6 +84,7 @@ __device__ inline void lds_dma16(const void* gsrc, void* lds_dst) {
       : "v"(gsrc), "s"(m0)
       : "memory");
 }
+__device__ inline void lds_dma16(const void* gsrc, void* lds_dst) { lds_dma16_at(gsrc, lds_addr(lds_dst)); }
 
 // LDS byte offset of logical 16-byte piece c of tile row r in a stage with
 // kCB bytes per row.  The piece is stored at slot c ^ f(r), which spreads the
@@ -248,16 +251,26 @@ __device__ inline void issue_loads(const CandParams& p, int64_t ti, int64_t tj, 
   if (wave >= kDmaWaves) return;
   constexpr int kPer = kTile / Q::kRowsPerDma / kDmaWaves;  // blocks per issuing wave and operand
   const uint8_t* ga0 = p.qa + (ti * kTile) * p.qld + (int64_t)step * Q::kCB;
-  const uint8_t* gb0 = p.qb + (tj * kTile) * p.qld + (int64_t)step * Q::kCB;
-#pragma unroll
-  for (int t = 0; t < kPer; ++t) {
-    const int q = wave * kPer + t;
-    const int row = q * Q::kRowsPerDma + lane / Q::kSlots;
+  const int64_t dba = (p.qb + (tj * kTile) * p.qld) - (p.qa + (ti * kTile) * p.qld);  // B source - A source
+  // The swizzle key of a row repeats every 2 * kRowsPerDma rows, so block t
+  // reads at the lane offset of block t & 1 plus (t - (t & 1)) *
+  // kRowsPerDma rows: two per-lane addresses, the rest is scalar.
+  static_assert(Q::kCB == 128 ? (2 * Q::kRowsPerDma) % 16 == 0 : (2 * Q::kRowsPerDma) % 32 == 0,
+                "swizzle period");
+  auto lane_src = [&](int u) {
+    const int row = (wave * kPer + u) * Q::kRowsPerDma + lane / Q::kSlots;
     const int phys = lane % Q::kSlots;
     const int c = (lds_off<Q::kCB>(row, phys) - row * Q::kCB) >> 4;  // the swizzle is an involution
-    const uint32_t off = (uint32_t)row * (uint32_t)p.qld + (uint32_t)(c * 16);
-    lds_dma16(ga0 + off, la + q * 1024);
-    lds_dma16(gb0 + off, lb + q * 1024);
+    return ga0 + ((uint32_t)row * (uint32_t)p.qld + (uint32_t)(c * 16));
+  };
+  const uint8_t* const pa0 = lane_src(0);
+  const uint8_t* const pa1 = lane_src(1);
+  const uint32_t la0 = lds_addr(la) + wave * kPer * 1024, lb0 = lds_addr(lb) + wave * kPer * 1024;
+#pragma unroll
+  for (int t = 0; t < kPer; ++t) {
+    const uint8_t* a = ((t & 1) ? pa1 : pa0) + (int64_t)((t & ~1) * Q::kRowsPerDma) * p.qld;
+    lds_dma16_at(a, la0 + t * 1024);
+    lds_dma16_at(a + dba, lb0 + t * 1024);
   }
 }
 
@@ -432,9 +445,8 @@ __device__ inline bool epilogue_eps(const CandParams& p, int64_t ti, int64_t tj,
     th[mb] = *reinterpret_cast<const float4*>(thr_tile + lrow0 + mb * 16);
     float m[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-      m[r] = fmaxf(fmaxf(acc[mb][0][r], acc[mb][1][r]), fmaxf(acc[mb][2][r], acc[mb][3][r]));
-    any |= mask_ge(m[0], th[mb].x) | mask_ge(m[1], th[mb].y) | mask_ge(m[2], th[mb].z) | mask_ge(m[3], th[mb].w);
+    for (int r = 0; r < 4; ++r) m[r] = max4_nan(acc[mb][0][r], acc[mb][1][r], acc[mb][2][r], acc[mb][3][r]);
+    any |= mask_uge(m[0], th[mb].x) | mask_uge(m[1], th[mb].y) | mask_uge(m[2], th[mb].z) | mask_uge(m[3], th[mb].w);
   }
   if (!any) return false;
   const int rrem = (int)min(p.nR - ti * kTile, (int64_t)kTile);
@@ -449,8 +461,7 @@ __device__ inline bool epilogue_eps(const CandParams& p, int64_t ti, int64_t tj,
     const float tv[4] = {th[mb].x, th[mb].y, th[mb].z, th[mb].w};
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const float mx = fmaxf(fmaxf(acc[mb][0][r], acc[mb][1][r]), fmaxf(acc[mb][2][r], acc[mb][3][r]));
-      if (!mask_ge(mx, tv[r])) continue;
+      if (!mask_uge(max4_nan(acc[mb][0][r], acc[mb][1][r], acc[mb][2][r], acc[mb][3][r]), tv[r])) continue;
       const int lr = lrow0 + mb * 16 + r;
       uint64_t m[4];
       int tot = 0;
