@@ -70,18 +70,14 @@ __device__ inline uint32_t lds_addr(const void* lds_ptr) {
 }
 // the same with the LDS destination given as a wave-uniform LDS address
 __device__ inline void lds_dma16_at(const void* gsrc, uint32_t m0) {
-  // M0 (the LDS base of the transfer) is saved and restored around the
-  // transfer, and one wait state separates the M0 write from the LDS-DMA
-  // instruction that reads it.
-  uint32_t saved;
+  // M0 (the LDS base of the transfer) is an operand bound to the register,
+  // so the compiler knows it is written; one wait state separates the M0
+  // write from the LDS-DMA instruction that reads it.
   asm volatile(
-      "s_mov_b32 %0, m0\n\t"
-      "s_mov_b32 m0, %2\n\t"
       "s_nop 0\n\t"
-      "global_load_lds_dwordx4 %1, off\n\t"
-      "s_mov_b32 m0, %0"
-      : "=&s"(saved)
-      : "v"(gsrc), "s"(m0)
+      "global_load_lds_dwordx4 %0, off"
+      :
+      : "v"(gsrc), "{m0}"(m0)
       : "memory");
 }
 __device__ inline void lds_dma16(const void* gsrc, void* lds_dst) { lds_dma16_at(gsrc, lds_addr(lds_dst)); }
@@ -306,7 +302,8 @@ __device__ inline void issue_side(const CandParams& p, int64_t ti, int64_t tj, c
 // to the slots.
 //
 // Fragment reads run ahead of the matrix instructions in a rolling window:
-// the first sub-step's B and A fragments are requested up front; the second
+// the first sub-step's fragments are requested up front, in the order the
+// matrix instructions use them (A0, B0..B3, A1..A7); the second
 // sub-step's A fragment mb (and B fragment nb) is requested right after the
 // instructions that consume the register it replaces.  The LDS latency is
 // then paid about once per step instead of once per pair of A fragments,
@@ -348,10 +345,14 @@ __device__ inline void mma_step(f32x4 (&acc)[8][4], const uint8_t* la, const uin
     };
     constexpr int kPerBlock = kPrec == DL_FP32 ? 4 : 1;  // matrix instructions per block product
     uint4 a[8], b0[4], b1[4];
+    // in the order of first use: the first instruction waits for two reads
+    a[0] = ldA(0, grp);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb) b0[nb] = ldB(nb, grp);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int mb = 0; mb < 8; ++mb) a[mb] = ldA(mb, grp);
+    for (int mb = 1; mb < 8; ++mb) a[mb] = ldA(mb, grp);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int mb = 0; mb < 8; ++mb) {
@@ -376,10 +377,11 @@ __device__ inline void mma_step(f32x4 (&acc)[8][4], const uint8_t* la, const uin
       return i32x8{(int)x0.x, (int)x0.y, (int)x0.z, (int)x0.w, (int)x1.x, (int)x1.y, (int)x1.z, (int)x1.w};
     };
     i32x8 b[4], a[4];
+    a[0] = ld8(ldA(0, 2 * grp), ldA(0, 2 * grp + 1));
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb) b[nb] = ld8(ldB(nb, 2 * grp), ldB(nb, 2 * grp + 1));
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb) a[mb] = ld8(ldA(mb, 2 * grp), ldA(mb, 2 * grp + 1));
+    for (int mb = 1; mb < 4; ++mb) a[mb] = ld8(ldA(mb, 2 * grp), ldA(mb, 2 * grp + 1));
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int mb = 0; mb < 8; ++mb) {
