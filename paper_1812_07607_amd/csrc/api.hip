@@ -14,7 +14,7 @@ hipError_t launch_hist_rgb8(const uint8_t*, int64_t, int32_t, int32_t, int32_t, 
 // prep.hip
 hipError_t launch_prep(const float*, int64_t, int32_t, int64_t, dl_prec, const Prep&, RelStats*, hipStream_t, int);
 hipError_t launch_threshold(const Prep&, int64_t, const RelStats*, int, double, const double*, float*, float*, int*,
-                            hipStream_t);
+                            uint32_t*, hipStream_t);
 }  // namespace dl
 
 #include "join_params.hpp"
@@ -117,6 +117,7 @@ struct TopkLayout {
   RelStats *sr, *ss;
   Counters* cnt;
   float* marg;
+  uint32_t* gkey;  // per row: best band threshold of any split so far (order key)
   uint2* band;
   int* bcount;
   size_t bytes;
@@ -160,6 +161,7 @@ static TopkLayout layout_topk(void* ws, int64_t nR, int64_t nS, int d, dl_prec p
   L.pr = carve_prep(b, nR, d, prec);
   L.ps = (self || s_ext) ? L.pr : carve_prep(b, nS, d, prec);
   L.marg = b.take<float>(L.pr.npad);
+  L.gkey = b.take<uint32_t>(L.pr.npad);
   L.band = b.take<uint2>((nR < 1 ? 1 : nR) * (int64_t)P * cap);
   L.bcount = b.take<int>((nR < 1 ? 1 : nR) * (int64_t)P);
   L.bytes = round_up((int64_t)b.off, 256);
@@ -449,7 +451,7 @@ dl_status eps_core(dl_ctx* c, const EpsJob& J, void* ws, size_t ws_bytes, dl_pai
     StageTimer t(c, 1, st);
     DL_HIP(c, launch_prep(R.data, R.n, R.d, R.ld, prec, L.pr, L.sr, st, c->cu_count));
     if (!self && !sx) DL_HIP(c, launch_prep(S.data, S.n, S.d, S.ld, prec, L.ps, L.ss, st, c->cu_count));
-    DL_HIP(c, launch_threshold(L.pr, R.n, L.ss, R.d, J.T, J.Trow, L.thr, nullptr, L.pex, st));
+    DL_HIP(c, launch_threshold(L.pr, R.n, L.ss, R.d, J.T, J.Trow, L.thr, nullptr, L.pex, nullptr, st));
   }
   {
     StageTimer t(c, 2, st);
@@ -551,7 +553,7 @@ dl_status topk_core(dl_ctx* c, const TopkJob& J, void* ws, size_t ws_bytes, uint
     StageTimer t(c, 1, st);
     DL_HIP(c, launch_prep(R.data, R.n, R.d, R.ld, prec, L.pr, L.sr, st, c->cu_count));
     if (!self && !sx) DL_HIP(c, launch_prep(S.data, S.n, S.d, S.ld, prec, L.ps, L.ss, st, c->cu_count));
-    DL_HIP(c, launch_threshold(L.pr, R.n, L.ss, R.d, 0.0, nullptr, nullptr, L.marg, nullptr, st));
+    DL_HIP(c, launch_threshold(L.pr, R.n, L.ss, R.d, 0.0, nullptr, nullptr, L.marg, nullptr, L.gkey, st));
   }
   if (S.n > 0) {
     StageTimer t(c, 2, st);
@@ -574,6 +576,7 @@ dl_status topk_core(dl_ctx* c, const TopkJob& J, void* ws, size_t ws_bytes, uint
     p.batch = band_defers(band_cap, k, tps) ? 8 : 1;  // one row per wave of the workgroup
     p.retight = retight_of(k, p.limit);
     p.marg = L.marg;
+    p.gkey = L.gkey;
     p.band = L.band;
     p.bcount = L.bcount;
     p.overflow = &L.cnt->overflow;

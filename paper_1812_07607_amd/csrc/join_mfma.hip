@@ -698,6 +698,18 @@ __device__ inline bool tighten_rows(const CandParams& p, int64_t ti, int64_t spl
   if (nq == 0 || (!drain && nq < p.batch && !__builtin_amdgcn_readfirstlane(L.urgent))) return false;
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int limit = p.limit;
+  // Every row's band threshold first rises to the best one any split of the
+  // row has published: each is v_s - E_i with v_s a lower bound of the k-th
+  // largest P~ over a subset of S, so at most the k-th largest over all of S
+  // minus E_i (the band stays a superset of the exact one).
+  for (int r = threadIdx.x; r < kTile; r += kThreads) {
+    const int64_t i = ti * kTile + r;
+    if (i < p.nR) {
+      const uint32_t g = __hip_atomic_load(p.gkey + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      L.thr[r] = fmaxf(L.thr[r], key_float(g));
+    }
+  }
+  __syncthreads();
   for (int t = wave; t < nq; t += kThreads / 64) {
     const int lr = __builtin_amdgcn_readfirstlane(L.list[1 + t]);
     const int64_t i = ti * kTile + lr;
@@ -707,6 +719,7 @@ __device__ inline bool tighten_rows(const CandParams& p, int64_t ti, int64_t spl
       L.cnt[lr] = w;
       L.trig[lr] = min(w + p.retight, limit);
       if (w > limit) atomicOr(p.overflow, 1);
+      atomicMax(p.gkey + i, order_key(L.thr[lr]));  // publish to the row's other splits
     }
   }
   __syncthreads();

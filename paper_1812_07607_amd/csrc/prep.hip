@@ -200,9 +200,10 @@ __device__ inline double row_margin(const Prep& R, const RelStats& s, int64_t i,
 __global__ __launch_bounds__(256) void threshold_kernel(Prep R, int64_t nR, const RelStats* __restrict__ S,
                                                         int d, double Tall, const double* __restrict__ Trow,
                                                         float* __restrict__ thr, float* __restrict__ marg,
-                                                        int* __restrict__ pex) {
+                                                        int* __restrict__ pex, uint32_t* __restrict__ gkey) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= R.npad) return;
+  if (gkey) gkey[i] = 0x007fffffu;  // order key of -inf (no bound yet)
   if (i >= nR) {
     if (thr) thr[i] = INFINITY;
     if (marg) marg[i] = 0.0f;
@@ -242,9 +243,9 @@ hipError_t launch_prep(const float* X, int64_t n, int32_t d, int64_t ld, dl_prec
 }
 
 hipError_t launch_threshold(const Prep& R, int64_t nR, const RelStats* S, int d, double T, const double* Trow,
-                            float* thr, float* marg, int* pex, hipStream_t st) {
+                            float* thr, float* marg, int* pex, uint32_t* gkey, hipStream_t st) {
   const dim3 grid((unsigned)((R.npad + 255) / 256));
-  hipLaunchKernelGGL(threshold_kernel, grid, dim3(256), 0, st, R, nR, S, d, T, Trow, thr, marg, pex);
+  hipLaunchKernelGGL(threshold_kernel, grid, dim3(256), 0, st, R, nR, S, d, T, Trow, thr, marg, pex, gkey);
   return hipGetLastError();
 }
 
