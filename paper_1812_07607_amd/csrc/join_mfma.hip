@@ -678,6 +678,39 @@ __device__ inline bool epilogue_band(const CandParams& p, int64_t ti, int64_t tj
   return wrote;
 }
 
+// The band epilogue of a workgroup's first tile when the tile is full: every
+// row's threshold is still -inf, so every output is a hit, and each row's
+// buffer takes the tile's 256 outputs in column order straight from the
+// registers (no staging, no atomics).  Then each row holds 256 entries and
+// is queued if that passed its trigger.  (A NaN output, possible only when
+// the inputs overflow, becomes an entry too; no threshold test keeps it
+// and the selection sorts it above every number, which can only lower the
+// threshold it finds.)
+__device__ inline void flood_band(const CandParams& p, int64_t ti, int64_t tj, int64_t split,
+                                  const f32x4 (&acc)[8][4], BandLds& L) {
+  const int lane = fresh_lane(), wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wm = wave >> 2, wn = wave & 3;
+  const int lrow0 = wm * kWaveM + 4 * (lane >> 4);
+  const int lcol0 = wn * kWaveN + (lane & 15);
+  const int64_t rstride = (int64_t)p.P * p.cap;  // entries from one row's buffer to the next's
+  uint2* const e0 = p.band + (ti * kTile * p.P + split) * (int64_t)p.cap + lrow0 * rstride + lcol0;
+  const uint32_t j0 = (uint32_t)(tj * kTile) + (uint32_t)lcol0;
+#pragma unroll
+  for (int mb = 0; mb < 8; ++mb) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      uint2* const e = e0 + (mb * 16 + r) * rstride;
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) e[nb * 16] = make_uint2(__float_as_uint(acc[mb][nb][r]), j0 + nb * 16);
+    }
+  }
+  for (int r = threadIdx.x; r < kTile; r += kThreads) {
+    L.cnt[r] = kTile;
+    if (L.trig[r] < kTile) L.list[1 + atomicAdd(&L.list[0], 1)] = r;
+    if (p.limit < kTile) L.urgent = 1;
+  }
+}
+
 // Rows queued by the band epilogue are tightened by one wave each and their
 // triggers re-armed retight entries further on (capped at limit).  A round
 // waits until batch rows are queued, unless some row has reached limit
@@ -873,7 +906,11 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
       if constexpr (kEps)
         dirty |= epilogue_eps<kStageP>(p, ti, tj, acc, side_thr[kEps ? sbuf : 0], lds_eq[kEps ? wave : 0],
                                        lds_eqp[kStageP ? wave : 0], eq);
-      else if (full) dirty |= epilogue_band<true>(p, ti, tj, split, acc, band);
+      else if (full && ctile == 0) {
+        // the first tile: no round has run, every threshold is -inf
+        flood_band(p, ti, tj, split, acc, band);
+        dirty = true;
+      } else if (full) dirty |= epilogue_band<true>(p, ti, tj, split, acc, band);
       else dirty |= epilogue_band<false>(p, ti, tj, split, acc, band);
     }
     ++step;
