@@ -196,6 +196,9 @@ __device__ inline float lane_d2(const float* a, const float* b, int d, bool vec4
   float acc = 0.0f;
   int q = 0;
   if (vec4) {
+    // unrolled so that several row loads are in flight per lane; the sum is
+    // still one chain in index order
+#pragma unroll 8
     for (; q + 4 <= d; q += 4) {
       const float4 x = *reinterpret_cast<const float4*>(a + q);
       const float4 y = *reinterpret_cast<const float4*>(b + q);
