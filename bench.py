@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=6.0, help="open-loop seconds per offered rate")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="copy this many MiB device-to-device first (scale for FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--secondary", action="store_true",
+                    help="instead of the headline step, time the unit-mixture eps and top-k joins (one JSON line)")
     return ap.parse_args()
 
 
@@ -192,12 +194,79 @@ def serving(args):
     return out
 
 
+def secondary():
+    """Stage times of the eps and top-k joins on two unit-vector mixtures
+    (200k x 200k at d = 128 with 1,000 centres; 20k queries x 1M rows at
+    d = 256 with 4,096 centres), per candidate format: mean of three timed
+    calls after one untimed call, stage times from HIP events.  eps is the
+    median 10th-neighbour distance of each workload."""
+    import torch
+
+    from paper_1812_07607_amd import ops, synth
+
+    torch.cuda.set_device(0)
+    ctx = ops.context()
+    out = {}
+
+    def run(name, fn, flops):
+        try:
+            r = fn()
+            torch.cuda.synchronize()
+        except Exception as e:  # a format that does not converge is reported, not fatal
+            out[name] = {"error": str(e)[:160]}
+            progress("%s: %s" % (name, out[name]["error"]))
+            return
+        ctx.timing(reset=True)
+        ctx.set_timing(True)
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        ctx.set_timing(False)
+        st = ctx.timing(reset=True)
+        rec = {k: round(v[0] / v[1], 3) for k, v in st.items() if v[1]}
+        rec["contract_tflops"] = round(flops / rec["contract"] / 1e9, 1)
+        if hasattr(r, "candidates"):
+            rec.update(candidates=int(r.candidates), pairs=int(r.count))
+        else:
+            rec.update(band_entries=int(r.band_entries), ties=int(r.ties))
+        out[name] = rec
+        progress("%s: %s" % (name, json.dumps(rec)))
+
+    def eps_of(R, S):
+        # the median 10th-neighbour distance: about ten pairs per query row
+        return float(ops.join_topk(R, S, 10, prec="bf16").dist[:, 9].median())
+
+    n = 200000
+    R = torch.from_numpy(synth.gaussian_mixture_unit(n, 128, 1000, seed=303)).cuda()
+    S = torch.from_numpy(synth.gaussian_mixture_unit(n, 128, 1000, seed=303, stream=1)).cuda()
+    fl = 2.0 * n * n * 128
+    eps = eps_of(R, S)
+    out["eps_200k_d128"] = round(eps, 6)
+    for prec in ("bf16", "fp16", "fp8"):
+        run("eps_200k_d128_%s" % prec, lambda: ops.join_eps(R, S, eps, prec, max_candidates=1 << 26), fl)
+    for prec in ("bf16", "fp16", "fp8"):
+        run("top10_200k_d128_%s" % prec, lambda: ops.join_topk(R, S, 10, prec=prec), fl)
+    del R, S
+    S = torch.from_numpy(synth.gaussian_mixture_unit(1000000, 256, 4096, seed=404)).cuda()
+    Q = torch.from_numpy(synth.gaussian_mixture_unit(20000, 256, 4096, seed=404, stream=1)).cuda()
+    fl = 2.0 * 20000 * 1000000 * 256
+    eps = eps_of(Q, S)
+    out["eps_20k_1m_d256"] = round(eps, 6)
+    for prec in ("bf16", "fp8"):
+        run("eps_20k_1m_d256_%s" % prec, lambda: ops.join_eps(Q, S, eps, prec, max_candidates=1 << 26), fl)
+    run("top32_20k_1m_d256_bf16", lambda: ops.join_topk(Q, S, 32, prec="bf16"), fl)
+    print(json.dumps({"secondary": out, "data": "synthetic", "timing": "mean of 3 calls, ms per stage"}))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
+    if args.secondary:
+        secondary()
+        return
     import numpy as np
     import torch
 
