@@ -313,9 +313,50 @@ __device__ inline void issue_side(const CandParams& p, int64_t ti, int64_t tj, c
 // its C operand from init[nb] (the block's initial value -h_j, one register
 // quad per column block) and writes the accumulator, so no per-tile copy of
 // the initial values into the 128 accumulator registers is needed.
-template <int kPrec, bool kFirst>
+// Fragment registers of a K-step (16-bit formats and fp32): the first
+// sub-step's A and B fragments, then the second sub-step's.  They live
+// across the barrier between K-steps: the second sub-step's products of A
+// blocks 4-7 are issued at the start of the next K-step (kTailIn), where
+// their operands are already in registers and they keep the matrix core
+// busy while that step's first fragment reads land; a tile's last K-step
+// leaves them to mma_tail, before the epilogue.
+struct Frags {
+  uint4 a[8], b0[4], b1[4];
+};
+
+// one block product c = c0 + x.y: 16x16x32 for the 16-bit formats, four
+// 16x16x4 for fp32
+template <int kPrec>
+__device__ inline void mac_block(f32x4& c, const f32x4& c0, const uint4& x, const uint4& y) {
+  if constexpr (kPrec == DL_BF16) {
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, x), __builtin_bit_cast(bf16x8, y), c0, 0,
+                                                0, 0);
+  } else if constexpr (kPrec == DL_FP16) {
+    c = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, x), __builtin_bit_cast(f16x8, y), c0, 0, 0,
+                                               0);
+  } else {
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(x.x), __uint_as_float(y.x), c0, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(x.y), __uint_as_float(y.y), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(x.z), __uint_as_float(y.z), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(x.w), __uint_as_float(y.w), c, 0, 0, 0);
+  }
+}
+
+// The products a K-step leaves for later: second sub-step, A blocks 4-7.
+template <int kPrec>
+__device__ inline void mma_tail(f32x4 (&acc)[8][4], const Frags& fr) {
+  if constexpr (kPrec != DL_FP8) {
+#pragma unroll
+    for (int mb = 4; mb < 8; ++mb) {
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) mac_block<kPrec>(acc[mb][nb], acc[mb][nb], fr.a[mb], fr.b1[nb]);
+    }
+  }
+}
+
+template <int kPrec, bool kFirst, bool kTailIn>
 __device__ inline void mma_step(f32x4 (&acc)[8][4], const uint8_t* la, const uint8_t* lb, int ra0, int rb0,
-                                const int (&sa)[8], const int (&sb)[4], const f32x4 (&init)[4]) {
+                                const int (&sa)[8], const int (&sb)[4], const f32x4 (&init)[4], Frags& fr) {
   constexpr int kCB = Pipe<kPrec>::kCB;
   const int lane = threadIdx.x & 63;
   const int r16 = lane & 15, grp = lane >> 4;
@@ -327,24 +368,11 @@ __device__ inline void mma_step(f32x4 (&acc)[8][4], const uint8_t* la, const uin
   };
   if constexpr (kPrec == DL_BF16 || kPrec == DL_FP16 || kPrec == DL_FP32) {
     static_assert(kCB == 128, "two sub-steps of 64 bytes");
-    // one block product: 16x16x32 for the 16-bit formats, four 16x16x4 for fp32
-    // c = c0 + x.y (c0 = c, or the initial value on a tile's first sub-step)
-    auto mac = [&](f32x4& c, const f32x4& c0, const uint4& x, const uint4& y) {
-      if constexpr (kPrec == DL_BF16) {
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, x), __builtin_bit_cast(bf16x8, y),
-                                                    c0, 0, 0, 0);
-      } else if constexpr (kPrec == DL_FP16) {
-        c = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, x), __builtin_bit_cast(f16x8, y), c0,
-                                                   0, 0, 0);
-      } else {
-        c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(x.x), __uint_as_float(y.x), c0, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(x.y), __uint_as_float(y.y), c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(x.z), __uint_as_float(y.z), c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(x.w), __uint_as_float(y.w), c, 0, 0, 0);
-      }
-    };
+    static_assert(!(kFirst && kTailIn), "a tile's first K-step has no earlier products pending");
     constexpr int kPerBlock = kPrec == DL_FP32 ? 4 : 1;  // matrix instructions per block product
-    uint4 a[8], b0[4], b1[4];
+    uint4(&a)[8] = fr.a;
+    uint4(&b0)[4] = fr.b0;
+    uint4(&b1)[4] = fr.b1;
     // in the order of first use: the first instruction waits for two reads
     a[0] = ldA(0, grp);
     __builtin_amdgcn_sched_barrier(0);
@@ -352,12 +380,19 @@ __device__ inline void mma_step(f32x4 (&acc)[8][4], const uint8_t* la, const uin
     for (int nb = 0; nb < 4; ++nb) b0[nb] = ldB(nb, grp);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int mb = 1; mb < 8; ++mb) a[mb] = ldA(mb, grp);
+    for (int mb = 1; mb < 4; ++mb) a[mb] = ldA(mb, grp);
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (kTailIn) {
+      mma_tail<kPrec>(acc, fr);  // the previous K-step's pending products
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int mb = 4; mb < 8; ++mb) a[mb] = ldA(mb, grp);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int mb = 0; mb < 8; ++mb) {
 #pragma unroll
-      for (int nb = 0; nb < 4; ++nb) mac(acc[mb][nb], kFirst ? init[nb] : acc[mb][nb], a[mb], b0[nb]);
+      for (int nb = 0; nb < 4; ++nb) mac_block<kPrec>(acc[mb][nb], kFirst ? init[nb] : acc[mb][nb], a[mb], b0[nb]);
       a[mb] = ldA(mb, 4 + grp);
       if (mb < 4) b1[mb] = ldB(mb, 4 + grp);
       __builtin_amdgcn_sched_group_barrier(0x008, 4 * kPerBlock, 0);  // matrix
@@ -365,10 +400,12 @@ __device__ inline void mma_step(f32x4 (&acc)[8][4], const uint8_t* la, const uin
       else __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
     }
 #pragma unroll
-    for (int mb = 0; mb < 8; ++mb) {
+    for (int mb = 0; mb < 4; ++mb) {
 #pragma unroll
-      for (int nb = 0; nb < 4; ++nb) mac(acc[mb][nb], acc[mb][nb], a[mb], b1[nb]);
+      for (int nb = 0; nb < 4; ++nb) mac_block<kPrec>(acc[mb][nb], acc[mb][nb], a[mb], b1[nb]);
     }
+    // A blocks 4-7 of the second sub-step: mma_tail, at the next K-step or
+    // before the epilogue
   } else {
     // E4M3, 128 bytes = 128 values per row: 16x16x128 with per-row E8M0
     // scales; each lane reads 32 bytes per fragment; a window of four A
@@ -850,76 +887,114 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
   }
   for (int s = 0; s < Q::kStages - 1 && lmore; ++s) issue();
 
-  int step = 0, chunk = 0, ctile = 0;
+  int step = 0, ctile = 0;
   int eq = 0;  // eps: candidates staged in this wave's queue
   bool dirty = true;  // the band set-up above wrote LDS only, but be exact once
   bool full = true;   // band mode: the tile needs no bounds or self checks
   f32x4 acc[8][4];
+  Frags fr;
   int sa[8], sb[4];
-  for (;;) {
-    // This step's operands are in LDS once this wave's transfers for it have
-    // landed and every wave has passed the barrier; transfers of later steps
-    // may stay in flight, unless this wave also wrote to global memory since
-    // the last full wait (stores and loads may then retire out of order).
-    // The barrier also means every wave is done with the stage computed in
-    // the previous step, so this step's new transfers may overwrite it.
-    wait_and_sync(dirty ? 0 : (issued - step - 1) * Q::kPerStep);
-    dirty = false;
-    const int sbuf = ctile % 3;
-    const bool more = lmore;  // a step follows this one
-    if (chunk == 0) {
-      if constexpr (!kEps) {
-        dirty |= tighten_rows(p, ti, split, band, false);
-        full = (ti + 1) * kTile <= p.nR && (tj + 1) * kTile <= p.nS && !(p.exclude_self && ti == tj);
-      }
-      const int l16 = fresh_lane() & 15;
-      const int cb = wn * kWaveN + l16, rb = wm * kWaveM + l16;
-      f32x4 init[4];
+  // Each K-step starts with a wait: its operands are in LDS once this wave's
+  // transfers for it have landed and every wave has passed the barrier;
+  // transfers of later steps may stay in flight, unless this wave also wrote
+  // to global memory since the last full wait (stores and loads may then
+  // retire out of order).  The barrier also means every wave is done with
+  // the stage computed in the previous step, so this step's new transfers
+  // may overwrite it.
+  if constexpr (kEps) {
+    // eps mode: one tile per pass; each K-step's last products are issued
+    // after the next barrier (mma_step, kTailIn)
+    for (;;) {  // one tile per pass
+      // ---- the tile's first K-step
+      wait_and_sync(dirty ? 0 : (issued - step - 1) * Q::kPerStep);
+      dirty = false;
+      const int sbuf = ctile % 3;
+      bool more = lmore;  // a step follows the current one
+      {
+        const int l16 = fresh_lane() & 15;
+        const int cb = wn * kWaveN + l16, rb = wm * kWaveM + l16;
+        f32x4 init[4];
 #pragma unroll
-      for (int nb = 0; nb < 4; ++nb) {
-        const float h0 = -side_hb[sbuf][cb + nb * 16];
-        init[nb] = f32x4{h0, h0, h0, h0};
-        // band mode keeps the copy into the accumulators (measured: reading
-        // C from init on its first step spills in band mode)
-        if constexpr (!kEps) {
-#pragma unroll
-          for (int mb = 0; mb < 8; ++mb) acc[mb][nb] = init[nb];
+        for (int nb = 0; nb < 4; ++nb) {
+          const float h0 = -side_hb[sbuf][cb + nb * 16];
+          init[nb] = f32x4{h0, h0, h0, h0};
+          if constexpr (kFp8) sb[nb] = side_sb[sbuf][cb + nb * 16] + 127;
         }
-        if constexpr (kFp8) sb[nb] = side_sb[sbuf][cb + nb * 16] + 127;
-      }
-      if constexpr (kFp8) {
+        if constexpr (kFp8) {
 #pragma unroll
-        for (int mb = 0; mb < 8; ++mb) sa[mb] = side_sa[sbuf][rb + mb * 16] + 127;
-      }
-      if constexpr (kEps) {
+          for (int mb = 0; mb < 8; ++mb) sa[mb] = side_sa[sbuf][rb + mb * 16] + 127;
+        }
         if (lmore) issue();
         const int st = step % Q::kStages;
-        mma_step<kPrec, true>(acc, lds_ab[st][0], lds_ab[st][1], wm * kWaveM, wn * kWaveN, sa, sb, init);
+        mma_step<kPrec, true, false>(acc, lds_ab[st][0], lds_ab[st][1], wm * kWaveM, wn * kWaveN, sa, sb, init, fr);
       }
-    }
-    if (!kEps || chunk != 0) {
-      if (lmore) issue();
-      const int st = step % Q::kStages;
-      mma_step<kPrec, false>(acc, lds_ab[st][0], lds_ab[st][1], wm * kWaveM, wn * kWaveN, sa, sb, acc[0]);
-    }
-    if (chunk == nsteps - 1) {
-      if constexpr (kEps)
-        dirty |= epilogue_eps<kStageP>(p, ti, tj, acc, side_thr[kEps ? sbuf : 0], lds_eq[kEps ? wave : 0],
-                                       lds_eqp[kStageP ? wave : 0], eq);
-      else if (full && ctile == 0) {
-        // the first tile: no round has run, every threshold is -inf
-        flood_band(p, ti, tj, split, acc, band);
-        dirty = true;
-      } else if (full) dirty |= epilogue_band<true>(p, ti, tj, split, acc, band);
-      else dirty |= epilogue_band<false>(p, ti, tj, split, acc, band);
-    }
-    ++step;
-    if (++chunk == nsteps) {
+      ++step;
+      // ---- its other K-steps
+      for (int c = 1; c < nsteps; ++c) {
+        wait_and_sync(dirty ? 0 : (issued - step - 1) * Q::kPerStep);
+        dirty = false;
+        more = lmore;
+        if (lmore) issue();
+        const int st = step % Q::kStages;
+        mma_step<kPrec, false, true>(acc, lds_ab[st][0], lds_ab[st][1], wm * kWaveM, wn * kWaveN, sa, sb, acc[0], fr);
+        ++step;
+      }
+      mma_tail<kPrec>(acc, fr);
+      // ---- epilogue
+      dirty |= epilogue_eps<kStageP>(p, ti, tj, acc, side_thr[sbuf], lds_eq[wave], lds_eqp[kStageP ? wave : 0], eq);
       if (!more) break;
-      chunk = 0;
       ti = iti;  // the step just issued opens the next tile
       tj = itj;
       ++ctile;
+    }
+  } else {
+    // band mode (more live state beside the accumulators): each K-step's
+    // products are all issued before the next barrier
+    int chunk = 0;
+    for (;;) {
+      wait_and_sync(dirty ? 0 : (issued - step - 1) * Q::kPerStep);
+      dirty = false;
+      const int sbuf = ctile % 3;
+      const bool more = lmore;  // a step follows this one
+      if (chunk == 0) {
+        dirty |= tighten_rows(p, ti, split, band, false);
+        full = (ti + 1) * kTile <= p.nR && (tj + 1) * kTile <= p.nS && !(p.exclude_self && ti == tj);
+        const int l16 = fresh_lane() & 15;
+        const int cb = wn * kWaveN + l16, rb = wm * kWaveM + l16;
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) {
+          // the initial values are copied into the accumulators (measured:
+          // reading C from them on the first step spills in band mode)
+          const float h0 = -side_hb[sbuf][cb + nb * 16];
+#pragma unroll
+          for (int mb = 0; mb < 8; ++mb) acc[mb][nb] = f32x4{h0, h0, h0, h0};
+          if constexpr (kFp8) sb[nb] = side_sb[sbuf][cb + nb * 16] + 127;
+        }
+        if constexpr (kFp8) {
+#pragma unroll
+          for (int mb = 0; mb < 8; ++mb) sa[mb] = side_sa[sbuf][rb + mb * 16] + 127;
+        }
+      }
+      if (lmore) issue();
+      const int st = step % Q::kStages;
+      mma_step<kPrec, false, false>(acc, lds_ab[st][0], lds_ab[st][1], wm * kWaveM, wn * kWaveN, sa, sb, acc[0], fr);
+      mma_tail<kPrec>(acc, fr);
+      if (chunk == nsteps - 1) {
+        if (full && ctile == 0) {
+          // the first tile: no round has run, every threshold is -inf
+          flood_band(p, ti, tj, split, acc, band);
+          dirty = true;
+        } else if (full) dirty |= epilogue_band<true>(p, ti, tj, split, acc, band);
+        else dirty |= epilogue_band<false>(p, ti, tj, split, acc, band);
+      }
+      ++step;
+      if (++chunk == nsteps) {
+        if (!more) break;
+        chunk = 0;
+        ti = iti;  // the step just issued opens the next tile
+        tj = itj;
+        ++ctile;
+      }
     }
   }
   if constexpr (kEps) {
