@@ -323,6 +323,7 @@ __device__ inline void issue_side(const CandParams& p, int64_t ti, int64_t tj, c
 struct Frags {
   uint4 a[8], b0[4], b1[4];
 };
+constexpr int kTailFrom = 4;  // first A block whose second-sub-step products are deferred
 
 // one block product c = c0 + x.y: 16x16x32 for the 16-bit formats, four
 // 16x16x4 for fp32
@@ -347,7 +348,7 @@ template <int kPrec>
 __device__ inline void mma_tail(f32x4 (&acc)[8][4], const Frags& fr) {
   if constexpr (kPrec != DL_FP8) {
 #pragma unroll
-    for (int mb = 4; mb < 8; ++mb) {
+    for (int mb = kTailFrom; mb < 8; ++mb) {
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb) mac_block<kPrec>(acc[mb][nb], acc[mb][nb], fr.a[mb], fr.b1[nb]);
     }
@@ -380,14 +381,14 @@ __device__ inline void mma_step(f32x4 (&acc)[8][4], const uint8_t* la, const uin
     for (int nb = 0; nb < 4; ++nb) b0[nb] = ldB(nb, grp);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int mb = 1; mb < 4; ++mb) a[mb] = ldA(mb, grp);
+    for (int mb = 1; mb < kTailFrom; ++mb) a[mb] = ldA(mb, grp);
     __builtin_amdgcn_sched_barrier(0);
     if constexpr (kTailIn) {
       mma_tail<kPrec>(acc, fr);  // the previous K-step's pending products
       __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
-    for (int mb = 4; mb < 8; ++mb) a[mb] = ldA(mb, grp);
+    for (int mb = kTailFrom; mb < 8; ++mb) a[mb] = ldA(mb, grp);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int mb = 0; mb < 8; ++mb) {
@@ -400,7 +401,7 @@ __device__ inline void mma_step(f32x4 (&acc)[8][4], const uint8_t* la, const uin
       else __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
     }
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb) {
+    for (int mb = 0; mb < kTailFrom; ++mb) {
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb) mac_block<kPrec>(acc[mb][nb], acc[mb][nb], a[mb], b1[nb]);
     }
