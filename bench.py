@@ -42,6 +42,9 @@ def parse():
                     help="copy this many MiB device-to-device first (scale for FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--secondary", action="store_true",
                     help="instead of the headline step, time the unit-mixture eps and top-k joins (one JSON line)")
+    ap.add_argument("--full-configs", action="store_true",
+                    help="instead of the headline step, time the 1M x 1M d=128 joins (bf16 and fp32) and the "
+                         "4M x 256 store with 50k top-32 queries (fp8 and bf16) at full size (one JSON line)")
     return ap.parse_args()
 
 
@@ -258,6 +261,70 @@ def secondary():
     print(json.dumps({"secondary": out, "data": "synthetic", "timing": "mean of 3 calls, ms per stage"}))
 
 
+def full_configs():
+    """The precision-form and FP8-store workloads at full size: a 1M x 1M
+    d = 128 mixture (top-10 and eps-join at the median 10th-neighbour
+    distance, bf16 candidates against the plain fp32 join) and a 4M x 256
+    store probed by 50k queries (top-32, E4M3 and bf16 candidates).  Stage
+    times are the mean of two calls after one untimed call."""
+    import torch
+
+    from paper_1812_07607_amd import ops, synth
+
+    torch.cuda.set_device(0)
+    ctx = ops.context()
+    out = {}
+
+    def run(name, fn, flops, reps=2):
+        progress("%s ..." % name)
+        try:
+            r = fn()
+            torch.cuda.synchronize()
+        except Exception as e:  # reported, not fatal
+            out[name] = {"error": str(e)[:200]}
+            progress("%s: %s" % (name, out[name]["error"]))
+            return None
+        ctx.timing(reset=True)
+        ctx.set_timing(True)
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        ctx.set_timing(False)
+        st = ctx.timing(reset=True)
+        rec = {k: round(v[0] / v[1], 3) for k, v in st.items() if v[1]}
+        rec["contract_tflops"] = round(flops / rec["contract"] / 1e9, 1)
+        if hasattr(r, "candidates"):
+            rec.update(candidates=int(r.candidates), pairs=int(r.count))
+        else:
+            rec.update(band_entries=int(r.band_entries), ties=int(r.ties))
+        out[name] = rec
+        progress("%s: %s" % (name, json.dumps(rec)))
+        return r
+
+    c3 = synth.config3()
+    R = torch.from_numpy(c3["R"]).cuda()
+    S = torch.from_numpy(c3["S"]).cuda()
+    del c3
+    n = R.shape[0]
+    fl = 2.0 * n * n * 128
+    t = run("c3_top10_bf16", lambda: ops.join_topk(R, S, 10, prec="bf16"), fl)
+    eps = float(t.dist[:, 9].median()) if t is not None else 0.6
+    out["c3_eps"] = round(eps, 6)
+    run("c3_eps_bf16", lambda: ops.join_eps(R, S, eps, "bf16", max_candidates=1 << 26), fl)
+    run("c3_eps_fp32", lambda: ops.join_eps(R, S, eps, "fp32", max_candidates=1 << 26), fl, reps=1)
+    run("c3_top10_fp32", lambda: ops.join_topk(R, S, 10, prec="fp32"), fl, reps=1)
+    del R, S, t
+    torch.cuda.empty_cache()
+    c4 = synth.config4()
+    S = torch.from_numpy(c4["S"]).cuda()
+    Q = torch.from_numpy(c4["Q"]).cuda()
+    del c4
+    fl = 2.0 * Q.shape[0] * S.shape[0] * 256
+    run("c4_top32_fp8", lambda: ops.join_topk(Q, S, 32, prec="fp8"), fl)
+    run("c4_top32_bf16", lambda: ops.join_topk(Q, S, 32, prec="bf16"), fl)
+    print(json.dumps({"full_configs": out, "data": "synthetic", "timing": "mean of 2 calls (fp32: 1), ms per stage"}))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -266,6 +333,9 @@ def main():
         sys.exit(2)
     if args.secondary:
         secondary()
+        return
+    if args.full_configs:
+        full_configs()
         return
     import numpy as np
     import torch

@@ -15,6 +15,7 @@ hipError_t launch_hist_rgb8(const uint8_t*, int64_t, int32_t, int32_t, int32_t, 
 hipError_t launch_prep(const float*, int64_t, int32_t, int64_t, dl_prec, const Prep&, RelStats*, hipStream_t, int);
 hipError_t launch_threshold(const Prep&, int64_t, const RelStats*, int, double, const double*, float*, float*, int*,
                             uint32_t*, hipStream_t);
+hipError_t launch_band_seed(const Prep&, int64_t, const float*, int, const float*, uint32_t*, hipStream_t);
 }  // namespace dl
 
 #include "join_params.hpp"
@@ -415,11 +416,28 @@ size_t eps_workspace(int64_t nR, int64_t nS, int d, dl_prec prec, bool self, boo
   return layout_eps(nullptr, nR, nS, d, prec, self, cap, s_ext).bytes;
 }
 
+// E4M3 top-k pilot.  The E4M3 margin E_i (about 0.1 on unit vectors) is
+// wide next to the spread of unrelated rows' P, so a band seeded at -inf
+// keeps most of them until the row has met k close neighbours, and can
+// overflow any buffer.  An exact bf16 top-k of R against every
+// kPilotStride-th row of S first gives each row a lower bound of its k-th
+// largest P (the sample is a subset of S), and the E4M3 pass starts from
+// that bound minus E_i.
+constexpr int kPilotStride = 16;
+static bool pilot_of(dl_prec prec, bool self, int64_t nS, int k) {
+  return prec == DL_FP8 && !self && nS >= (int64_t)kPilotStride * kTile && nS / kPilotStride >= 4 * (int64_t)k;
+}
+static int64_t pilot_rows(int64_t nS) { return (nS + kPilotStride - 1) / kPilotStride; }
+static size_t pilot_out_bytes(int64_t nR, int k) { return (size_t)round_up(nR * (int64_t)k * 4, 256); }
+
 size_t topk_workspace(int64_t nR, int64_t nS, int d, dl_prec prec, bool self, bool s_ext, int k, int band_cap,
                       int cu) {
   int64_t tps = 1;
   const int P = topk_splits(nR, nS, cu, &tps);
-  return layout_topk(nullptr, nR, nS, d, prec, self, P, band_cap_of(band_cap, k, tps), s_ext).bytes;
+  size_t b = layout_topk(nullptr, nR, nS, d, prec, self, P, band_cap_of(band_cap, k, tps), s_ext).bytes;
+  if (pilot_of(prec, self, nS, k))  // the pilot's outputs and workspace follow
+    b += 2 * pilot_out_bytes(nR, k) + topk_workspace(nR, pilot_rows(nS), d, DL_BF16, false, false, k, 0, cu);
+  return b;
 }
 
 dl_status eps_core(dl_ctx* c, const EpsJob& J, void* ws, size_t ws_bytes, dl_pairs* out, hipStream_t st) {
@@ -530,13 +548,33 @@ dl_status topk_core(dl_ctx* c, const TopkJob& J, void* ws, size_t ws_bytes, uint
   int64_t tps = 1;
   const int P = topk_splits(R.n, S.n, c->cu_count, &tps);
   const int band_cap = band_cap_of(J.band_cap, k, tps);
-  const size_t need = layout_topk(nullptr, R.n, S.n, R.d, prec, self, P, band_cap, sx).bytes;
+  const size_t main_bytes = layout_topk(nullptr, R.n, S.n, R.d, prec, self, P, band_cap, sx).bytes;
+  const bool pilot = pilot_of(prec, self, S.n, k);
+  const size_t need = pilot ? main_bytes + 2 * pilot_out_bytes(R.n, k) +
+                                  topk_workspace(R.n, pilot_rows(S.n), R.d, DL_BF16, false, false, k, 0, c->cu_count)
+                            : main_bytes;
   if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(c, DL_ERR_INVALID, "workspace is not 256-byte aligned");
   if (!ws || ws_bytes < need) {
     c->required_ws = need;
     return fail(c, DL_ERR_WORKSPACE, "workspace of %zu bytes below the %zu needed", ws_bytes, need);
   }
   if (R.n == 0) return DL_OK;
+  // the pilot (see pilot_of) runs first, in its own part of the workspace
+  const float* pilot_dist = nullptr;
+  if (pilot) {
+    uint8_t* pw = static_cast<uint8_t*>(ws) + main_bytes;
+    uint32_t* pj = reinterpret_cast<uint32_t*>(pw);
+    float* pd = reinterpret_cast<float*>(pw + pilot_out_bytes(R.n, k));
+    uint8_t* pws = pw + 2 * pilot_out_bytes(R.n, k);
+    dl_mat Ss = S;
+    Ss.n = pilot_rows(S.n);
+    Ss.ld = S.ld * kPilotStride;
+    const TopkJob Jp{R, Ss, false, false, DL_BF16, nullptr, nullptr, k, 0};
+    const dl_status ps = topk_core(c, Jp, pws, ws_bytes - main_bytes - 2 * pilot_out_bytes(R.n, k), pj, pd, nullptr,
+                                   st);
+    if (ps == DL_OK) pilot_dist = pd;  // otherwise the E4M3 pass starts unseeded
+    else if (ps != DL_ERR_WORKSPACE) return ps;
+  }
   TopkLayout L = layout_topk(ws, R.n, S.n, R.d, prec, self, P, band_cap, sx);
   if (sx) {
     L.ps = *J.ps_ext;
@@ -554,6 +592,7 @@ dl_status topk_core(dl_ctx* c, const TopkJob& J, void* ws, size_t ws_bytes, uint
     DL_HIP(c, launch_prep(R.data, R.n, R.d, R.ld, prec, L.pr, L.sr, st, c->cu_count));
     if (!self && !sx) DL_HIP(c, launch_prep(S.data, S.n, S.d, S.ld, prec, L.ps, L.ss, st, c->cu_count));
     DL_HIP(c, launch_threshold(L.pr, R.n, L.ss, R.d, 0.0, nullptr, nullptr, L.marg, nullptr, L.gkey, st));
+    if (pilot_dist) DL_HIP(c, launch_band_seed(L.pr, R.n, pilot_dist, k, L.marg, L.gkey, st));
   }
   if (S.n > 0) {
     StageTimer t(c, 2, st);
@@ -577,6 +616,7 @@ dl_status topk_core(dl_ctx* c, const TopkJob& J, void* ws, size_t ws_bytes, uint
     p.retight = retight_of(k, p.limit);
     p.marg = L.marg;
     p.gkey = L.gkey;
+    p.flood = pilot_dist ? 0 : 1;
     p.band = L.band;
     p.bcount = L.bcount;
     p.overflow = &L.cnt->overflow;
@@ -604,7 +644,7 @@ dl_status topk_core(dl_ctx* c, const TopkJob& J, void* ws, size_t ws_bytes, uint
   }
   if (dl_status bad = check_inputs(c)) return bad;
   if (hc.overflow || hc.too_many) {
-    c->required_ws = layout_topk(nullptr, R.n, S.n, R.d, prec, self, P, band_cap * 2, sx).bytes;
+    c->required_ws = topk_workspace(R.n, S.n, R.d, prec, self, sx, k, band_cap * 2, c->cu_count);
     return fail(c, DL_ERR_WORKSPACE, "top-k band exceeded its capacity (%s); retry with band_cap %d",
                 hc.overflow ? "band buffer" : "near-tie contenders", band_cap * 2);
   }

@@ -58,6 +58,16 @@ inline int64_t dpad_of(int d, dl_prec p) {
 // of Numerical Algorithms, Lemma 3.1).
 __host__ __device__ inline double gamma_n(double n, double u) { return n * u / (1.0 - n * u); }
 
+// Order-preserving 32-bit keys of floats (unsigned order = float order;
+// -inf maps to 0x007fffff, NaNs to the ends), and back.
+__host__ __device__ inline uint32_t order_key(float f) {
+  const uint32_t u = __builtin_bit_cast(uint32_t, f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__host__ __device__ inline float key_float(uint32_t k) {
+  return __builtin_bit_cast(float, (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+}
+
 // Wave-wide comparison masks straight from the vector compare (lane l's bit
 // is set when its comparison holds; inactive lanes read 0).  Written with
 // the compare builtins rather than a ballot of a bool, which the compiler

@@ -533,13 +533,6 @@ __device__ inline bool epilogue_eps(const CandParams& p, int64_t ti, int64_t tj,
   return wrote;
 }
 
-__device__ inline uint32_t order_key(float f) {
-  const uint32_t u = __float_as_uint(f);
-  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-__device__ inline float key_float(uint32_t k) {
-  return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
-}
 
 constexpr int kSelPerLane = 8;  // entries per lane in the k-selection subset
 constexpr int kSelBits = 24;    // key bits resolved by the selection
@@ -877,7 +870,8 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
   if constexpr (!kEps) {
     split = uniform64(lit.split);
     for (int r = threadIdx.x; r < kTile; r += kThreads) {
-      band.thr[r] = -INFINITY;
+      // -inf, or a row's seeded threshold (p.flood == 0)
+      band.thr[r] = (!p.flood && ti * kTile + r < p.nR) ? key_float(p.gkey[ti * kTile + r]) : -INFINITY;
       band.cnt[r] = 0;
       band.trig[r] = p.retight;
     }
@@ -981,7 +975,7 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
       mma_step<kPrec, false, false>(acc, lds_ab[st][0], lds_ab[st][1], wm * kWaveM, wn * kWaveN, sa, sb, acc[0], fr);
       mma_tail<kPrec>(acc, fr);
       if (chunk == nsteps - 1) {
-        if (full && ctile == 0) {
+        if (full && ctile == 0 && p.flood) {
           // the first tile: no round has run, every threshold is -inf
           flood_band(p, ti, tj, split, acc, band);
           dirty = true;

@@ -44,6 +44,7 @@ struct CandParams {
   int limit;           // highest trigger; a count reaching it forces a round
   int batch;           // queued rows that start a tightening round
   uint32_t* gkey;      // per row: largest band threshold of any split (order key)
+  int flood;           // 1: every threshold starts at -inf (else from gkey)
   const float* marg;   // E_i per R row
   uint2* band;         // (P~ bits, j): [(row * P + split) * cap + slot]
   int* bcount;         // [row * P + split]

@@ -203,7 +203,7 @@ __global__ __launch_bounds__(256) void threshold_kernel(Prep R, int64_t nR, cons
                                                         int* __restrict__ pex, uint32_t* __restrict__ gkey) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= R.npad) return;
-  if (gkey) gkey[i] = 0x007fffffu;  // order key of -inf (no bound yet)
+  if (gkey) gkey[i] = order_key(-INFINITY);  // no bound yet
   if (i >= nR) {
     if (thr) thr[i] = INFINITY;
     if (marg) marg[i] = 0.0f;
@@ -221,6 +221,33 @@ __global__ __launch_bounds__(256) void threshold_kernel(Prep R, int64_t nR, cons
     if (isinf(T)) thr[i] = -INFINITY;
     else thr[i] = f32_down(0.5 * (a2 - T - E) - 0x1p-50 * (fabs(a2) + fabs(T) + E));
   }
+}
+
+// Seeds each row's top-k band from an exact top-k of the row against a
+// sample of S (dist: the sample's k smallest distances, ascending, +inf
+// padded).  P = x.y - |y|^2/2 = (|x|^2 - d^2)/2, so the sample's k-th
+// smallest d^2 gives a lower bound of the k-th largest P over the sample,
+// hence over S; the band threshold is that bound minus E_i.  The bound is
+// loosened generously (the reported distance is a float rounding of the
+// exact one): any smaller threshold keeps the band a superset.
+__global__ __launch_bounds__(256) void band_seed_kernel(Prep R, int64_t nR, const float* __restrict__ dist, int k,
+                                                        const float* __restrict__ marg, uint32_t* __restrict__ gkey) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nR) return;
+  const float dk = dist[i * k + (k - 1)];
+  if (!(dk < INFINITY)) return;  // fewer than k sample rows: no bound
+  const double d2 = (double)dk * (double)dk * (1.0 + 0x1p-10) + 0x1p-30;
+  const double x2 = R.nrm2[i] * (1.0 - 0x1p-40);
+  const float t = f32_down(0.5 * (x2 - d2) - (double)marg[i] - 0x1p-30);
+  gkey[i] = max(gkey[i], order_key(t));
+}
+
+hipError_t launch_band_seed(const Prep& R, int64_t nR, const float* dist, int k, const float* marg, uint32_t* gkey,
+                            hipStream_t st) {
+  if (nR == 0) return hipSuccess;
+  hipLaunchKernelGGL(band_seed_kernel, dim3((unsigned)((nR + 255) / 256)), dim3(256), 0, st, R, nR, dist, k, marg,
+                     gkey);
+  return hipGetLastError();
 }
 
 hipError_t launch_prep(const float* X, int64_t n, int32_t d, int64_t ld, dl_prec prec, const Prep& P,

@@ -92,3 +92,21 @@ def test_many_splits_large_union(orc, k):
     ref_j, _, ref_dist = orc.topk(R, S, k)
     got = ops.join_topk(dev(R), dev(S), k, prec="bf16")
     assert_topk_equal(got, ref_j, ref_dist, 32, "splits k=%d" % k)
+
+
+def test_fp8_top32_seeded_by_bf16_pilot(orc):
+    """The E4M3 top-32 on a 4,096-centre d = 256 store (the FP8 workload at
+    a tenth of its size: 400,000 store rows, 5,000 queries).  Unseeded, the
+    E4M3 band keeps most unrelated rows until a row has met 32 neighbours
+    and overflows any buffer; the bf16 pilot over every 16th store row seeds
+    it.  The oracle checks 64 sampled query rows (rows of a top-k join are
+    independent)."""
+    cfg = synth.config4(0.1)
+    S, Q = cfg["S"], cfg["Q"]
+    got = ops.join_topk(dev(Q), dev(S), 32, prec="fp8")
+    rows = synth.sample_rows(Q.shape[0], 64, seed=12)
+    ref_j, _, ref_dist = orc.topk(np.ascontiguousarray(Q[rows]), S, 32)
+    sub = ops.TopkResult(got.j[dev(rows).long()], got.dist[dev(rows).long()], 0, 0)
+    assert_topk_equal(sub, ref_j, ref_dist, 256, "fp8 store top-32, sampled rows")
+    # the band stays near the 32 nearest (plus the E4M3 margin's contenders)
+    assert got.band_entries < Q.shape[0] * 2000
