@@ -313,13 +313,14 @@ __device__ inline void issue_side(const CandParams& p, int64_t ti, int64_t tj, c
 // its C operand from init[nb] (the block's initial value -h_j, one register
 // quad per column block) and writes the accumulator, so no per-tile copy of
 // the initial values into the 128 accumulator registers is needed.
+
 // Fragment registers of a K-step (16-bit formats and fp32): the first
 // sub-step's A and B fragments, then the second sub-step's.  They live
 // across the barrier between K-steps: the second sub-step's products of A
-// blocks 4-7 are issued at the start of the next K-step (kTailIn), where
-// their operands are already in registers and they keep the matrix core
-// busy while that step's first fragment reads land; a tile's last K-step
-// leaves them to mma_tail, before the epilogue.
+// blocks kTailFrom..7 are issued at the start of the next K-step (kTailIn),
+// after that step's first fragment reads, so the matrix core has work while
+// those reads land; a tile's last K-step leaves them to mma_tail, before the
+// epilogue.
 struct Frags {
   uint4 a[8], b0[4], b1[4];
 };
@@ -343,7 +344,8 @@ __device__ inline void mac_block(f32x4& c, const f32x4& c0, const uint4& x, cons
   }
 }
 
-// The products a K-step leaves for later: second sub-step, A blocks 4-7.
+// The products a K-step leaves for later: second sub-step, A blocks
+// kTailFrom..7.
 template <int kPrec>
 __device__ inline void mma_tail(f32x4 (&acc)[8][4], const Frags& fr) {
   if constexpr (kPrec != DL_FP8) {
@@ -405,8 +407,8 @@ __device__ inline void mma_step(f32x4 (&acc)[8][4], const uint8_t* la, const uin
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb) mac_block<kPrec>(acc[mb][nb], acc[mb][nb], a[mb], b1[nb]);
     }
-    // A blocks 4-7 of the second sub-step: mma_tail, at the next K-step or
-    // before the epilogue
+    // A blocks kTailFrom..7 of the second sub-step: mma_tail, at the next
+    // K-step or before the epilogue
   } else {
     // E4M3, 128 bytes = 128 values per row: 16x16x128 with per-row E8M0
     // scales; each lane reads 32 bytes per fragment; a window of four A
@@ -763,9 +765,10 @@ __device__ inline bool tighten_rows(const CandParams& p, int64_t ti, int64_t spl
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int limit = p.limit;
   // Every row's band threshold first rises to the best one any split of the
-  // row has published: each is v_s - E_i with v_s a lower bound of the k-th
-  // largest P~ over a subset of S, so at most the k-th largest over all of S
-  // minus E_i (the band stays a superset of the exact one).
+  // row has published (or a seed, see the E4M3 pilot on the host): each is
+  // v - E_i with v a lower bound of the k-th largest P~ over a subset of S,
+  // so at most the k-th largest over all of S minus E_i (the band stays a
+  // superset of the exact one).
   for (int r = threadIdx.x; r < kTile; r += kThreads) {
     const int64_t i = ti * kTile + r;
     if (i < p.nR) {
