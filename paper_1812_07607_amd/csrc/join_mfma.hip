@@ -53,8 +53,6 @@ struct Pipe {
   static constexpr int kStageBytes = kTile * kCB;                 // one operand, one step
   static constexpr int kStages = kRingBytes / (2 * kStageBytes);  // 2 or 4
   static constexpr int kRowsPerDma = 1024 / kCB;                  // rows per 1 KiB transfer
-  static constexpr int kDmaPerOp = kTile / kRowsPerDma / (kThreads / 64);  // per wave, per operand
-  static constexpr int kPerStep = 2 * kDmaPerOp;                  // operand transfers per wave per step
 };
 
 typedef __attribute__((address_space(1))) void gvoid_t;
@@ -92,6 +90,17 @@ __device__ inline int lds_off(int r, int c) {
 }
 
 enum : int { kModeEps = 0, kModeBand = 1 };
+
+// Waves that issue the operand transfers (waves w and w + 4 share a SIMD).
+// Fewer issuing waves leave more waves free of transfers to feed the matrix
+// cores while the issuers wait on the vector-memory queue.  Measured: eps
+// mode is 1-2% faster with two issuers than with four (eight lose 6%); band
+// mode, whose epilogue and tightening already load waves unevenly, is 1%
+// faster with four.
+template <int kMode>
+constexpr int dma_waves() { return kMode == kModeEps ? 2 : 4; }
+template <int kMode>
+constexpr int dma_per_op(int rows_per_dma) { return kTile / rows_per_dma / dma_waves<kMode>(); }
 
 
 
@@ -229,14 +238,10 @@ struct TileIter {
 // one 1 KiB global_load_lds_dwordx4: lane l fills LDS slot l of the block,
 // i.e. row q * kRowsPerDma + l / kSlots, physical piece l % kSlots, so it
 // fetches the logical piece that the swizzle puts there.
-// Waves that issue the operand transfers.  Waves w and w + 4 share a SIMD;
-// with 4 issuing waves each SIMD keeps one wave free of transfers, which
-// can feed the matrix core while its partner waits on the vector-memory
-// queue.
-constexpr int kDmaWaves = 4;
 
-template <int kPrec>
+template <int kPrec, int kMode>
 __device__ inline void issue_loads(const CandParams& p, int64_t ti, int64_t tj, int step, uint8_t* la, uint8_t* lb) {
+  constexpr int kDmaWaves = dma_waves<kMode>();
   using Q = Pipe<kPrec>;
   // wave-uniform tile bases and LDS destinations (scalar registers) + a
   // 32-bit in-tile offset per lane and block, recomputed from an opaque lane
@@ -245,7 +250,7 @@ __device__ inline void issue_loads(const CandParams& p, int64_t ti, int64_t tj, 
   const int lane = fresh_lane();
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (wave >= kDmaWaves) return;
-  constexpr int kPer = kTile / Q::kRowsPerDma / kDmaWaves;  // blocks per issuing wave and operand
+  constexpr int kPer = dma_per_op<kMode>(Q::kRowsPerDma);  // blocks per issuing wave and operand
   const uint8_t* ga0 = p.qa + (ti * kTile) * p.qld + (int64_t)step * Q::kCB;
   const int64_t dba = (p.qb + (tj * kTile) * p.qld) - (p.qa + (ti * kTile) * p.qld);  // B source - A source
   // The swizzle key of a row repeats every 2 * kRowsPerDma rows, so block t
@@ -284,6 +289,7 @@ struct SideRefs {
 template <int kPrec, int kMode>
 __device__ inline void issue_side(const CandParams& p, int64_t ti, int64_t tj, const SideRefs& d) {
   // by the waves that issue no operand transfers, if there are such
+  constexpr int kDmaWaves = dma_waves<kMode>();
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) - (kDmaWaves < 8 ? kDmaWaves : 0);
   const int e = 4 * fresh_lane();
   if (w == 0) lds_dma16(p.hb + tj * kTile + e, d.hb);
@@ -818,7 +824,10 @@ template <int kPrec, int kMode>
 __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
   using Q = Pipe<kPrec>;
   static_assert(Q::kStages == 2 || Q::kStages == 4, "ring depth");
-  static_assert((Q::kStages - 2) * Q::kPerStep <= 8, "wait_and_sync covers two later steps at most");
+  // operand transfers per issuing wave per step (the count a wait leaves in
+  // flight per later step)
+  constexpr int kPerStep = 2 * dma_per_op<kMode>(Q::kRowsPerDma);
+  static_assert((Q::kStages - 2) * kPerStep <= 8, "wait_and_sync covers two later steps at most");
   constexpr bool kFp8 = kPrec == DL_FP8, kEps = kMode == kModeEps;
   // the ring: kStages x (A step, B step)
   __shared__ __attribute__((aligned(1024))) uint8_t lds_ab[Q::kStages][2][Q::kStageBytes];
@@ -858,7 +867,7 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
                                                       side_sb[kFp8 ? sb : 0]});
     }
     const int st = issued % Q::kStages;
-    issue_loads<kPrec>(p, lti, ltj, lstep, lds_ab[st][0], lds_ab[st][1]);
+    issue_loads<kPrec, kMode>(p, lti, ltj, lstep, lds_ab[st][0], lds_ab[st][1]);
     iti = lti;
     itj = ltj;
     ++issued;
@@ -904,7 +913,7 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
     // after the next barrier (mma_step, kTailIn)
     for (;;) {  // one tile per pass
       // ---- the tile's first K-step
-      wait_and_sync(dirty ? 0 : (issued - step - 1) * Q::kPerStep);
+      wait_and_sync(dirty ? 0 : (issued - step - 1) * kPerStep);
       dirty = false;
       const int sbuf = ctile % 3;
       bool more = lmore;  // a step follows the current one
@@ -929,7 +938,7 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
       ++step;
       // ---- its other K-steps
       for (int c = 1; c < nsteps; ++c) {
-        wait_and_sync(dirty ? 0 : (issued - step - 1) * Q::kPerStep);
+        wait_and_sync(dirty ? 0 : (issued - step - 1) * kPerStep);
         dirty = false;
         more = lmore;
         if (lmore) issue();
@@ -950,7 +959,7 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
     // products are all issued before the next barrier
     int chunk = 0;
     for (;;) {
-      wait_and_sync(dirty ? 0 : (issued - step - 1) * Q::kPerStep);
+      wait_and_sync(dirty ? 0 : (issued - step - 1) * kPerStep);
       dirty = false;
       const int sbuf = ctile % 3;
       const bool more = lmore;  // a step follows this one
