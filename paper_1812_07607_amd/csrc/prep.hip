@@ -61,8 +61,9 @@ __global__ __launch_bounds__(256) void prep_kernel(const float* __restrict__ X, 
   double nrm2 = 0.0, qn2 = 0.0, r2 = 0.0;
   int qlsb = kLsbNone, mlsb = kLsbNone, bad = 0;
   uint8_t* qrow = reinterpret_cast<uint8_t*>(P.q) + row * P.qld;
-  for (int64_t k = lane; k < dpad; k += 64) {
-    float v = (real && k < d) ? x[k] : 0.0f;
+  // one element: the operand copy and the row statistics (in index order per
+  // lane)
+  auto element = [&](float v, int64_t k) {
     if (!isfinite(v)) { bad++; v = 0.0f; }
     float qv;
     if (kPrec == DL_FP32) {
@@ -87,6 +88,26 @@ __global__ __launch_bounds__(256) void prep_kernel(const float* __restrict__ X, 
     r2 += dr * dr;
     qlsb = min(qlsb, lsb_exp(qv));
     mlsb = min(mlsb, lsb_exp(v));
+  };
+  if (real) {
+    // eight of the row's loads in flight per lane (clamped into the row,
+    // zero past d), then the elements in order
+    const int64_t dm1 = d - 1;
+    int64_t k = lane;
+    for (; k + 64 * 7 < dpad; k += 64 * 8) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t kk = k + 64 * u;
+        const float t = x[kk < d ? kk : dm1];
+        v[u] = kk < d ? t : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) element(v[u], k + 64 * u);
+    }
+    for (; k < dpad; k += 64) element(k < d ? x[k] : 0.0f, k);
+  } else {
+    for (int64_t k = lane; k < dpad; k += 64) element(0.0f, k);
   }
   nrm2 = wave_sum(nrm2);
   qn2 = wave_sum(qn2);
