@@ -174,7 +174,9 @@ typedef struct dl_topk_info {
 } dl_topk_info;
 
 /* Scratch bytes for dl_join_topk with `band_cap` band entries per row and
- * S-split (0 = library default). */
+ * S-split (0 = library default).  For DL_FP8 (not self-joins, nS at least
+ * 4,096 rows) this includes an exact bf16 pilot top-k against every 16th row
+ * of S, whose k-th distances seed the E4M3 band thresholds. */
 size_t dl_join_topk_workspace(int64_t nR, int64_t nS, int32_t d, dl_prec prec,
                               int self_join, int32_t k, int32_t band_cap);
 
@@ -185,9 +187,11 @@ size_t dl_join_topk_workspace(int64_t nR, int64_t nS, int32_t d, dl_prec prec,
  *   out_j     device uint32[nR*k]; UINT32_MAX pads rows with fewer than k.
  *   out_dist  device float[nR*k];  +inf pads.
  *   info      host, nullable.
- * Returns DL_ERR_WORKSPACE if a row's band does not fit band_cap (retry with
- * a larger band_cap), DL_ERR_INVALID for bad arguments.  Synchronises
- * `stream`. */
+ * Returns DL_ERR_WORKSPACE if the workspace is too small, if a row's band
+ * does not fit band_cap ("band buffer" in dl_last_error: retry with a larger
+ * band_cap), or if a row has more near-tie contenders than the selection
+ * holds (512; a larger band_cap does not help); DL_ERR_INVALID for bad
+ * arguments.  Synchronises `stream`. */
 dl_status dl_join_topk(dl_ctx* ctx, dl_mat R, dl_mat S, int self_join,
                        int32_t k, int exclude_self, dl_prec prec,
                        int32_t band_cap, void* ws, size_t ws_bytes,

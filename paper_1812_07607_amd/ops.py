@@ -38,6 +38,12 @@ class Context:
         if st != _lib.DL_OK:
             raise _lib.DLError(st, self.L.dl_last_error(self.h).decode())
 
+    def band_full(self, st: int) -> bool:
+        """A top-k call failed only because a row's band buffer was full (a
+        larger band_cap helps; more near-tie contenders than the selection
+        holds does not)."""
+        return st == _lib.DL_ERR_WORKSPACE and b"band buffer" in (self.L.dl_last_error(self.h) or b"")
+
     def __del__(self):
         try:
             if getattr(self, "h", None):
@@ -210,7 +216,7 @@ def join_topk(R: torch.Tensor, S: torch.Tensor | None, k: int, exclude_self: boo
         st = c.L.dl_join_topk(c.h, _mat(R), _mat(Sm), int(self_join), k, int(exclude_self), p, band_cap,
                               ctypes.c_void_p(buf.data_ptr()), buf.numel(), ctypes.c_void_p(oj.data_ptr()),
                               ctypes.c_void_p(od.data_ptr()), ctypes.byref(info), _stream_ptr(stream))
-        if st == _lib.DL_ERR_WORKSPACE:
+        if c.band_full(st):
             band_cap = max(2 * (band_cap or 1024), 1024)
             continue
         c.check(st)
@@ -285,7 +291,7 @@ class Store:
             st = L.dl_join_topk_store(c.h, _mat(R), self.h, k, band_cap, ctypes.c_void_p(buf.data_ptr()), buf.numel(),
                                       ctypes.c_void_p(oj.data_ptr()), ctypes.c_void_p(od.data_ptr()), ctypes.byref(info),
                                       _stream_ptr(stream))
-            if st == _lib.DL_ERR_WORKSPACE:
+            if c.band_full(st):
                 band_cap = max(2 * (band_cap or 1024), 1024)
                 continue
             c.check(st)
