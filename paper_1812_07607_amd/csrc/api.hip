@@ -26,7 +26,8 @@ hipError_t launch_cand_band(dl_prec, CandParams, hipStream_t);
 hipError_t launch_recheck_eps(const RecheckParams&, hipStream_t, int);
 hipError_t launch_pair_d2(const float*, int64_t, int64_t, const float*, int64_t, int64_t, int, const uint32_t*,
                           const uint32_t*, int64_t, double*, int*, hipStream_t, int);
-hipError_t launch_topk_select(const SelectParams&, hipStream_t);
+hipError_t launch_topk_select(const SelectParams&, bool, hipStream_t);
+bool topk_select_small(int);
 int64_t scan_scratch_words(int64_t);
 int64_t radix_hist_words(int64_t);
 int radix_sort_pairs(unsigned long long*, float*, unsigned long long*, float*, int64_t, int, uint32_t*, uint32_t*,
@@ -52,6 +53,7 @@ struct Counters {
   int pad[13];
 };
 static_assert(sizeof(Counters) == 96, "counter block size");
+static_assert(offsetof(Counters, band) == offsetof(Counters, ties) + 8, "ties and band are cleared together");
 
 // ------------------------------------------------------------ workspace
 static Prep carve_prep(Bump& b, int64_t n, int d, dl_prec prec) {
@@ -622,9 +624,10 @@ dl_status topk_core(dl_ctx* c, const TopkJob& J, void* ws, size_t ws_bytes, uint
     p.overflow = &L.cnt->overflow;
     DL_HIP(c, launch_cand_band(prec, p, st));
   }
+  SelectParams q{};
+  const bool small_sel = topk_select_small(k);
   {
     StageTimer t(c, 5, st);
-    SelectParams q{};
     q.R = R.data; q.ldr = R.ld;
     q.S = S.data; q.lds = S.ld;
     q.d = R.d; q.nR = R.n;
@@ -634,10 +637,24 @@ dl_status topk_core(dl_ctx* c, const TopkJob& J, void* ws, size_t ws_bytes, uint
     q.sS = L.ss;
     q.out_j = out_j; q.out_dist = out_dist;
     q.nband = &L.cnt->band; q.nties = &L.cnt->ties; q.too_many = &L.cnt->too_many;
-    DL_HIP(c, launch_topk_select(q, st));
+    DL_HIP(c, launch_topk_select(q, small_sel, st));
   }
   DL_HIP(c, readback(c, L.cnt, L.sr, L.ss, st));
-  const Counters hc = *reinterpret_cast<const Counters*>(c->pinned);
+  Counters hc = *reinterpret_cast<const Counters*>(c->pinned);
+  if (small_sel && hc.too_many && !hc.overflow) {
+    // a row had more near-tie contenders than the small selection holds:
+    // select again (the bands are unchanged) with the large one
+    hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(&L.cnt->ties),
+                       (int64_t)4);  // ties and band
+    hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(&L.cnt->too_many),
+                       (int64_t)1);
+    {
+      StageTimer t(c, 5, st);
+      DL_HIP(c, launch_topk_select(q, false, st));
+    }
+    DL_HIP(c, readback(c, L.cnt, L.sr, L.ss, st));
+    hc = *reinterpret_cast<const Counters*>(c->pinned);
+  }
   if (info) {
     info->band_entries = (int64_t)hc.band;
     info->ties = (int64_t)hc.ties;

@@ -178,7 +178,11 @@ hipError_t launch_pair_d2(const float* R, int64_t ldr, int64_t nR, const float* 
 }
 
 // ------------------------------------------------------------ top-k select
-constexpr int kSelMax = 512;  // contenders per row held in LDS
+// Contenders per row held in LDS: kSelSmall for k <= 128 (smaller LDS
+// buffers, more waves per CU), kSelLarge otherwise and whenever a row of
+// the small launch had more (the host then runs the select again).
+constexpr int kSelSmall = 256;
+constexpr int kSelLarge = 512;
 constexpr int kSelWaves = 4;
 constexpr int kSelRegs = 8;   // band entries per lane held in registers (unions up to 512)
 
@@ -223,10 +227,13 @@ __device__ inline float lane_d2(const float* a, const float* b, int d, bool vec4
 // (scalar popcounts, no shuffle chains); distances are computed one entry
 // per lane; the k nearest are emitted by rank, since the (key, j) pairs of a
 // row are distinct.
-__global__ __launch_bounds__(64 * kSelWaves) void topk_select_kernel(SelectParams p) {
-  __shared__ float s_d2[kSelWaves][kSelMax];
-  __shared__ uint32_t s_j[kSelWaves][kSelMax];
-  __shared__ double s_key[kSelWaves][kSelMax];
+// LDS per wave: the contenders' float32 d2, j and float64 key (16 bytes
+// each), and, before any contender is written, the staged band entries
+// (64 * kSelRegs of 8 bytes) in the same bytes.
+template <int kSelMax>
+__global__ __launch_bounds__(64 * kSelWaves, kSelMax == kSelSmall ? 6 : 4) void topk_select_kernel(SelectParams p) {
+  constexpr int kBytes = 16 * kSelMax > 8 * 64 * kSelRegs ? 16 * kSelMax : 8 * 64 * kSelRegs;
+  __shared__ __attribute__((aligned(16))) uint8_t s_buf[kSelWaves][kBytes];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t i = (int64_t)blockIdx.x * kSelWaves + wave;
@@ -256,9 +263,9 @@ __global__ __launch_bounds__(64 * kSelWaves) void topk_select_kernel(SelectParam
   const double c0 = ex ? 0.0 : ((double)p.d + 2.0) * 0x1p-148 + ((double)p.d + 4.0) * 0x1p-52 * xsum * xsum;
   const bool vec4 = ((reinterpret_cast<uintptr_t>(p.S) | reinterpret_cast<uintptr_t>(a)) & 15) == 0 &&
                     (p.lds & 3) == 0;
-  float* cd = s_d2[wave];
-  uint32_t* cj = s_j[wave];
-  double* ck = s_key[wave];
+  float* cd = reinterpret_cast<float*>(s_buf[wave]);
+  uint32_t* cj = reinterpret_cast<uint32_t*>(s_buf[wave] + 4 * kSelMax);
+  double* ck = reinterpret_cast<double*>(s_buf[wave] + 8 * kSelMax);
   int nc = 0, nb = 0;
   // entries with d2 - beta > D_k + beta(D_k) cannot be among the k nearest
   auto cut_of = [&](uint64_t dk) {
@@ -267,7 +274,7 @@ __global__ __launch_bounds__(64 * kSelWaves) void topk_select_kernel(SelectParam
   };
   // Stage into LDS, compactly, the union's entries with P~ >= floor (up to
   // 64 * kSelRegs of them); returns how many there are.
-  uint2* st = reinterpret_cast<uint2*>(ck);
+  uint2* st = reinterpret_cast<uint2*>(s_buf[wave]);
   auto stage = [&](float floor) {
     int g = 0;
     for (int s = 0; s < p.P; ++s) {
@@ -495,11 +502,13 @@ __global__ __launch_bounds__(64 * kSelWaves) void topk_select_kernel(SelectParam
   }
 }
 
-hipError_t launch_topk_select(const SelectParams& p, hipStream_t st) {
+hipError_t launch_topk_select(const SelectParams& p, bool small, hipStream_t st) {
   if (p.nR == 0) return hipSuccess;
-  hipLaunchKernelGGL(topk_select_kernel, dim3((unsigned)((p.nR + kSelWaves - 1) / kSelWaves)), dim3(64 * kSelWaves), 0,
-                     st, p);
+  const dim3 grid((unsigned)((p.nR + kSelWaves - 1) / kSelWaves)), block(64 * kSelWaves);
+  if (small) hipLaunchKernelGGL(topk_select_kernel<kSelSmall>, grid, block, 0, st, p);
+  else hipLaunchKernelGGL(topk_select_kernel<kSelLarge>, grid, block, 0, st, p);
   return hipGetLastError();
 }
+bool topk_select_small(int k) { return k <= 128; }
 
 }  // namespace dl

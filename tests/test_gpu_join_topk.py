@@ -110,3 +110,17 @@ def test_fp8_top32_seeded_by_bf16_pilot(orc):
     assert_topk_equal(sub, ref_j, ref_dist, 256, "fp8 store top-32, sampled rows")
     # the band stays near the 32 nearest (plus the E4M3 margin's contenders)
     assert got.band_entries < Q.shape[0] * 2000
+
+
+def test_many_exact_ties_use_the_large_selection(orc):
+    """300 copies of one row in S, all at the same distance from every query
+    row: more near-tie contenders than the small selection holds (256), so
+    the library selects again with the large one (512); ties go to the
+    smaller index."""
+    rng = np.random.default_rng(77)
+    S = rng.standard_normal((3000, 48)).astype(np.float32)
+    S[1000:1300] = S[5]
+    R = (S[5] + 0.01 * rng.standard_normal((40, 48))).astype(np.float32)
+    ref_j, _, ref_dist = orc.topk(R, S, 10)
+    got = ops.join_topk(dev(R), dev(S), 10, prec="bf16")
+    assert_topk_equal(got, ref_j, ref_dist, 48, "300 exact ties")
