@@ -28,12 +28,9 @@ hipError_t launch_pair_d2(const float*, int64_t, int64_t, const float*, int64_t,
                           const uint32_t*, int64_t, double*, int*, hipStream_t, int);
 hipError_t launch_topk_select(const SelectParams&, bool, hipStream_t);
 bool topk_select_small(int);
-int64_t scan_scratch_words(int64_t);
-int64_t radix_hist_words(int64_t);
-int radix_sort_pairs(unsigned long long*, float*, unsigned long long*, float*, int64_t, int, uint32_t*, uint32_t*,
-                     hipStream_t, hipError_t*);
-hipError_t launch_unpack_pairs(const unsigned long long*, const float*, int64_t, int, uint32_t*, uint32_t*, float*,
-                               hipStream_t, int);
+int64_t row_sort_words(int64_t);
+hipError_t row_sort_pairs(const unsigned long long*, const float*, int64_t, int64_t, int, unsigned long long*, float*,
+                          uint32_t*, int64_t, uint32_t*, uint32_t*, float*, hipStream_t, int);
 
 // ------------------------------------------------------------ small kernels
 __global__ void zero_words_kernel(uint32_t* p, int64_t n) {
@@ -84,7 +81,7 @@ struct EpsLayout {
   float* candp;
   unsigned long long *k0, *k1;
   float *v0, *v1;
-  uint32_t *hist, *scan;
+  uint32_t* rows;  // row-sort scratch
   size_t bytes;
 };
 
@@ -108,9 +105,7 @@ static EpsLayout layout_eps(void* ws, int64_t nR, int64_t nS, int d, dl_prec pre
   L.k1 = b.take<unsigned long long>(c);
   L.v0 = b.take<float>(c);
   L.v1 = b.take<float>(c);
-  const int64_t hw = radix_hist_words(c);
-  L.hist = b.take<uint32_t>(hw);
-  L.scan = b.take<uint32_t>(scan_scratch_words(hw) + 1);
+  L.rows = b.take<uint32_t>(row_sort_words(nR < 1 ? 1 : nR));
   L.bytes = round_up((int64_t)b.off, 256);
   return L;
 }
@@ -493,7 +488,7 @@ dl_status eps_core(dl_ctx* c, const EpsJob& J, void* ws, size_t ws_bytes, dl_pai
     p.ccap = cap;
     DL_HIP(c, launch_cand_eps(prec, p, st, c->cu_count));
   }
-  const int bj = bits_for(S.n), bi = bits_for(R.n);
+  const int bj = bits_for(S.n);  // the recheck's keys are i << bj | j
   {
     StageTimer t(c, 3, st);
     RecheckParams q{};
@@ -526,12 +521,9 @@ dl_status eps_core(dl_ctx* c, const EpsJob& J, void* ws, size_t ws_bytes, dl_pai
   out->count = m;
   {
     StageTimer t(c, 4, st);
-    hipError_t e;
-    const int which = radix_sort_pairs(L.k0, L.v0, L.k1, L.v1, m, bi + bj, L.hist, L.scan, st, &e);
-    DL_HIP(c, e);
     const int64_t w = m < out->capacity ? m : out->capacity;
-    DL_HIP(c, launch_unpack_pairs(which ? L.k1 : L.k0, which ? L.v1 : L.v0, w, bj, out->i, out->j, out->dist, st,
-                                  c->cu_count));
+    DL_HIP(c, row_sort_pairs(L.k0, L.v0, m, R.n, bj, L.k1, L.v1, L.rows, w, out->i, out->j, out->dist, st,
+                             c->cu_count));
   }
   if (m > out->capacity)
     return fail(c, DL_ERR_CAPACITY, "%lld pairs exceed the output capacity %lld", (long long)m,

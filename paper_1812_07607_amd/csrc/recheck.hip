@@ -241,20 +241,6 @@ __global__ __launch_bounds__(64 * kSelWaves, kSelMax == kSelSmall ? 6 : 4) void 
   const float* a = p.R + i * p.ldr;
   const int k = p.k;
   const uint64_t lt = __lanemask_lt();
-  // number of entries of the row whose first word w satisfies pred(w)
-  auto count = [&](auto pred) {
-    int c = 0;
-    for (int s = 0; s < p.P; ++s) {
-      const uint2* e = p.band + (i * p.P + s) * (int64_t)p.cap;
-      const int n = p.bcount[i * p.P + s];
-      for (int base = 0; base < n; base += 64) {
-        const int t = base + lane;
-        c += __popcll(__ballot(t < n && pred(e[t].x)));
-      }
-    }
-    return c;
-  };
-
   int total = 0;
   for (int s = 0; s < p.P; ++s) total += p.bcount[i * p.P + s];
   const double xsum = (double)p.xnR[i] + (double)p.sS->xnorm_max;

@@ -1,18 +1,13 @@
 // sort.hip -- canonical (i, j) order for the eps-join output.
 //
-// Stable least-significant-digit radix sort of 64-bit keys (i << bj | j) with
-// a float payload, 8 bits per pass over only the bits the keys use.  Each
-// pass: per-tile digit histograms, one exclusive scan over the digit-major
-// histogram table, and a stable scatter that ranks equal digits inside a
-// tile with wave ballots.  Deterministic: the output depends only on the
-// set of keys, not on the order the candidate kernel produced them in.
+// The confirmed pairs (keys i << bj | j with a float distance) are bucketed
+// by row with a count, an exclusive scan and an atomic placement, then each
+// row's segment is ordered by j.  Deterministic: the output depends only on
+// the set of pairs, not on the order the candidate kernel produced them in.
 #include "dl_internal.hpp"
 
 namespace dl {
 
-constexpr int kSortThreads = 256;
-constexpr int kSortItems = 8;
-constexpr int kSortTile = kSortThreads * kSortItems;  // keys per tile
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanChunk = kScanThreads * kScanItems;  // 4096
@@ -100,117 +95,153 @@ hipError_t launch_exclusive_scan(const uint32_t* in, int64_t n, uint32_t* out, u
   return hipGetLastError();
 }
 
-// --------------------------------------------------------------- radix
-// hist layout: digit-major, hist[digit * ntiles + tile]
-__global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const unsigned long long* keys, int64_t n, int shift,
-                                                                  uint32_t* hist, int64_t ntiles) {
-  __shared__ uint32_t h[256];
-  h[threadIdx.x] = 0;
-  __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
-  for (int t = 0; t < kSortItems; ++t) {
-    const int64_t idx = base + (int64_t)t * kSortThreads + threadIdx.x;
-    if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 255u], 1u);
-  }
-  __syncthreads();
-  hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+// --------------------------------------------------------------- rows
+// Canonical (i, j) order by rows: count the pairs of each row, scan the
+// counts into row offsets, place every pair in its row's segment (in any
+// order), then order each segment by j, one wave per row.  A pair's output
+// slot is the number of the row's pairs with a smaller j (the (i, j) pairs
+// are distinct, so the result does not depend on the order of placement):
+// rows of at most 64 pairs rank in registers; longer rows set one bit per
+// pair in an LDS bitmap over a window of j, take a prefix count of the
+// bitmap words, and read each pair's rank from it, window by window, so the
+// work is linear in the row length.  Seven launches where an 8-bit LSD radix
+// sort of 34-bit keys takes 25.
+__global__ void fill_words_kernel(uint32_t* p, int64_t n, uint32_t v) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    p[t] = v;
 }
 
-__global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(const unsigned long long* kin, const float* vin,
-                                                                     int64_t n, int shift, const uint32_t* offs,
-                                                                     int64_t ntiles, unsigned long long* kout,
-                                                                     float* vout) {
-  __shared__ uint32_t run[256];           // keys of each digit already placed by this tile
-  __shared__ uint32_t wcnt[kSortThreads / 64][256];
-  const int wave = threadIdx.x >> 6;
-  run[threadIdx.x] = 0;
-  for (int w = 0; w < kSortThreads / 64; ++w) wcnt[w][threadIdx.x] = 0;
-  __syncthreads();
-  const uint64_t lt = __lanemask_lt();
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
-  for (int t = 0; t < kSortItems; ++t) {
-    // keys of this round are in index order wave-major, lane-minor
-    const int64_t idx = base + (int64_t)t * kSortThreads + threadIdx.x;
-    const bool valid = idx < n;
-    unsigned long long key = 0;
-    float val = 0.0f;
-    uint32_t dig = 0;
-    if (valid) {
-      key = kin[idx];
-      val = vin[idx];
-      dig = (uint32_t)(key >> shift) & 255u;
-    }
-    uint64_t peers = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const uint64_t bal = __ballot((dig >> b) & 1u);
-      peers &= ((dig >> b) & 1u) ? bal : ~bal;
-    }
-    const int rank = __popcll(peers & lt);
-    const bool leader = valid && rank == 0;
-    if (leader) wcnt[wave][dig] = __popcll(peers);
-    __syncthreads();
-    if (valid) {
-      uint32_t pos = run[dig] + rank;
-      for (int w = 0; w < wave; ++w) pos += wcnt[w][dig];
-      const uint64_t gp = offs[(int64_t)dig * ntiles + blockIdx.x] + pos;
-      kout[gp] = key;
-      vout[gp] = val;
-    }
-    __syncthreads();
-    uint32_t add = 0;
-    for (int w = 0; w < kSortThreads / 64; ++w) {
-      add += wcnt[w][threadIdx.x];
-      wcnt[w][threadIdx.x] = 0;
-    }
-    run[threadIdx.x] += add;
-    __syncthreads();
-  }
+__global__ void count_rows_kernel(const unsigned long long* __restrict__ keys, int64_t m, int bj,
+                                  uint32_t* __restrict__ cnt) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(&cnt[keys[t] >> bj], 1u);
 }
 
-__global__ void unpack_pairs_kernel(const unsigned long long* keys, const float* vals, int64_t m, int bj, uint32_t* oi,
-                                    uint32_t* oj, float* od) {
-  const unsigned long long mask = (1ull << bj) - 1;
+__global__ void place_rows_kernel(const unsigned long long* __restrict__ keys, const float* __restrict__ vals,
+                                  int64_t m, int bj, const uint32_t* __restrict__ off, uint32_t* __restrict__ fill,
+                                  unsigned long long* __restrict__ pk, float* __restrict__ pv) {
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x) {
     const unsigned long long k = keys[t];
-    oi[t] = (uint32_t)(k >> bj);
-    oj[t] = (uint32_t)(k & mask);
-    od[t] = vals[t];
+    const uint64_t i = k >> bj;
+    const uint32_t pos = off[i] + atomicAdd(&fill[i], 1u);
+    pk[pos] = k;
+    pv[pos] = vals[t];
   }
 }
 
-int64_t radix_hist_words(int64_t n) { return 256 * ((n + kSortTile - 1) / kSortTile); }
+constexpr int kRowWaves = 4;
+constexpr int kWinWords = 1024;             // bitmap words per wave
+constexpr int kWinBits = 32 * kWinWords;    // j values per window
+constexpr int kWordsPerLane = kWinWords / 64;
 
-// Sorts (k0, v0) of n entries by the low `bits` key bits.  Uses (k1, v1) as
-// the other buffer; returns which buffer holds the result (0 or 1).
-int radix_sort_pairs(unsigned long long* k0, float* v0, unsigned long long* k1, float* v1, int64_t n, int bits,
-                     uint32_t* hist, uint32_t* scan_sums, hipStream_t st, hipError_t* err) {
-  *err = hipSuccess;
-  if (n <= 1) return 0;
-  const int64_t ntiles = (n + kSortTile - 1) / kSortTile;
-  int cur = 0;
-  for (int shift = 0; shift < bits; shift += 8) {
-    unsigned long long* ki = cur ? k1 : k0;
-    float* vi = cur ? v1 : v0;
-    unsigned long long* ko = cur ? k0 : k1;
-    float* vo = cur ? v0 : v1;
-    hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)ntiles), dim3(kSortThreads), 0, st, ki, n, shift, hist, ntiles);
-    hipError_t e = launch_exclusive_scan(hist, 256 * ntiles, hist, scan_sums, st);
-    if (e != hipSuccess) { *err = e; return cur; }
-    hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)ntiles), dim3(kSortThreads), 0, st, ki, vi, n, shift, hist,
-                       ntiles, ko, vo);
-    cur ^= 1;
-  }
-  *err = hipGetLastError();
-  return cur;
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_wave_barrier();
 }
 
-hipError_t launch_unpack_pairs(const unsigned long long* keys, const float* vals, int64_t m, int bj, uint32_t* oi,
-                               uint32_t* oj, float* od, hipStream_t st, int cu_count) {
-  if (m == 0) return hipSuccess;
-  int64_t blocks = (m + 255) / 256;
-  if (blocks > (int64_t)cu_count * 8) blocks = (int64_t)cu_count * 8;
-  hipLaunchKernelGGL(unpack_pairs_kernel, dim3((unsigned)blocks), dim3(256), 0, st, keys, vals, m, bj, oi, oj, od);
+__global__ __launch_bounds__(64 * kRowWaves) void order_rows_kernel(const unsigned long long* __restrict__ pk,
+                                                                   const float* __restrict__ pv, int64_t nR,
+                                                                   const uint32_t* __restrict__ off, int64_t m,
+                                                                   int bj, int64_t w, uint32_t* __restrict__ oi,
+                                                                   uint32_t* __restrict__ oj, float* __restrict__ od) {
+  __shared__ uint32_t bits_lds[kRowWaves][kWinWords];
+  __shared__ uint32_t pre_lds[kRowWaves][kWinWords];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * kRowWaves + wave;
+  if (i >= nR) return;
+  const int64_t b = off[i], e = i + 1 < nR ? (int64_t)off[i + 1] : m;
+  const unsigned long long mask = (1ull << bj) - 1;
+  auto emit = [&](int64_t at, int64_t t, uint32_t j) {
+    if (at < w) {
+      oi[at] = (uint32_t)i;
+      oj[at] = j;
+      od[at] = pv[t];
+    }
+  };
+  if (e - b <= 64) {
+    const int64_t t = b + lane;
+    const uint32_t j = t < e ? (uint32_t)(pk[t] & mask) : 0xffffffffu;
+    int rank = 0;
+    for (int u = 0; u < (int)(e - b); ++u) rank += __shfl(j, u, 64) < j;
+    if (t < e) emit(b + rank, t, j);
+    return;
+  }
+  uint32_t* bm = bits_lds[wave];
+  uint32_t* pre = pre_lds[wave];
+  uint32_t jlo = 0xffffffffu, jhi = 0;
+  for (int64_t t = b + lane; t < e; t += 64) {
+    const uint32_t j = (uint32_t)(pk[t] & mask);
+    jlo = j < jlo ? j : jlo;
+    jhi = j > jhi ? j : jhi;
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const uint32_t a = __shfl_xor(jlo, o, 64), z = __shfl_xor(jhi, o, 64);
+    jlo = a < jlo ? a : jlo;
+    jhi = z > jhi ? z : jhi;
+  }
+  int64_t below = 0;  // pairs of the row in earlier windows
+  for (uint64_t lo = jlo; lo <= jhi; lo += kWinBits) {
+#pragma unroll
+    for (int q = 0; q < kWordsPerLane; ++q) bm[lane * kWordsPerLane + q] = 0;
+    wave_lds_sync();
+    for (int64_t t = b + lane; t < e; t += 64) {
+      const uint64_t r = (pk[t] & mask) - lo;
+      if (r < (uint64_t)kWinBits) atomicOr(&bm[r >> 5], 1u << (r & 31));
+    }
+    wave_lds_sync();
+    uint32_t c[kWordsPerLane], run = 0;
+#pragma unroll
+    for (int q = 0; q < kWordsPerLane; ++q) {
+      c[q] = run;
+      run += __popc(bm[lane * kWordsPerLane + q]);
+    }
+    uint32_t x = run;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    const uint32_t base = x - run, total = __shfl(x, 63, 64);
+#pragma unroll
+    for (int q = 0; q < kWordsPerLane; ++q) pre[lane * kWordsPerLane + q] = base + c[q];
+    wave_lds_sync();
+    for (int64_t t = b + lane; t < e; t += 64) {
+      const uint64_t j = pk[t] & mask;
+      const uint64_t r = j - lo;
+      if (r < (uint64_t)kWinBits) {
+        const uint32_t wd = (uint32_t)(r >> 5);
+        const uint32_t rank = pre[wd] + __popc(bm[wd] & ((1u << (r & 31)) - 1u));
+        emit(b + below + rank, t, (uint32_t)j);
+      }
+    }
+    below += total;
+    wave_lds_sync();
+  }
+}
+
+int64_t row_sort_words(int64_t nR) { return 2 * (nR + 1) + scan_scratch_words(nR + 1) + 1; }
+
+// keys/vals: the m confirmed pairs (key i << bj | j); pk/pv: m entries of
+// scratch; words: row_sort_words(nR) words of scratch.  Writes the first w
+// pairs in (i, j) order to oi/oj/od.
+hipError_t row_sort_pairs(const unsigned long long* keys, const float* vals, int64_t m, int64_t nR, int bj,
+                          unsigned long long* pk, float* pv, uint32_t* words, int64_t w, uint32_t* oi, uint32_t* oj,
+                          float* od, hipStream_t st, int cu_count) {
+  if (m == 0 || nR == 0) return hipSuccess;
+  uint32_t* cnt = words;
+  uint32_t* off = words + (nR + 1);
+  uint32_t* sums = words + 2 * (nR + 1);
+  const int64_t gw = (nR + 255) / 256 < (int64_t)cu_count * 4 ? (nR + 255) / 256 : (int64_t)cu_count * 4;
+  const int64_t gm = (m + 255) / 256 < (int64_t)cu_count * 8 ? (m + 255) / 256 : (int64_t)cu_count * 8;
+  hipLaunchKernelGGL(fill_words_kernel, dim3((unsigned)gw), dim3(256), 0, st, cnt, nR, 0u);
+  hipLaunchKernelGGL(count_rows_kernel, dim3((unsigned)gm), dim3(256), 0, st, keys, m, bj, cnt);
+  hipError_t e = launch_exclusive_scan(cnt, nR, off, sums, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fill_words_kernel, dim3((unsigned)gw), dim3(256), 0, st, cnt, nR, 0u);
+  hipLaunchKernelGGL(place_rows_kernel, dim3((unsigned)gm), dim3(256), 0, st, keys, vals, m, bj, off, cnt, pk, pv);
+  hipLaunchKernelGGL(order_rows_kernel, dim3((unsigned)((nR + kRowWaves - 1) / kRowWaves)), dim3(64 * kRowWaves), 0,
+                     st, pk, pv, nR, off, m, bj, w, oi, oj, od);
   return hipGetLastError();
 }
 

@@ -208,3 +208,19 @@ def test_rejects_misaligned_workspace():
     with pytest.raises(DLError) as e:
         ops.join_topk(R, R, 5, prec="bf16", workspace=_Misaligned(R.device))
     assert e.value.status == DL_ERR_INVALID
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_long_rows_keep_j_order(orc, prec):
+    """Rows of 0 to ~70,000 pairs: the output ordering ranks short rows in
+    registers and long ones through bitmap windows of 32,768 j values, so a
+    70,000-column S with eps at the 40% order statistic spans several windows
+    per row, and a far-away row yields few or no pairs."""
+    R = synth.gaussian_mixture_unit(5, 8, 3, seed=41)
+    S = synth.gaussian_mixture_unit(70000, 8, 3, seed=41, stream=1)
+    R[4] = -R[0]  # likely far from most of S
+    pairs = synth.sample_pairs(5, 70000, 4000, False, seed=3)
+    eps = eps_quantile(orc, R, S, pairs, 0.4)
+    ref = orc.eps_join(R, S, eps)
+    got = ops.join_eps(dev(R), dev(S), eps, prec)
+    assert_eps_equal(got, ref, 8, "long-rows/" + prec)
