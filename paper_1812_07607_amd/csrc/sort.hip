@@ -104,7 +104,7 @@ hipError_t launch_exclusive_scan(const uint32_t* in, int64_t n, uint32_t* out, u
 // rows of at most 64 pairs rank in registers; longer rows set one bit per
 // pair in an LDS bitmap over a window of j, take a prefix count of the
 // bitmap words, and read each pair's rank from it, window by window, so the
-// work is linear in the row length.  Seven launches where an 8-bit LSD radix
+// work is linear in the row length.  Six launches where an 8-bit LSD radix
 // sort of 34-bit keys takes 25.
 __global__ void fill_words_kernel(uint32_t* p, int64_t n, uint32_t v) {
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
@@ -117,13 +117,15 @@ __global__ void count_rows_kernel(const unsigned long long* __restrict__ keys, i
     atomicAdd(&cnt[keys[t] >> bj], 1u);
 }
 
+// cnt holds each row's pair count on entry and zero on exit: every pair
+// takes one of its row's slots by an atomic decrement.
 __global__ void place_rows_kernel(const unsigned long long* __restrict__ keys, const float* __restrict__ vals,
-                                  int64_t m, int bj, const uint32_t* __restrict__ off, uint32_t* __restrict__ fill,
+                                  int64_t m, int bj, const uint32_t* __restrict__ off, uint32_t* __restrict__ cnt,
                                   unsigned long long* __restrict__ pk, float* __restrict__ pv) {
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x) {
     const unsigned long long k = keys[t];
     const uint64_t i = k >> bj;
-    const uint32_t pos = off[i] + atomicAdd(&fill[i], 1u);
+    const uint32_t pos = off[i] + atomicSub(&cnt[i], 1u) - 1u;
     pk[pos] = k;
     pv[pos] = vals[t];
   }
@@ -238,7 +240,6 @@ hipError_t row_sort_pairs(const unsigned long long* keys, const float* vals, int
   hipLaunchKernelGGL(count_rows_kernel, dim3((unsigned)gm), dim3(256), 0, st, keys, m, bj, cnt);
   hipError_t e = launch_exclusive_scan(cnt, nR, off, sums, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(fill_words_kernel, dim3((unsigned)gw), dim3(256), 0, st, cnt, nR, 0u);
   hipLaunchKernelGGL(place_rows_kernel, dim3((unsigned)gm), dim3(256), 0, st, keys, vals, m, bj, off, cnt, pk, pv);
   hipLaunchKernelGGL(order_rows_kernel, dim3((unsigned)((nR + kRowWaves - 1) / kRowWaves)), dim3(64 * kRowWaves), 0,
                      st, pk, pv, nR, off, m, bj, w, oi, oj, od);
