@@ -101,10 +101,11 @@ hipError_t launch_exclusive_scan(const uint32_t* in, int64_t n, uint32_t* out, u
 // order), then order each segment by j, one wave per row.  A pair's output
 // slot is the number of the row's pairs with a smaller j (the (i, j) pairs
 // are distinct, so the result does not depend on the order of placement):
-// rows of at most 64 pairs rank in registers; longer rows set one bit per
-// pair in an LDS bitmap over a window of j, take a prefix count of the
-// bitmap words, and read each pair's rank from it, window by window, so the
-// work is linear in the row length.  Six launches where an 8-bit LSD radix
+// rows of at most 64 pairs rank in registers, rows of at most 256 against
+// their j values staged in LDS; longer rows set one bit per pair in an LDS
+// bitmap over a window of j, take a prefix count of the bitmap words, and
+// read each pair's rank from it, window by window (windows that hold no
+// pair are skipped), so the work is linear in the row length.  Six launches where an 8-bit LSD radix
 // sort of 34-bit keys takes 25.
 __global__ void fill_words_kernel(uint32_t* p, int64_t n, uint32_t v) {
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
@@ -135,6 +136,7 @@ constexpr int kRowWaves = 4;
 constexpr int kWinWords = 1024;             // bitmap words per wave
 constexpr int kWinBits = 32 * kWinWords;    // j values per window
 constexpr int kWordsPerLane = kWinWords / 64;
+constexpr int kQuadRow = 256;               // longest row ranked pair against pair
 
 __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_s_waitcnt(0);
@@ -169,6 +171,28 @@ __global__ __launch_bounds__(64 * kRowWaves) void order_rows_kernel(const unsign
     return;
   }
   uint32_t* bm = bits_lds[wave];
+  if (e - b <= kQuadRow) {
+    // rank against the row's j values staged in LDS (broadcast reads)
+    for (int64_t t = b + lane; t < e; t += 64) bm[t - b] = (uint32_t)(pk[t] & mask);
+    wave_lds_sync();
+    const int len = (int)(e - b);
+    uint32_t jq[kQuadRow / 64];
+    int rk[kQuadRow / 64];
+#pragma unroll
+    for (int q = 0; q < kQuadRow / 64; ++q) {
+      jq[q] = lane + 64 * q < len ? bm[lane + 64 * q] : 0u;
+      rk[q] = 0;
+    }
+    for (int u = 0; u < len; ++u) {
+      const uint32_t v = bm[u];
+#pragma unroll
+      for (int q = 0; q < kQuadRow / 64; ++q) rk[q] += v < jq[q];
+    }
+#pragma unroll
+    for (int q = 0; q < kQuadRow / 64; ++q)
+      if (lane + 64 * q < len) emit(b + rk[q], b + lane + 64 * q, jq[q]);
+    return;
+  }
   uint32_t* pre = pre_lds[wave];
   uint32_t jlo = 0xffffffffu, jhi = 0;
   for (int64_t t = b + lane; t < e; t += 64) {
@@ -183,7 +207,8 @@ __global__ __launch_bounds__(64 * kRowWaves) void order_rows_kernel(const unsign
     jhi = z > jhi ? z : jhi;
   }
   int64_t below = 0;  // pairs of the row in earlier windows
-  for (uint64_t lo = jlo; lo <= jhi; lo += kWinBits) {
+  uint64_t lo = jlo;
+  while (lo <= jhi) {
 #pragma unroll
     for (int q = 0; q < kWordsPerLane; ++q) bm[lane * kWordsPerLane + q] = 0;
     wave_lds_sync();
@@ -208,6 +233,7 @@ __global__ __launch_bounds__(64 * kRowWaves) void order_rows_kernel(const unsign
 #pragma unroll
     for (int q = 0; q < kWordsPerLane; ++q) pre[lane * kWordsPerLane + q] = base + c[q];
     wave_lds_sync();
+    uint32_t nxt = 0xffffffffu;  // smallest j past this window: the next window starts there
     for (int64_t t = b + lane; t < e; t += 64) {
       const uint64_t j = pk[t] & mask;
       const uint64_t r = j - lo;
@@ -215,9 +241,17 @@ __global__ __launch_bounds__(64 * kRowWaves) void order_rows_kernel(const unsign
         const uint32_t wd = (uint32_t)(r >> 5);
         const uint32_t rank = pre[wd] + __popc(bm[wd] & ((1u << (r & 31)) - 1u));
         emit(b + below + rank, t, (uint32_t)j);
+      } else if (j > lo && j < nxt) {
+        nxt = (uint32_t)j;
       }
     }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const uint32_t a = __shfl_xor(nxt, o, 64);
+      nxt = a < nxt ? a : nxt;
+    }
     below += total;
+    lo = nxt;
     wave_lds_sync();
   }
 }

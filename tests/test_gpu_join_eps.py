@@ -224,3 +224,21 @@ def test_long_rows_keep_j_order(orc, prec):
     ref = orc.eps_join(R, S, eps)
     got = ops.join_eps(dev(R), dev(S), eps, prec)
     assert_eps_equal(got, ref, 8, "long-rows/" + prec)
+
+
+def test_rows_with_gaps_between_j_windows(orc):
+    """A row of 3,000 pairs whose j values sit in two runs 190,000 apart
+    (the ordering skips the empty bitmap windows between them), next to
+    rows of a few hundred pairs (ranked pair against pair in LDS)."""
+    R = synth.gaussian_mixture_unit(6, 8, 3, seed=43)
+    S = synth.gaussian_mixture_unit(200000, 8, 3, seed=43, stream=1)
+    rng = np.random.default_rng(44)
+    for lo, hi, src in ((0, 1500, 0), (198500, 200000, 0), (50000, 50250, 1), (120000, 120200, 2)):
+        x = R[src].astype(np.float64) + 1e-3 * rng.standard_normal((hi - lo, 8))
+        S[lo:hi] = (x / np.linalg.norm(x, axis=1, keepdims=True)).astype(np.float32)
+    eps = 0.01
+    ref = orc.eps_join(R, S, eps)
+    counts = np.bincount(ref["i"], minlength=6)
+    assert counts[0] >= 3000 and 64 < counts[1] <= 256 and 64 < counts[2] <= 256
+    got = ops.join_eps(dev(R), dev(S), eps, "bf16")
+    assert_eps_equal(got, ref, 8, "gapped-rows")
