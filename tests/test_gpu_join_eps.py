@@ -54,7 +54,7 @@ def test_histogram_self_join(orc, prec):
 
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("shape", [(1, 1, 1), (1, 300, 3), (257, 300, 3), (300, 257, 129), (513, 700, 64),
-                                   (64, 64, 256), (100, 1000, 200)])
+                                   (64, 64, 256), (100, 1000, 200), (200, 333, 1024)])
 def test_ragged_shapes(orc, prec, shape):
     nR, nS, d = shape
     R = synth.gaussian_mixture_unit(nR, d, 7, seed=nR + d)
