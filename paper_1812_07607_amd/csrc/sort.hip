@@ -112,23 +112,59 @@ __global__ void fill_words_kernel(uint32_t* p, int64_t n, uint32_t v) {
     p[t] = v;
 }
 
-__global__ void count_rows_kernel(const unsigned long long* __restrict__ keys, int64_t m, int bj,
-                                  uint32_t* __restrict__ cnt) {
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x)
-    atomicAdd(&cnt[keys[t] >> bj], 1u);
+// The confirmed pairs arrive in runs of equal i (the candidate pass emits
+// them tile by tile), so the row counters take one atomic per run of equal
+// rows inside a wave rather than one per pair.  For the pair of lane l:
+// head = the lane that starts its run, len = the run's length.
+struct RowRun {
+  uint64_t i;
+  int head, len;
+  bool valid;
+};
+
+__device__ inline RowRun row_run(const unsigned long long* keys, int64_t t, int64_t m, int bj) {
+  const int lane = threadIdx.x & 63;
+  RowRun r;
+  r.valid = t < m;
+  r.i = r.valid ? keys[t] >> bj : ~0ull;
+  const uint64_t prev = __shfl_up(r.i, 1, 64);
+  const bool start = r.valid && (lane == 0 || prev != r.i);
+  const uint64_t heads = __ballot(start);
+  const uint64_t ends = heads | ~__ballot(r.valid);  // a run also ends at the first lane past m
+  r.head = 63 - __clzll(heads & (~0ull >> (63 - lane)));
+  const uint64_t after = ends & ~(~0ull >> (63 - r.head));
+  r.len = (after ? __ffsll((long long)after) - 1 : 64) - r.head;
+  return r;
 }
 
-// cnt holds each row's pair count on entry and zero on exit: every pair
-// takes one of its row's slots by an atomic decrement.
+__global__ void count_rows_kernel(const unsigned long long* __restrict__ keys, int64_t m, int bj,
+                                  uint32_t* __restrict__ cnt) {
+  const int lane = threadIdx.x & 63;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); t0 < m; t0 += stride) {
+    const RowRun r = row_run(keys, t0 + lane, m, bj);
+    if (r.valid && r.head == lane) atomicAdd(&cnt[r.i], (uint32_t)r.len);
+  }
+}
+
+// cnt holds each row's pair count on entry and zero on exit: each run takes
+// len of its row's slots by one atomic decrement.
 __global__ void place_rows_kernel(const unsigned long long* __restrict__ keys, const float* __restrict__ vals,
                                   int64_t m, int bj, const uint32_t* __restrict__ off, uint32_t* __restrict__ cnt,
                                   unsigned long long* __restrict__ pk, float* __restrict__ pv) {
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x) {
-    const unsigned long long k = keys[t];
-    const uint64_t i = k >> bj;
-    const uint32_t pos = off[i] + atomicSub(&cnt[i], 1u) - 1u;
-    pk[pos] = k;
-    pv[pos] = vals[t];
+  const int lane = threadIdx.x & 63;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); t0 < m; t0 += stride) {
+    const int64_t t = t0 + lane;
+    const RowRun r = row_run(keys, t, m, bj);
+    uint32_t first = 0;
+    if (r.valid && r.head == lane) first = off[r.i] + atomicSub(&cnt[r.i], (uint32_t)r.len) - (uint32_t)r.len;
+    first = __shfl(first, r.head, 64);
+    if (r.valid) {
+      const uint32_t pos = first + (uint32_t)(lane - r.head);
+      pk[pos] = keys[t];
+      pv[pos] = vals[t];
+    }
   }
 }
 
