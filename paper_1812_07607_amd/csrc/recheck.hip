@@ -20,11 +20,6 @@
 
 namespace dl {
 
-__device__ inline float wave_sumf(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
 __device__ inline int wave_sumi(int v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -44,12 +39,42 @@ __device__ inline double beta32(double d2, int d, double xsum) {
          ((double)d + 4.0) * 0x1p-52 * xsum * xsum;
 }
 
+// float32 direct-form d2 of rows a and b, summed by one lane in increasing
+// k (any order stays within the bound beta).  vec4: both rows 16-byte
+// aligned.
+__device__ inline float lane_d2(const float* a, const float* b, int d, bool vec4) {
+  float acc = 0.0f;
+  int q = 0;
+  if (vec4) {
+    // unrolled so that several row loads are in flight per lane; the sum is
+    // still one chain in index order
+#pragma unroll 8
+    for (; q + 4 <= d; q += 4) {
+      const float4 x = *reinterpret_cast<const float4*>(a + q);
+      const float4 y = *reinterpret_cast<const float4*>(b + q);
+      float u = x.x - y.x;
+      acc = fmaf(u, u, acc);
+      u = x.y - y.y;
+      acc = fmaf(u, u, acc);
+      u = x.z - y.z;
+      acc = fmaf(u, u, acc);
+      u = x.w - y.w;
+      acc = fmaf(u, u, acc);
+    }
+  }
+  for (; q < d; ++q) {
+    const float u = a[q] - b[q];
+    acc = fmaf(u, u, acc);
+  }
+  return acc;
+}
+
 // ------------------------------------------------------------ eps recheck
 
 
-// A wave takes 64 candidates at a time: it computes their float32 distances
-// one after the other with all lanes (coalesced row reads), lane t keeping
-// candidate t's sum, then classifies the 64 lane-parallel; the confirmed
+// A wave takes 64 candidates at a time: each lane computes its candidate's
+// float32 distance from the two rows (16-byte row loads, several in flight),
+// then the wave classifies the 64 lane-parallel; the confirmed
 // ones of kRecheckChunks such batches are appended with a single atomic (one
 // counter serves the whole grid, so its atomics are kept few).  A candidate
 // whose P~ the matrix-core pass computed exactly (pexR) and whose float32
@@ -64,6 +89,8 @@ __global__ __launch_bounds__(256) void recheck_eps_kernel(RecheckParams p) {
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
   const int64_t n = min((int64_t)*p.ccount, p.ccap);
   const uint64_t lt = __lanemask_lt();
+  // 16-byte row loads when S rows are aligned (R rows are checked per row)
+  const bool vec4 = (reinterpret_cast<uintptr_t>(p.S) & 15) == 0 && (p.lds & 3) == 0 && (p.ldr & 3) == 0;
   constexpr int64_t kSpan = 64 * kRecheckChunks;
   for (int64_t base0 = gw * kSpan; base0 < n; base0 += nw * kSpan) {
     bool in[kRecheckChunks], tie[kRecheckChunks];
@@ -83,19 +110,11 @@ __global__ __launch_bounds__(256) void recheck_eps_kernel(RecheckParams p) {
           mys = (float)(p.nrm2R[mine[c].x] - 2.0 * (double)p.candp[base + lane]);
         }
       }
-      const uint64_t slow = __ballot(lane < cnt && !quick);
-      for (uint64_t rest = slow; rest; rest &= rest - 1) {
-        const int t = __ffsll((unsigned long long)rest) - 1;
-        const uint32_t ci = __shfl(mine[c].x, t, 64), cj = __shfl(mine[c].y, t, 64);
-        const float* a = p.R + (int64_t)ci * p.ldr;
-        const float* b = p.S + (int64_t)cj * p.lds;
-        float s = 0.0f;
-        for (int k = lane; k < p.d; k += 64) {
-          const float u = a[k] - b[k];
-          s = fmaf(u, u, s);
-        }
-        s = wave_sumf(s);
-        if (lane == t) mys = s;
+      // each lane sums its own candidate's row pair: the value depends on
+      // the pair alone, not on which candidates share the wave
+      if (lane < cnt && !quick) {
+        const float* a = p.R + (int64_t)mine[c].x * p.ldr;
+        mys = lane_d2(a, p.S + (int64_t)mine[c].y * p.lds, p.d, vec4 && (reinterpret_cast<uintptr_t>(a) & 15) == 0);
       }
       in[c] = false;
       tie[c] = false;
@@ -193,35 +212,6 @@ __device__ inline uint32_t ord_f(float f) {
   return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
-// float32 direct-form d2 of rows a and b, summed by one lane in increasing
-// k (any order stays within the bound beta).  The query row a is the same
-// for the whole wave.
-__device__ inline float lane_d2(const float* a, const float* b, int d, bool vec4) {
-  float acc = 0.0f;
-  int q = 0;
-  if (vec4) {
-    // unrolled so that several row loads are in flight per lane; the sum is
-    // still one chain in index order
-#pragma unroll 8
-    for (; q + 4 <= d; q += 4) {
-      const float4 x = *reinterpret_cast<const float4*>(a + q);
-      const float4 y = *reinterpret_cast<const float4*>(b + q);
-      float u = x.x - y.x;
-      acc = fmaf(u, u, acc);
-      u = x.y - y.y;
-      acc = fmaf(u, u, acc);
-      u = x.z - y.z;
-      acc = fmaf(u, u, acc);
-      u = x.w - y.w;
-      acc = fmaf(u, u, acc);
-    }
-  }
-  for (; q < d; ++q) {
-    const float u = a[q] - b[q];
-    acc = fmaf(u, u, acc);
-  }
-  return acc;
-}
 
 // One wave per row.  Counting over the row's band entries uses ballots
 // (scalar popcounts, no shuffle chains); distances are computed one entry
