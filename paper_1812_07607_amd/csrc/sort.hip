@@ -105,8 +105,8 @@ hipError_t launch_exclusive_scan(const uint32_t* in, int64_t n, uint32_t* out, u
 // their j values staged in LDS; longer rows set one bit per pair in an LDS
 // bitmap over a window of j, take a prefix count of the bitmap words, and
 // read each pair's rank from it, window by window (windows that hold no
-// pair are skipped), so the work is linear in the row length.  Six launches where an 8-bit LSD radix
-// sort of 34-bit keys takes 25.
+// pair are skipped), so the work is linear in the row length.  Six
+// launches where an 8-bit LSD radix sort of 34-bit keys takes 25.
 __global__ void fill_words_kernel(uint32_t* p, int64_t n, uint32_t v) {
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
     p[t] = v;
