@@ -33,6 +33,8 @@ class Context:
         if st != _lib.DL_OK:
             raise _lib.DLError(st, "dl_create(%d) failed" % device)
         self.h = h
+        self.band_caps = {}  # top-k call shape -> band capacity that sufficed
+        self.eps_caps = {}   # eps-join call shape and eps -> output capacity that sufficed
 
     def check(self, st: int):
         if st != _lib.DL_OK:
@@ -158,6 +160,11 @@ def join_eps(R: torch.Tensor, S: torch.Tensor | None, eps: float, prec: str = "b
     if max_candidates is None:
         max_candidates = max(1 << 20, 4 * (nR + nS))
     cap = capacity if capacity is not None else max(1 << 16, nR + nS)
+    # a call of the same shape and eps starts from the output size that
+    # sufficed last time instead of failing on capacity again
+    key = (nR, nS, d, p, self_join, float(eps))
+    if capacity is None:
+        cap = max(cap, c.eps_caps.get(key, 0))
     if out is not None and capacity is None:
         cap = out[0].numel()
     for _ in range(8):
@@ -184,6 +191,8 @@ def join_eps(R: torch.Tensor, S: torch.Tensor | None, eps: float, prec: str = "b
             continue
         c.check(st)
         m = int(pr.count)
+        if capacity is None:
+            c.eps_caps[key] = cap
         return EpsResult(oi[:m], oj[:m], od[:m], m, int(pr.candidates), int(pr.ties))
     raise RuntimeError("join_eps did not converge on workspace / capacity")
 
@@ -210,6 +219,12 @@ def join_topk(R: torch.Tensor, S: torch.Tensor | None, k: int, exclude_self: boo
     oj = torch.empty((nR, k), dtype=torch.int32, device=R.device)
     od = torch.empty((nR, k), dtype=torch.float32, device=R.device)
     info = _lib.dl_topk_info()
+    # a call of the same shape starts from the band capacity that sufficed
+    # last time instead of growing it again from the default
+    key = (nR, nS, d, p, k, self_join, bool(exclude_self))
+    asked = band_cap
+    if not band_cap:
+        band_cap = c.band_caps.get(key, 0)
     for _ in range(6):
         need = c.L.dl_join_topk_workspace(nR, nS, d, p, int(self_join), k, band_cap)
         buf = ws.get(need)
@@ -220,6 +235,8 @@ def join_topk(R: torch.Tensor, S: torch.Tensor | None, k: int, exclude_self: boo
             band_cap = max(2 * (band_cap or 1024), 1024)
             continue
         c.check(st)
+        if not asked and band_cap:
+            c.band_caps[key] = band_cap
         return TopkResult(oj, od, int(info.band_entries), int(info.ties))
     raise RuntimeError("join_topk did not converge on band capacity")
 
