@@ -65,6 +65,35 @@ def test_d2_within_rounding_of_exact(orc, d):
             assert abs(got - ex) <= Fraction(gamma(d + 2)) * ex
 
 
+def read_d2_order_cases():
+    """Cases of tests/golden/d2_order.txt: name -> (a, b, expected d2)."""
+    cases, cur = {}, None
+    for row in read_golden("d2_order.txt"):
+        if row[0] == "case":
+            cur = row[1]
+            cases[cur] = {}
+        elif row[0] in ("a", "b"):
+            cases[cur][row[0]] = np.array([float.fromhex(v) for v in row[1:]], np.float32)
+        elif row[0] == "d2":
+            cases[cur]["d2"] = float.fromhex(row[1])
+    return {k: (v["a"], v["b"], v["d2"]) for k, v in cases.items()}
+
+
+@pytest.mark.parametrize("case", ["order", "fma"])
+def test_canonical_summation_order_golden(orc, case):
+    """The float64 value follows the canonical sequence bit for bit: summed
+    in increasing k, each operation rounded on its own (hand-worked values;
+    reversing the loop changes the 'order' case, a fused multiply-add the
+    'fma' case)."""
+    a, b, expect = read_d2_order_cases()[case]
+    got = orc.d2(a, b)
+    assert got == expect, "%s: %s vs %s" % (case, got.hex(), expect.hex())
+    # the eps-join and top-k report the same canonical value
+    R, S = a[None, :].copy(), b[None, :].copy()
+    assert orc.eps_join(R, S, math.inf)["d2"][0] == expect
+    assert orc.topk(R, S, 1)[1][0, 0] == expect
+
+
 def test_integer_grid_is_exact(orc):
     # vectors with small dyadic entries: every operation is exact in double
     rng = np.random.default_rng(5)

@@ -25,6 +25,8 @@ MUTANTS = {
     "strict_compare": ("if (dist <= eps) {", "if (dist < eps) {"),
     "strict_count": ("if (sqrt(d2) <= eps) ++c;", "if (sqrt(d2) < eps) ++c;"),
     "tie_larger_j_first": ("return da < db || (da == db && ja < jb);", "return da < db || (da == db && ja > jb);"),
+    "reverse_order": ("for (int32_t k = 0; k < d; ++k) {", "for (int32_t k = d - 1; k >= 0; --k) {"),
+    "fma_contract": ("d2 = d2 + t * t;", "d2 = fma(t, t, d2);"),
     "self_join_keeps_diagonal": ("for (int64_t j = self ? gi + 1 : 0; j < nS; ++j) {",
                                  "for (int64_t j = self ? gi : 0; j < nS; ++j) {"),
 }
@@ -37,6 +39,8 @@ PINS = [
     J.test_pythagorean_closed_form,
     J.test_identity_and_bitwise_symmetry,
     J.test_integer_grid_is_exact,
+    lambda o: J.test_canonical_summation_order_golden(o, "order"),
+    lambda o: J.test_canonical_summation_order_golden(o, "fma"),
     J.test_self_join_is_upper_half_of_symmetric_full_join,
     J.test_eps_extremes_and_monotone,
     T.test_hand_ties,
