@@ -47,10 +47,21 @@ struct Counters {
   int bad_index;
   int overflow;
   int too_many;
-  int pad[13];
+  int invalid;  // an input relation has a non-finite value or a row norm >= 2^62
+  int pad[12];
 };
 static_assert(sizeof(Counters) == 96, "counter block size");
 static_assert(offsetof(Counters, band) == offsetof(Counters, ties) + 8, "ties and band are cleared together");
+
+// Sets *invalid when either relation holds a non-finite value or a row whose
+// norm reaches 2^62 (squared distances would overflow float32).  The
+// candidate and selection kernels read the flag first and do no work when it
+// is set, so bad input costs prep, not a whole join, before the call reports
+// DL_ERR_INVALID.
+__global__ void input_gate_kernel(const RelStats* r, const RelStats* s, int* invalid) {
+  if (threadIdx.x == 0)
+    *invalid = (r->nonfinite || s->nonfinite || !(r->xnorm_max < 0x1p62f) || !(s->xnorm_max < 0x1p62f)) ? 1 : 0;
+}
 
 // ------------------------------------------------------------ workspace
 static Prep carve_prep(Bump& b, int64_t n, int d, dl_prec prec) {
@@ -453,6 +464,8 @@ dl_status eps_core(dl_ctx* c, const EpsJob& J, void* ws, size_t ws_bytes, dl_pai
   int64_t cap = (int64_t)((double)(ws_bytes - fixed) / ((double)per / (1 << 16))) - 1024;
   while (cap > 1 && layout_eps(nullptr, R.n, S.n, R.d, prec, self, cap, sx).bytes > ws_bytes) cap = cap * 63 / 64;
   if (cap < 1) cap = 1;
+  // the canonical ordering keeps per-row offsets in 32 bits
+  if (cap > kMaxPairs) cap = kMaxPairs;
   if (R.n == 0 || S.n == 0) return DL_OK;
 
   EpsLayout L = layout_eps(ws, R.n, S.n, R.d, prec, self, cap, sx);
@@ -466,6 +479,7 @@ dl_status eps_core(dl_ctx* c, const EpsJob& J, void* ws, size_t ws_bytes, dl_pai
     StageTimer t(c, 1, st);
     DL_HIP(c, launch_prep(R.data, R.n, R.d, R.ld, prec, L.pr, L.sr, st, c->cu_count));
     if (!self && !sx) DL_HIP(c, launch_prep(S.data, S.n, S.d, S.ld, prec, L.ps, L.ss, st, c->cu_count));
+    hipLaunchKernelGGL(input_gate_kernel, dim3(1), dim3(64), 0, st, L.sr, L.ss, &L.cnt->invalid);
     DL_HIP(c, launch_threshold(L.pr, R.n, L.ss, R.d, J.T, J.Trow, L.thr, nullptr, L.pex, nullptr, st));
   }
   {
@@ -486,6 +500,7 @@ dl_status eps_core(dl_ctx* c, const EpsJob& J, void* ws, size_t ws_bytes, dl_pai
     p.cand = L.cand;
     p.candp = prec == DL_FP8 ? nullptr : L.candp;  // E4M3 stages no P~ (LDS budget)
     p.ccap = cap;
+    p.gate = &L.cnt->invalid;
     DL_HIP(c, launch_cand_eps(prec, p, st, c->cu_count));
   }
   const int bj = bits_for(S.n);  // the recheck's keys are i << bj | j
@@ -512,6 +527,9 @@ dl_status eps_core(dl_ctx* c, const EpsJob& J, void* ws, size_t ws_bytes, dl_pai
   if (dl_status bad = check_inputs(c)) return bad;
   out->candidates = (int64_t)hc.cand;
   out->ties = (int64_t)hc.ties;
+  if ((int64_t)hc.cand > cap && cap == kMaxPairs)
+    return fail(c, DL_ERR_CAPACITY, "%llu candidates exceed the %lld one call can order; split R", hc.cand,
+                (long long)kMaxPairs);
   if ((int64_t)hc.cand > cap) {
     c->required_ws =
         layout_eps(nullptr, R.n, S.n, R.d, prec, self, (int64_t)hc.cand + (int64_t)hc.cand / 8 + 1024, sx).bytes;
@@ -585,6 +603,7 @@ dl_status topk_core(dl_ctx* c, const TopkJob& J, void* ws, size_t ws_bytes, uint
     StageTimer t(c, 1, st);
     DL_HIP(c, launch_prep(R.data, R.n, R.d, R.ld, prec, L.pr, L.sr, st, c->cu_count));
     if (!self && !sx) DL_HIP(c, launch_prep(S.data, S.n, S.d, S.ld, prec, L.ps, L.ss, st, c->cu_count));
+    hipLaunchKernelGGL(input_gate_kernel, dim3(1), dim3(64), 0, st, L.sr, L.ss, &L.cnt->invalid);
     DL_HIP(c, launch_threshold(L.pr, R.n, L.ss, R.d, 0.0, nullptr, nullptr, L.marg, nullptr, L.gkey, st));
     if (pilot_dist) DL_HIP(c, launch_band_seed(L.pr, R.n, pilot_dist, k, L.marg, L.gkey, st));
   }
@@ -614,6 +633,7 @@ dl_status topk_core(dl_ctx* c, const TopkJob& J, void* ws, size_t ws_bytes, uint
     p.band = L.band;
     p.bcount = L.bcount;
     p.overflow = &L.cnt->overflow;
+    p.gate = &L.cnt->invalid;
     DL_HIP(c, launch_cand_band(prec, p, st));
   }
   SelectParams q{};
@@ -629,6 +649,7 @@ dl_status topk_core(dl_ctx* c, const TopkJob& J, void* ws, size_t ws_bytes, uint
     q.sS = L.ss;
     q.out_j = out_j; q.out_dist = out_dist;
     q.nband = &L.cnt->band; q.nties = &L.cnt->ties; q.too_many = &L.cnt->too_many;
+    q.gate = &L.cnt->invalid;
     DL_HIP(c, launch_topk_select(q, small_sel, st));
   }
   DL_HIP(c, readback(c, L.cnt, L.sr, L.ss, st));

@@ -16,6 +16,9 @@ constexpr int kMaxDim = 4096;
 constexpr int kTile = 256;          // rows of R and of S per contraction tile
 constexpr int kChunkBytes = 128;    // bytes of one row per K-chunk in LDS
 constexpr int kLsbNone = 100000;    // "no nonzero element" lsb sentinel
+// Most candidate pairs one eps-join call holds: the canonical ordering keeps
+// per-row offsets and counts in 32 bits.
+constexpr int64_t kMaxPairs = (1ll << 32) - (1ll << 24);
 
 // ------------------------------------------------------- per-row statistics
 // Derived data of one relation, built by the prep kernel in the workspace.

@@ -844,6 +844,8 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
   constexpr bool kStageP = kEps && !kFp8;
   __shared__ uint32_t lds_eqp[kStageP ? kThreads / 64 : 1][kStageP ? kQueue : 1];
 
+  // invalid input (non-finite values, norms out of range): no work at all
+  if (p.gate && __builtin_amdgcn_readfirstlane(*p.gate)) return;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wm = wave >> 2, wn = wave & 3;
   const int nsteps = (int)(p.qld / Q::kCB);

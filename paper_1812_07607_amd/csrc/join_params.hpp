@@ -49,6 +49,7 @@ struct CandParams {
   uint2* band;         // (P~ bits, j): [(row * P + split) * cap + slot]
   int* bcount;         // [row * P + split]
   int* overflow;       // set when a band exceeds cap - 256
+  const int* gate;     // nonzero: invalid input, the kernel does nothing
 };
 
 // eps-join recheck (recheck.hip).
@@ -80,6 +81,7 @@ struct SelectParams {
   const RelStats* sS;  // S maxima: xnorm_max, mlsb_min
   uint32_t* out_j; float* out_dist;
   unsigned long long* nband; unsigned long long* nties; int* too_many;
+  const int* gate;  // nonzero: invalid input, every row is written as padding
 };
 
 }  // namespace dl

@@ -230,6 +230,15 @@ __global__ __launch_bounds__(64 * kSelWaves, kSelMax == kSelSmall ? 6 : 4) void 
   if (i >= p.nR) return;
   const float* a = p.R + i * p.ldr;
   const int k = p.k;
+  if (p.gate && __builtin_amdgcn_readfirstlane(*p.gate)) {
+    // invalid input: the candidate pass did no work and the band counts are
+    // not set; the call reports the error, the rows hold padding
+    for (int t = lane; t < k; t += 64) {
+      p.out_j[i * k + t] = 0xffffffffu;
+      p.out_dist[i * k + t] = INFINITY;
+    }
+    return;
+  }
   const uint64_t lt = __lanemask_lt();
   int total = 0;
   for (int s = 0; s < p.P; ++s) total += p.bcount[i * p.P + s];
