@@ -79,7 +79,9 @@ typedef struct dl_mat {
 /* ---------------------------------------------------------------- context */
 
 /* Create a context on HIP device `device`.  Allocates a few bytes of pinned
- * host memory for counts; no device memory. */
+ * host memory for counts.  The first context on a device also looks up that
+ * device's fixed scratch of dl_join_eps_noalloc (device memory the library's
+ * code object holds from when it is loaded on the device). */
 dl_status dl_create(int device, dl_ctx** out);
 void dl_destroy(dl_ctx* ctx);
 /* Message for the last error on this context ("" if none).  Valid until the
@@ -165,6 +167,28 @@ dl_status dl_join_eps(dl_ctx* ctx, dl_mat R, dl_mat S, int self_join,
 
 /* Bytes of workspace the last DL_ERR_WORKSPACE failure on ctx needed. */
 size_t dl_required_workspace(const dl_ctx* ctx);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * eps-join as dl_join_eps, with the library's fixed scratch as its
+ * workspace.  The call itself allocates nothing (no hipMalloc, hipFree or
+ * event creation; no per-stage timing is recorded).
+ *   The scratch is DL_NOALLOC_SCRATCH_BYTES of device memory per GPU, held
+ *   from the first dl_create on that GPU until the process ends.  Every call
+ *   on a GPU uses that GPU's one copy, so calls that overlap on one GPU (two
+ *   threads, two streams, or a stream still running an earlier call) race
+ *   and their results are undefined: serialise them.  The scratch keeps the
+ *   last call's contents; the call clears what it needs cleared itself.
+ * Same arguments, outputs and errors as dl_join_eps, except that a join
+ * whose operand copies alone exceed the scratch, or whose candidates do not
+ * fit beside them, returns DL_ERR_WORKSPACE at once (dl_last_error says how
+ * much it needs; dl_required_workspace() gives 0: use dl_join_eps with a
+ * workspace instead), and DL_ERR_DEVICE if the scratch could not be set up
+ * on the context's device.  Synchronises `stream`. */
+#define DL_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+dl_status dl_join_eps_noalloc(dl_ctx* ctx, dl_mat R, dl_mat S, int self_join,
+                              double eps, dl_prec prec, dl_pairs* out,
+                              void* stream);
 
 /* ---------------------------------------------------------------- top-k */
 

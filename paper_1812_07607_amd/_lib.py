@@ -58,6 +58,7 @@ class dl_server_info(ctypes.Structure):
 
 
 DL_MODE_EPS, DL_MODE_TOPK = 0, 1
+NOALLOC_SCRATCH_BYTES = 64 << 20  # DL_NOALLOC_SCRATCH_BYTES
 
 # name -> (restype, argtypes); every symbol include/dlmi.h declares
 P, i32, i64, f64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
@@ -74,6 +75,8 @@ SIGNATURES = {
     "dl_join_eps": (ctypes.c_int, [P, dl_mat, dl_mat, ctypes.c_int, f64, ctypes.c_int, P, sz,
                                    ctypes.POINTER(dl_pairs), P]),
     "dl_required_workspace": (sz, [P]),
+    "dl_join_eps_noalloc": (ctypes.c_int, [P, dl_mat, dl_mat, ctypes.c_int, f64, ctypes.c_int,
+                                           ctypes.POINTER(dl_pairs), P]),
     "dl_join_topk_workspace": (sz, [i64, i64, i32, ctypes.c_int, ctypes.c_int, i32, i32]),
     "dl_join_topk": (ctypes.c_int, [P, dl_mat, dl_mat, ctypes.c_int, i32, ctypes.c_int, ctypes.c_int, i32, P, sz,
                                     P, P, ctypes.POINTER(dl_topk_info), P]),

@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "core.hpp"
@@ -279,6 +280,39 @@ dl_status check_inputs(dl_ctx* c) {
 }
 }  // namespace
 
+// ------------------------------------------------------------ fixed scratch
+// The workspace of dl_join_eps_noalloc: a file-scope device array, so that
+// the call needs no allocation.  Each device holds its own copy at its own
+// address, looked up once per device (with that device current) when the
+// first context on it is created.  In host code `scratch` names a host-side
+// stand-in, never the device memory: only the looked-up address is used.
+static __device__ __align__(256) uint8_t scratch[DL_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+
+// The device's scratch address (call with `device` current).  A failed
+// lookup is kept and reported by the no-allocation call, not by dl_create.
+void* scratch_of(int device, hipError_t* err) {
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (device < 0 || device >= kMaxDevices) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  if (!g_scratch_ptr[device] && g_scratch_err[device] == hipSuccess) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e == hipSuccess && p) g_scratch_ptr[device] = p;
+    else g_scratch_err[device] = e == hipSuccess ? hipErrorInvalidSymbol : e;
+  }
+  *err = g_scratch_err[device];
+  return g_scratch_ptr[device];
+}
+}  // namespace
+
 extern "C" {
 
 const char* dl_version(void) { return "dlmi 0.1 (gfx950)"; }
@@ -300,6 +334,7 @@ dl_status dl_create(int device, dl_ctx** out) {
   }
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->cu_count = prop.multiProcessorCount;
+  c->scratch = scratch_of(device, &c->scratch_err);
   *out = c;
   return DL_OK;
 }
@@ -715,6 +750,39 @@ dl_status dl_join_eps(dl_ctx* c, dl_mat R, dl_mat S, int self_join, double eps, 
   DL_HIP(c, hipSetDevice(c->device));
   EpsJob J{R, S, self_join != 0, prec, nullptr, nullptr, threshold_from_eps(eps), nullptr};
   return eps_core(c, J, ws, ws_bytes, out, static_cast<hipStream_t>(stream));
+}
+
+dl_status dl_join_eps_noalloc(dl_ctx* c, dl_mat R, dl_mat S, int self_join, double eps, dl_prec prec,
+                              dl_pairs* out, void* stream) {
+  if (!c) return DL_ERR_INVALID;
+  c->err.clear();
+  c->required_ws = 0;
+  if (self_join) S = R;
+  dl_status s;
+  if ((s = check_mat(c, R, "R")) != DL_OK || (s = check_mat(c, S, "S")) != DL_OK) return s;
+  if (R.d != S.d) return fail(c, DL_ERR_INVALID, "R.d %d != S.d %d", R.d, S.d);
+  if (std::isnan(eps) || eps < 0) return fail(c, DL_ERR_INVALID, "eps must be >= 0 (got %g)", eps);
+  if (!prec_ok(prec)) return fail(c, DL_ERR_INVALID, "unknown precision %d", (int)prec);
+  if (!out || out->capacity < 0) return fail(c, DL_ERR_INVALID, "bad output struct");
+  if (out->capacity > 0 && (!out->i || !out->j || !out->dist)) return fail(c, DL_ERR_INVALID, "null output array");
+  if (!c->scratch)
+    return fail(c, DL_ERR_DEVICE, "fixed scratch unavailable on device %d: %s", c->device,
+                hipGetErrorString(c->scratch_err));
+  const size_t need = eps_workspace(R.n, S.n, R.d, prec, self_join != 0, false, 1);
+  if (need > (size_t)DL_NOALLOC_SCRATCH_BYTES)
+    return fail(c, DL_ERR_WORKSPACE,
+                "a %lld x %lld d=%d join needs at least %zu bytes of scratch; the fixed scratch holds %zu "
+                "(use dl_join_eps with a workspace)",
+                (long long)R.n, (long long)S.n, R.d, need, (size_t)DL_NOALLOC_SCRATCH_BYTES);
+  DL_HIP(c, hipSetDevice(c->device));
+  EpsJob J{R, S, self_join != 0, prec, nullptr, nullptr, threshold_from_eps(eps), nullptr};
+  // no per-stage events either: the call creates nothing
+  const bool timing = c->timing;
+  c->timing = false;
+  const dl_status r = eps_core(c, J, c->scratch, (size_t)DL_NOALLOC_SCRATCH_BYTES, out, static_cast<hipStream_t>(stream));
+  c->timing = timing;
+  if (r == DL_ERR_WORKSPACE) c->required_ws = 0;  // a larger workspace is not an option here
+  return r;
 }
 
 size_t dl_join_topk_workspace(int64_t nR, int64_t nS, int32_t d, dl_prec prec, int self_join, int32_t k,

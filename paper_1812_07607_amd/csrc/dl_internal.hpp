@@ -217,4 +217,6 @@ struct dl_ctx {
   double stage_ms[DL_NUM_STAGES] = {0};
   int64_t stage_calls[DL_NUM_STAGES] = {0};
   int cu_count = 256;
+  void* scratch = nullptr;  // this device's fixed scratch (dl_join_eps_noalloc)
+  hipError_t scratch_err = hipSuccess;
 };
