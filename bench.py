@@ -1,11 +1,23 @@
-"""Benchmark: featurise + exact eps self-join of 100,000 RGB patches on one GPU.
+"""Benchmark: exact eps-join of 1,000,000 x 1,000,000 unit-norm vectors
+(d = 128) with bf16 candidates on one GPU.
 
 One step is the whole hot path over one batch of synthetic input already
-resident in HBM: colour histograms of 100,000 uint8 32x32 patches (8x8x8
-bins), operand prep, the matrix-core candidate pass with the fused eps
-filter, the float32 / float64 recheck and the canonical (i, j) sort, for the
-self-join i < j at the 0.01% distance quantile.  `value` is the number of
-distance pairs in the join's domain (n(n-1)/2) per second of step time.
+resident in HBM: operand prep of R and S (norms, bf16 copies, residual
+bounds), the matrix-core candidate pass with the fused margin-widened eps
+filter, the float32 / float64 recheck of every candidate and the canonical
+(i, j) ordering of the emitted pairs.  R and S are drawn from a 1,000-centre
+Gaussian mixture on the sphere (sigma 0.05); eps is the lower median of the
+exact 10th-neighbour distance of 256 seeded rows of R.  `value` is the
+number of distance pairs in the join's domain (|R| |S|) per second of step
+time.
+
+Beside the headline the line carries: the plain fp32 join on the same input
+(its (i, j) arrays compared with the timed result), the top-10 join of the
+same relations, the featurise + self-join of 100,000 RGB patches (fp32
+candidates as that workload states, and the exact fp16 variant), the E4M3
+and bf16 top-32 of 50,000 queries against a 4,000,000 x 256 store, the
+serving loop, and the float64 oracle on seeded rows (its time, and the
+element-wise agreement of those rows with the timed result).
 
 Prints one JSON line.  Runs on one GPU only.
 """
@@ -30,16 +42,20 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--prec", default="fp16", choices=sorted(PEAK_TFLOPS))
-    ap.add_argument("--n", type=int, default=100000, help="patches (default: the full workload)")
+    ap.add_argument("--prec", default="bf16", choices=sorted(PEAK_TFLOPS), help="candidate format of the headline")
+    ap.add_argument("--n", type=int, default=1000000, help="rows of R and of S (default: the full workload)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="headline only: no fp32 comparison, top-10, histogram, store or serving legs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for the CPU baseline")
-    ap.add_argument("--no-fp32-compare", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-store", type=int, default=8000000, help="rows of the serving store")
-    ap.add_argument("--serve-seconds", type=float, default=6.0, help="open-loop seconds per offered rate")
+    ap.add_argument("--serve-seconds", type=float, default=20.0, help="open-loop seconds per offered rate")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="copy this many MiB device-to-device first (scale for FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--histogram-headline", action="store_true",
+                    help="instead of the headline step, time featurise + self-join of 100,000 patches (--prec, "
+                         "default fp16 there) for profiling")
     ap.add_argument("--secondary", action="store_true",
                     help="instead of the headline step, time the unit-mixture eps and top-k joins (one JSON line)")
     ap.add_argument("--full-configs", action="store_true",
@@ -50,7 +66,8 @@ def parse():
 
 KERNEL_SOURCES = ["paper_1812_07607_amd/csrc/join_mfma.hip", "paper_1812_07607_amd/csrc/join_params.hpp",
                   "paper_1812_07607_amd/csrc/dl_internal.hpp"]
-TRAFFIC_SUMMARY = "profiles/cand_kernel_fp16_selfjoin_100k_traffic.txt"
+TRAFFIC_SUMMARY = {"bf16": "profiles/cand_kernel_bf16_eps_1m_d128_traffic.txt",
+                   "fp16": "profiles/cand_kernel_fp16_selfjoin_100k_traffic.txt"}
 
 
 def progress(msg):
@@ -67,19 +84,19 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(prec):
+def measured_traffic(prec, workload):
     """HBM bytes per launch of the contraction kernel from the committed
-    rocprofv3 counter summary, if it was taken on the current kernel source
-    (else None)."""
-    path = os.path.join(ROOT, TRAFFIC_SUMMARY)
-    if prec != "fp16" or not os.path.exists(path):
+    rocprofv3 counter summary of this workload, if it was taken on the
+    current kernel source (else None)."""
+    path = os.path.join(ROOT, TRAFFIC_SUMMARY.get(prec, ""))
+    if not os.path.isfile(path):
         return None
     vals = {}
     for line in open(path):
         if ":" in line:
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256_16") != kernel_hash():
+    if vals.get("kernel_source_sha256_16") != kernel_hash() or vals.get("workload") != workload:
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -87,34 +104,84 @@ def measured_traffic(prec):
         return None
 
 
-def cpu_baseline(H, eps, n, target_s):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def timed_calls(ctx, fn, reps):
+    """Stage times (ms per call, HIP events) of `reps` calls after one
+    untimed call; returns (last result, per-stage dict)."""
+    import torch
+    r = fn()
+    torch.cuda.synchronize()
+    ctx.timing(reset=True)
+    ctx.set_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        r = fn()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    ctx.set_timing(False)
+    st = ctx.timing(reset=True)
+    rec = {k: round(v[0] / reps, 3) for k, v in st.items() if v[1]}
+    rec["ms_per_call"] = round(wall * 1e3, 3)
+    rec["contractions_per_call"] = round(st["contract"][1] / reps, 2)
+    return r, rec
+
+
+def rows_of(res, rows):
+    """The pairs of an eps result whose i is one of `rows` (host int64 arrays
+    i, j and float32 dist, in the result's (i, j) order)."""
+    import numpy as np
+    import torch
+    gi = res.i.long() & 0xffffffff
+    keep = torch.isin(gi, torch.from_numpy(np.asarray(rows, np.int64)).to(gi.device))
+    return (gi[keep].cpu().numpy(), (res.j.long()[keep] & 0xffffffff).cpu().numpy(),
+            res.dist[keep].cpu().numpy())
+
+
+def cpu_baseline(R, S, eps, res, target_s):
     """The oracle (plain C, float64) on a bounded sample of rows of the same
-    self-join, on all host cores."""
+    eps-join, on all host cores: its rate, and the element-wise agreement of
+    those rows of the timed GPU result with it."""
     import numpy as np
 
     import oracle
     from paper_1812_07607_amd import synth
     threads = oracle.max_threads()
-    t0 = time.perf_counter()
-    feat = oracle.hist_rgb8(H["patches"][:2000], 8, nthreads=threads)
-    t_feat = (time.perf_counter() - t0) / 2000
-    del feat
-    Hn = H["hist"]
+    n = R.shape[0]
     # grow the sample until one run takes most of target_s (small samples
     # are dominated by thread start-up and load imbalance)
     m = 16
     while True:
         rows = synth.sample_rows(n, m, seed=78)
-        pairs = int(sum(n - 1 - r for r in rows))
         t0 = time.perf_counter()
-        oracle.eps_join(np.ascontiguousarray(Hn[rows]), Hn, eps, self_join=True, row_ids=rows, nthreads=threads)
+        ref = oracle.eps_join(np.ascontiguousarray(R[rows]), S, eps, row_ids=rows, nthreads=threads,
+                              cap=64 * m + 4096)
         dt = time.perf_counter() - t0
+        if ref["count"] > 64 * m + 4096:
+            ref = oracle.eps_join(np.ascontiguousarray(R[rows]), S, eps, row_ids=rows, nthreads=threads)
         if dt >= 0.6 * target_s or m >= n:
             break
         m = min(n, int(m * min(8.0, max(1.5, 0.9 * target_s / max(dt, 1e-3)))))
-    return {"value": pairs / dt / 1e9, "unit": "G distance-pairs/s", "cores": threads, "kind": "oracle",
-            "sample": "eps self-join of %d seeded rows x all later rows (%d pairs, %.1f s); featurise %.2f us/patch "
-                      "(not in value)" % (m, pairs, dt, t_feat * 1e6)}
+    pairs = m * S.shape[0]
+    gi, gj, gd = rows_of(res, rows)
+    same = bool(len(gi) == ref["count"] and np.array_equal(gi, ref["i"]) and np.array_equal(gj, ref["j"]))
+    err = float(np.max(np.abs(gd.astype(np.float64) - ref["dist"]) / np.maximum(ref["dist"], 1e-30))) \
+        if same and len(gi) else 0.0
+    return {"value": pairs / dt / 1e9, "unit": "G distance-pairs/s", "cores": threads, "cpu": cpu_model(),
+            "kind": "oracle",
+            "sample": "eps-join of %d seeded rows of R x all %d rows of S (%d pairs, %.1f s); the rate is "
+                      "extrapolated from this sample" % (m, S.shape[0], pairs, dt),
+            "agreement": {"rows": m, "oracle_pairs": int(ref["count"]), "gpu_pairs": int(len(gi)),
+                          "pair_set_identical": same, "max_rel_dist_err": err}}
 
 
 def serving(args):
@@ -335,6 +402,115 @@ def full_configs():
                       "timing": "ms per stage per call, mean of 2 calls (fp32: 1)"}))
 
 
+def eps_of_rows(R, S, rows, k=10):
+    """eps of the precision-form workload: the lower median, over seeded rows
+    of R, of each row's exact k-th neighbour distance in S (the GPU's exact
+    top-k)."""
+    import numpy as np
+
+    from paper_1812_07607_amd import ops, synth
+    import torch
+    idx = torch.from_numpy(np.asarray(rows, np.int64)).to(R.device)
+    t = ops.join_topk(R.index_select(0, idx).contiguous(), S, k, prec="bf16")
+    return float(synth.order_statistic(t.dist[:, k - 1].double().cpu().numpy(), 0.5))
+
+
+def histogram_leg(args, prec_list, steps):
+    """Featurise 100,000 RGB 32x32 patches + the exact eps self-join at the
+    0.01% distance quantile, per candidate format: ms per step (featurise
+    included), pairs/s, and the pair arrays of every format compared with the
+    first one's."""
+    import numpy as np
+    import torch
+
+    from paper_1812_07607_amd import ops, synth
+    ctx = ops.context()
+    n = 100000
+    cfg = synth.config2(1.0)
+    patches = torch.from_numpy(cfg["patches"]).cuda()
+    hist = torch.empty((n, 512), dtype=torch.float32, device="cuda")
+    ops.featurize_rgb8(patches, 8, out=hist)
+    pi, pj = cfg["pairs"]
+    d2 = ops.pair_d2(hist, hist, torch.from_numpy(pi), torch.from_numpy(pj)).cpu().numpy()
+    eps = float(np.sqrt(synth.order_statistic(d2, cfg["q"])))
+    pairs = n * (n - 1) // 2
+    out = {"workload": "featurise 100000 RGB 32x32 patches (8x8x8 histograms, 16 base colours + N(0,20^2)) + "
+                       "exact eps self-join i<j at the 0.01%% distance quantile (eps %.6g)" % eps}
+    first = None
+    for prec in prec_list:
+        ws = ops.Workspace(hist.device)
+
+        def step():
+            ops.featurize_rgb8(patches, 8, out=hist)
+            return ops.join_eps(hist, None, eps, prec, workspace=ws)
+
+        r, rec = timed_calls(ctx, step, steps)
+        rec["value"] = pairs / (rec["ms_per_call"] * 1e-3) / 1e9
+        rec["contract_tflops"] = pairs * 2.0 * 512 / (rec["contract"] * 1e-3) / 1e12
+        rec["contract_frac"] = rec["contract_tflops"] / PEAK_TFLOPS[prec]
+        rec.update(result_pairs=r.count, candidates=r.candidates, fp64_ties=r.ties)
+        if first is None:
+            first = r
+        else:
+            rec["same_pairs_as_" + prec_list[0]] = bool(
+                r.count == first.count and torch.equal(r.i, first.i) and torch.equal(r.j, first.j))
+        out[prec] = rec
+        progress("histogram leg %s: %s" % (prec, json.dumps(rec)))
+    return out, {"patches": cfg["patches"], "hist": hist, "eps": eps}
+
+
+def store_leg():
+    """Top-32 of 50,000 queries against a 4,000,000 x 256 store (4,096-centre
+    mixture): E4M3 candidates (with their bf16 pilot) and bf16, ms per call
+    (prep of both sides included), the two results compared."""
+    import torch
+
+    from paper_1812_07607_amd import ops, synth
+    ctx = ops.context()
+    c4 = synth.config4()
+    S = torch.from_numpy(c4["S"]).cuda()
+    Q = torch.from_numpy(c4["Q"]).cuda()
+    del c4
+    pairs = Q.shape[0] * S.shape[0]
+    out = {"workload": "top-32 of 50000 queries x 4000000 x 256 store (4096-centre mixture)"}
+    res = {}
+    for prec in ("fp8", "bf16"):
+        try:
+            r, rec = timed_calls(ctx, lambda: ops.join_topk(Q, S, 32, prec=prec), 2)
+        except Exception as e:  # reported, not fatal
+            out[prec] = {"error": str(e)[:200]}
+            continue
+        rec["value"] = pairs / (rec["ms_per_call"] * 1e-3) / 1e9
+        rec.update(band_entries=r.band_entries, ties=r.ties)
+        res[prec] = r
+        out[prec] = rec
+        progress("store leg %s: %s" % (prec, json.dumps(rec)))
+    if len(res) == 2:
+        out["same_neighbours"] = bool(torch.equal(res["fp8"].j, res["bf16"].j))
+        if "ms_per_call" in out.get("fp8", {}):
+            out["fp8_speedup_end_to_end"] = out["bf16"]["ms_per_call"] / out["fp8"]["ms_per_call"]
+    return out
+
+
+def histogram_headline(args):
+    """The featurise + self-join step alone (profiling runs of that kernel)."""
+    import numpy as np
+    prec = args.prec if args.prec != "bf16" else "fp16"
+    leg, _ = histogram_leg(args, [prec], args.steps)
+    rec = leg[prec]
+    pairs = 100000 * 99999 // 2
+    res = {"metric": METRIC, "value": rec["value"], "unit": "G distance-pairs/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": 1, "ms_per_step": rec["ms_per_call"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": prec, "data": "synthetic",
+           "config": {"workload": leg["workload"], "pairs": pairs},
+           "roofline": {"kernel": "cand_kernel<%s, eps>" % prec, "bound": "mfma", "achieved": rec["contract_tflops"],
+                        "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s", "frac": rec["contract_frac"],
+                        "traffic": measured_traffic(prec, "featurise + eps self-join, 100000 patches"),
+                        "flops_per_launch": pairs * 2.0 * 512, "avg_launch_ms": rec["contract"]}}
+    del np
+    print(json.dumps(res))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -360,24 +536,27 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.histogram_headline:
+        histogram_headline(args)
+        return
     n = args.n
-    cfg = synth.config2(n / 100000.0)
-    patches = torch.from_numpy(cfg["patches"]).cuda()
-    hist = torch.empty((n, 512), dtype=torch.float32, device="cuda")
-    ops.featurize_rgb8(patches, 8, out=hist)
-    pi, pj = cfg["pairs"]
-    d2 = ops.pair_d2(hist, hist, torch.from_numpy(pi), torch.from_numpy(pj)).cpu().numpy()
-    eps = float(np.sqrt(synth.order_statistic(d2, cfg["q"])))
+    d = 128
+    c3 = synth.config3(n / 1000000.0)
+    R_h, S_h = c3["R"], c3["S"]
+    del c3
+    R = torch.from_numpy(R_h).cuda()
+    S = torch.from_numpy(S_h).cuda()
+    n = R.shape[0]
+    eps = eps_of_rows(R, S, synth.sample_rows(n, 256, seed=3031))
     ctx = ops.context()
-    ws = ops.Workspace(hist.device)
+    ws = ops.Workspace(R.device)
 
     def step(prec, out=None):
-        ops.featurize_rgb8(patches, 8, out=hist)
-        return ops.join_eps(hist, None, eps, prec, workspace=ws, out=out)
+        return ops.join_eps(R, S, eps, prec, workspace=ws, out=out, max_candidates=1 << 26)
 
     progress("setup done (eps %.6g); warm-up and %d timed steps" % (eps, args.steps))
     r = step(args.prec)
-    cap = max(r.count * 2, 1 << 16)
+    cap = max(r.count + r.count // 4, 1 << 16)
     out = (torch.empty(cap, dtype=torch.int32, device="cuda"), torch.empty(cap, dtype=torch.int32, device="cuda"),
            torch.empty(cap, dtype=torch.float32, device="cuda"))
     for _ in range(args.warmup):
@@ -397,53 +576,74 @@ def main():
     elapsed = time.perf_counter() - t_all
     ctx.set_timing(False)
     stages = ctx.timing(reset=True)
-    pairs = n * (n - 1) // 2
+    pairs = n * n
     ms_step = elapsed / args.steps * 1e3
     value = pairs / (elapsed / args.steps) / 1e9
+    progress("timed steps: %.3f ms/step" % ms_step)
 
     # dominant kernel: the matrix-core contraction (stage "contract")
     c_ms, c_calls = stages["contract"]
     c_avg = c_ms / max(c_calls, 1)
-    flops = pairs * 2.0 * 512
+    flops = pairs * 2.0 * d
     achieved = flops / (c_avg * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.prec]
+    workload = "eps-join %d x %d, d=128, unit-norm 1000-centre mixture" % (n, n)
     roof = {"kernel": "cand_kernel<%s, eps>" % args.prec, "bound": "mfma", "achieved": achieved, "peak": peak,
-            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": measured_traffic(args.prec),
+            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": measured_traffic(args.prec, workload),
             "flops_per_launch": flops, "avg_launch_ms": c_avg}
     res = {
         "metric": METRIC, "value": value, "unit": "G distance-pairs/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
-        "config": {"workload": "featurise %d RGB 32x32 patches (8x8x8 histograms, 16 base colours + N(0,20^2)) + "
-                               "exact eps self-join i<j at the 0.01%% distance quantile" % n,
-                   "patches": n, "dim": 512, "pairs": pairs, "eps": eps, "result_pairs": r.count,
+        "config": {"workload": "exact eps-join of R = S-size %d x 128 unit-norm float32 vectors (1,000-centre "
+                               "Gaussian mixture, sigma 0.05; R and S independent draws) at eps = lower median "
+                               "exact 10th-neighbour distance of 256 seeded rows; %s candidates, float32/float64 "
+                               "recheck, (i, j)-ordered output" % (n, args.prec),
+                   "rows_R": n, "rows_S": n, "dim": d, "pairs": pairs, "eps": eps, "result_pairs": r.count,
                    "candidates": r.candidates, "fp64_ties": r.ties},
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3)},
         "stages_ms_per_step": {k: v[0] / max(args.steps, 1) for k, v in stages.items() if v[1]},
         "roofline": roof,
     }
-    progress("timed steps: %.3f ms/step" % ms_step)
-    if not args.no_fp32_compare and args.prec != "fp32":
-        # the plain fp32 GPU join on the same input, for comparison
-        step("fp32", out)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        k32 = max(1, min(3, args.steps))
-        for _ in range(k32):
-            r32 = step("fp32", out)
-        torch.cuda.synchronize()
-        t32 = (time.perf_counter() - t0) / k32
-        res["fp32_join"] = {"value": pairs / t32 / 1e9, "ms_per_step": t32 * 1e3, "candidates": r32.candidates,
-                            "same_pairs": bool(r32.count == r.count)}
-    if not args.no_serving:
-        try:
-            res["serving"] = serving(args)
-        except Exception as e:  # reported, not fatal to the main measurement
-            res["serving"] = {"error": repr(e)}
+    if not args.no_extras:
+        if args.prec != "fp32":
+            # the plain fp32 GPU join on the same input: time and pair arrays
+            progress("plain fp32 join")
+            r32, rec = timed_calls(ctx, lambda: step("fp32"), 1)
+            rec["value"] = pairs / (rec["ms_per_call"] * 1e-3) / 1e9
+            rec["contract_tflops"] = flops / (rec["contract"] * 1e-3) / 1e12
+            rec["same_pairs"] = bool(r32.count == r.count and torch.equal(r32.i, r.i[:r.count])
+                                     and torch.equal(r32.j, r.j[:r.count]))
+            rec["speedup_of_%s" % args.prec] = rec["ms_per_call"] / ms_step
+            res["fp32_join"] = rec
+            del r32
+        progress("top-10 join")
+        t, rec = timed_calls(ctx, lambda: ops.join_topk(R, S, 10, prec=args.prec, workspace=ws), 2)
+        rec["value"] = pairs / (rec["ms_per_call"] * 1e-3) / 1e9
+        rec["contract_tflops"] = flops / (rec["contract"] * 1e-3) / 1e12
+        rec.update(band_entries=t.band_entries, ties=t.ties)
+        res["top10_join"] = rec
+        del t
+        torch.cuda.empty_cache()
+    # the oracle leg needs the timed result; keep its rows on the host
+    gpu_res = r
     if not args.no_cpu_baseline:
         progress("cpu baseline (oracle, about %.0f s)" % args.cpu_seconds)
-        res["cpu_baseline"] = cpu_baseline({"patches": cfg["patches"], "hist": hist.cpu().numpy()}, eps, n,
-                                           args.cpu_seconds)
+        res["cpu_baseline"] = cpu_baseline(R_h, S_h, eps, gpu_res, args.cpu_seconds)
+    del R, S, ws, out, gpu_res, r
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        progress("histogram leg")
+        res["histogram_join"], _ = histogram_leg(args, ["fp32", "fp16"], 3)
+        torch.cuda.empty_cache()
+        progress("store leg")
+        res["store_top32"] = store_leg()
+        torch.cuda.empty_cache()
+        if not args.no_serving:
+            try:
+                res["serving"] = serving(args)
+            except Exception as e:  # reported, not fatal to the main measurement
+                res["serving"] = {"error": repr(e)}
     print(json.dumps(res))
 
 
