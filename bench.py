@@ -50,7 +50,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for the CPU baseline")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-store", type=int, default=8000000, help="rows of the serving store")
-    ap.add_argument("--serve-seconds", type=float, default=20.0, help="open-loop seconds per offered rate")
+    ap.add_argument("--serve-seconds", type=float, default=60.0, help="open-loop seconds per offered rate")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="instead of the headline step, run the serving leg alone (profiling runs of the loop)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="copy this many MiB device-to-device first (scale for FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--histogram-headline", action="store_true",
@@ -238,7 +240,22 @@ def serving(args):
         th.join()
         st = srv.stats()
         bad = sum(1 for r in done if r["status"] != 0)
+        small = [r["latency_ms"] for r in done if r["rows"] <= 4096 and r["status"] == 0]
+        st["small_p50_ms"] = float(np.percentile(small, 50)) if small else None
+        st["small_p99_ms"] = float(np.percentile(small, 99)) if small else None
         return st, bad, float(rows.sum())
+
+    def roof(st):
+        # matrix-core rate of the served joins (2 d flop per pair) against the
+        # dense bf16 peak: over the phase's span, and while batches ran
+        flop = 2.0 * 128
+        span = st["pairs_done"] * flop / max(st["span_ms"], 1e-9) / 1e9
+        per_batch = st["batch_pairs"] * flop / max(st["batch_ms"], 1e-9) / 1e9
+        return {"bound": "mfma", "peak": PEAK_TFLOPS["bf16"], "unit": "TFLOP/s", "span_tflops": span,
+                "span_frac": span / PEAK_TFLOPS["bf16"], "per_batch_tflops": per_batch,
+                "per_batch_frac": per_batch / PEAK_TFLOPS["bf16"],
+                "note": "per_batch: summed batch pairs x 2d / summed batch run time (batches overlap on "
+                        "the device, so each one's share of the GPU is less than the whole)"}
 
     torch.cuda.synchronize()
     # closed loop: all requests at once
@@ -250,7 +267,7 @@ def serving(args):
            "setup_s": t_setup, "capacity_rps": cap_rps,
            "capacity": {"requests": st["completed"], "gpairs_per_s": st["pairs_done"] / st["span_ms"] * 1e-6,
                         "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_batch": st["mean_batch_requests"],
-                        "errors": bad}}
+                        "errors": bad, "roofline": roof(st)}}
     for frac in (0.5, 0.8):
         rate = frac * cap_rps
         n_req = max(8, int(rate * args.serve_seconds))
@@ -259,7 +276,10 @@ def serving(args):
         out["offered_%.1fC" % frac] = {"rate_rps": rate, "requests": st["completed"],
                                        "gpairs_per_s": st["pairs_done"] / max(st["span_ms"], 1e-9) * 1e-6,
                                        "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "max_ms": st["max_ms"],
-                                       "mean_batch": st["mean_batch_requests"], "errors": bad}
+                                       "p99_over_p50": st["p99_ms"] / max(st["p50_ms"], 1e-9),
+                                       "small_requests_p50_ms": st["small_p50_ms"],
+                                       "small_requests_p99_ms": st["small_p99_ms"],
+                                       "mean_batch": st["mean_batch_requests"], "errors": bad, "roofline": roof(st)}
     srv.close()
     return out
 
@@ -538,6 +558,9 @@ def main():
         del src, dst
     if args.histogram_headline:
         histogram_headline(args)
+        return
+    if args.serving_only:
+        print(json.dumps({"serving": serving(args)}))
         return
     n = args.n
     d = 128

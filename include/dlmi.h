@@ -92,11 +92,12 @@ const char* dl_version(void);
 
 /* Per-stage GPU timing with HIP events, recorded on the call's stream.
  * Stages: 0 featurize, 1 prep, 2 candidate contraction (the matrix-core
- * kernel), 3 recheck (fp32 + fp64 ties), 4 canonical sort, 5 top-k select.
+ * kernel), 3 recheck (fp32 + fp64 ties), 4 canonical sort, 5 top-k select,
+ * 6 index build (pivot order, block balls, bound pass, tile list).
  * dl_get_timing adds, per stage, the summed milliseconds and the number of
  * timed launches since the last reset into ms[] and calls[] (arrays of
  * DL_NUM_STAGES); it synchronises on the recorded events. */
-#define DL_NUM_STAGES 6
+#define DL_NUM_STAGES 7
 dl_status dl_set_timing(dl_ctx* ctx, int enable);
 dl_status dl_get_timing(dl_ctx* ctx, double* ms, int64_t* calls, int reset);
 
@@ -190,6 +191,39 @@ dl_status dl_join_eps_noalloc(dl_ctx* ctx, dl_mat R, dl_mat S, int self_join,
                               double eps, dl_prec prec, dl_pairs* out,
                               void* stream);
 
+/* ------------------------------------------------------ indexed eps-join */
+
+/* What the index of dl_join_eps_indexed pruned. */
+typedef struct dl_index_info {
+  int64_t tiles_total;    /* 256 x 256 tiles of the join (self-join: upper triangle) */
+  int64_t tiles_computed; /* tiles the candidate pass ran on                         */
+  int32_t pivots;         /* pivots of the row ordering; 0: no index was built        */
+} dl_index_info;
+
+/* Scratch bytes for dl_join_eps_indexed with room for `max_candidates`
+ * candidates; pivots as for the join (0 = default). */
+size_t dl_join_eps_indexed_workspace(int64_t nR, int64_t nS, int32_t d,
+                                     dl_prec prec, int self_join,
+                                     int64_t max_candidates, int32_t pivots);
+
+/* The eps-join of dl_join_eps -- same pair set, order, distances, outputs
+ * and errors -- with an index built on the fly inside the call (section
+ * "Query Processing": an index on one relation, probed by the other, built
+ * during the join; section "Derived Data": a Ball-tree answers Euclidean
+ * threshold queries).  The rows of each relation are ordered by their
+ * nearest pivot (`pivots` rows of S at a fixed stride; 0 = nS / 1,024,
+ * clamped to 16..4,096), every block of 256 ordered rows gets a ball
+ * (centroid, radius), and a 256 x 256 tile of pairs is computed only if a
+ * row of each side lies within eps + radius of the other side's ball, a test
+ * the triangle inequality makes exact (no result pair is ever pruned).  On
+ * clustered data most tiles are skipped.  Without a finite eps, or with a
+ * relation under 512 rows, it runs as dl_join_eps.  info (host, nullable)
+ * reports the tiles computed.  Synchronises `stream`. */
+dl_status dl_join_eps_indexed(dl_ctx* ctx, dl_mat R, dl_mat S, int self_join,
+                              double eps, dl_prec prec, int32_t pivots,
+                              void* ws, size_t ws_bytes, dl_pairs* out,
+                              dl_index_info* info, void* stream);
+
 /* ---------------------------------------------------------------- top-k */
 
 typedef struct dl_topk_info {
@@ -211,11 +245,12 @@ size_t dl_join_topk_workspace(int64_t nR, int64_t nS, int32_t d, dl_prec prec,
  *   out_j     device uint32[nR*k]; UINT32_MAX pads rows with fewer than k.
  *   out_dist  device float[nR*k];  +inf pads.
  *   info      host, nullable.
- * Returns DL_ERR_WORKSPACE if the workspace is too small, if a row's band
+ * Rows with more near-tie contenders than the selection holds in LDS (512:
+ * many rows of S at one distance, such as duplicates) are selected again
+ * over their band buffers in memory: slower, with the same exact answer.
+ * Returns DL_ERR_WORKSPACE if the workspace is too small or if a row's band
  * does not fit band_cap ("band buffer" in dl_last_error: retry with a larger
- * band_cap), or if a row has more near-tie contenders than the selection
- * holds (512; a larger band_cap does not help); DL_ERR_INVALID for bad
- * arguments.  Synchronises `stream`. */
+ * band_cap); DL_ERR_INVALID for bad arguments.  Synchronises `stream`. */
 dl_status dl_join_topk(dl_ctx* ctx, dl_mat R, dl_mat S, int self_join,
                        int32_t k, int exclude_self, dl_prec prec,
                        int32_t band_cap, void* ws, size_t ws_bytes,
@@ -260,7 +295,11 @@ dl_status dl_join_topk_store(dl_ctx* ctx, dl_mat R, const dl_store* store, int32
  * k) that fits the batch limits and the free arena memory, run them as one
  * join against the store, and publish per-request results.  Requests that
  * arrive while batches run are admitted as streams and memory free up.  A
- * request's result does not depend on the batch it ran in. */
+ * request's result and status do not depend on the batch it ran in: a batch
+ * that outgrows its output, candidate or band capacity puts its requests
+ * back at the head of the queue to run alone, and a request that outgrows
+ * them alone runs again with the capacity it reported (up to four times).
+ * With n_streams >= 2 the first stream is a lane for small requests. */
 typedef struct dl_server dl_server;
 
 #define DL_MODE_EPS 0
@@ -272,6 +311,9 @@ typedef struct dl_server_config {
   int64_t max_batch_rows;     /* query rows per batch (default 65536)            */
   int64_t pairs_per_row;      /* eps output room per query row (default 64)     */
   int32_t band_cap;           /* top-k band entries per row and split (0 = default) */
+  int64_t small_rows;         /* with n_streams >= 2 the first stream only runs
+                                 requests of at most this many rows (0 = 4,096;
+                                 < 0: no small-request lane)                 */
 } dl_server_config;
 
 typedef struct dl_request {
@@ -308,6 +350,8 @@ typedef struct dl_server_info {
   double span_ms;     /* first submit -> last completion */
   double p50_ms, p99_ms, max_ms;
   size_t arena_in_use, arena_peak;
+  double batch_ms;    /* summed wall time of successful batch runs (batch start -> results ready) */
+  double batch_pairs; /* summed rows x store rows of those batches */
 } dl_server_info;
 
 /* Starts the workers on `device`.  `arena` (device, caller-owned) holds every

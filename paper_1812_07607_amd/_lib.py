@@ -15,8 +15,8 @@ DL_OK, DL_ERR_INVALID, DL_ERR_OOM, DL_ERR_CAPACITY, DL_ERR_WORKSPACE, DL_ERR_DEV
 STATUS_NAMES = {0: "DL_OK", 1: "DL_ERR_INVALID", 2: "DL_ERR_OOM", 3: "DL_ERR_CAPACITY", 4: "DL_ERR_WORKSPACE",
                 5: "DL_ERR_DEVICE", 6: "DL_ERR_BUSY", 7: "DL_ERR_CANCELLED"}
 PREC = {"fp32": 0, "bf16": 1, "fp16": 2, "fp8": 3}
-NUM_STAGES = 6
-STAGES = ["featurize", "prep", "contract", "recheck", "sort", "select"]
+NUM_STAGES = 7
+STAGES = ["featurize", "prep", "contract", "recheck", "sort", "select", "index"]
 
 
 class dl_mat(ctypes.Structure):
@@ -29,13 +29,18 @@ class dl_pairs(ctypes.Structure):
                 ("ties", ctypes.c_int64)]
 
 
+class dl_index_info(ctypes.Structure):
+    _fields_ = [("tiles_total", ctypes.c_int64), ("tiles_computed", ctypes.c_int64), ("pivots", ctypes.c_int32)]
+
+
 class dl_topk_info(ctypes.Structure):
     _fields_ = [("band_entries", ctypes.c_int64), ("ties", ctypes.c_int64)]
 
 
 class dl_server_config(ctypes.Structure):
     _fields_ = [("n_streams", ctypes.c_int32), ("max_batch_requests", ctypes.c_int32),
-                ("max_batch_rows", ctypes.c_int64), ("pairs_per_row", ctypes.c_int64), ("band_cap", ctypes.c_int32)]
+                ("max_batch_rows", ctypes.c_int64), ("pairs_per_row", ctypes.c_int64), ("band_cap", ctypes.c_int32),
+                ("small_rows", ctypes.c_int64)]
 
 
 class dl_request(ctypes.Structure):
@@ -54,7 +59,8 @@ class dl_server_info(ctypes.Structure):
                 ("cancelled", ctypes.c_int64), ("batches", ctypes.c_int64), ("queued", ctypes.c_int64),
                 ("mean_batch_requests", ctypes.c_double), ("pairs_done", ctypes.c_double),
                 ("span_ms", ctypes.c_double), ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
-                ("max_ms", ctypes.c_double), ("arena_in_use", ctypes.c_size_t), ("arena_peak", ctypes.c_size_t)]
+                ("max_ms", ctypes.c_double), ("arena_in_use", ctypes.c_size_t), ("arena_peak", ctypes.c_size_t),
+                ("batch_ms", ctypes.c_double), ("batch_pairs", ctypes.c_double)]
 
 
 DL_MODE_EPS, DL_MODE_TOPK = 0, 1
@@ -77,6 +83,9 @@ SIGNATURES = {
     "dl_required_workspace": (sz, [P]),
     "dl_join_eps_noalloc": (ctypes.c_int, [P, dl_mat, dl_mat, ctypes.c_int, f64, ctypes.c_int,
                                            ctypes.POINTER(dl_pairs), P]),
+    "dl_join_eps_indexed_workspace": (sz, [i64, i64, i32, ctypes.c_int, ctypes.c_int, i64, i32]),
+    "dl_join_eps_indexed": (ctypes.c_int, [P, dl_mat, dl_mat, ctypes.c_int, f64, ctypes.c_int, i32, P, sz,
+                                           ctypes.POINTER(dl_pairs), ctypes.POINTER(dl_index_info), P]),
     "dl_join_topk_workspace": (sz, [i64, i64, i32, ctypes.c_int, ctypes.c_int, i32, i32]),
     "dl_join_topk": (ctypes.c_int, [P, dl_mat, dl_mat, ctypes.c_int, i32, ctypes.c_int, ctypes.c_int, i32, P, sz,
                                     P, P, ctypes.POINTER(dl_topk_info), P]),

@@ -29,7 +29,8 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + INCLUDE, "-I" + CSRC,
 ]
-SOURCES = ["api.hip", "featurize.hip", "prep.hip", "join_mfma.hip", "recheck.hip", "sort.hip", "serve.hip"]
+SOURCES = ["api.hip", "featurize.hip", "prep.hip", "join_mfma.hip", "recheck.hip", "sort.hip", "serve.hip",
+           "index.hip"]
 
 
 def _compile(src: str) -> str:

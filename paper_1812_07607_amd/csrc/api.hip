@@ -13,7 +13,8 @@ namespace dl {
 // featurize.hip
 hipError_t launch_hist_rgb8(const uint8_t*, int64_t, int32_t, int32_t, int32_t, float*, hipStream_t, int);
 // prep.hip
-hipError_t launch_prep(const float*, int64_t, int32_t, int64_t, dl_prec, const Prep&, RelStats*, hipStream_t, int);
+hipError_t launch_prep(const float*, int64_t, int32_t, int64_t, dl_prec, const Prep&, RelStats*, hipStream_t, int,
+                       const uint32_t* perm = nullptr);
 hipError_t launch_threshold(const Prep&, int64_t, const RelStats*, int, double, const double*, float*, float*, int*,
                             uint32_t*, hipStream_t);
 hipError_t launch_band_seed(const Prep&, int64_t, const float*, int, const float*, uint32_t*, hipStream_t);
@@ -23,11 +24,26 @@ hipError_t launch_band_seed(const Prep&, int64_t, const float*, int, const float
 
 namespace dl {
 hipError_t launch_cand_eps(dl_prec, CandParams, hipStream_t, int);
+hipError_t launch_cand_list(dl_prec, CandParams, hipStream_t, int);
+hipError_t launch_cand_mark(dl_prec, CandParams, hipStream_t, int);
+// index.hip
+hipError_t launch_gather_rows(const float*, int64_t, int64_t, int64_t, int, float*, hipStream_t, int);
+hipError_t launch_pivot_keys(const uint32_t*, int64_t, int64_t, int, unsigned long long*, float*, hipStream_t, int);
+hipError_t launch_block_balls(const float*, int64_t, const uint32_t*, int64_t, int, double, float*, double*,
+                              hipStream_t);
+hipError_t launch_survive(const uint32_t*, int64_t, const uint32_t*, int64_t, int64_t, int64_t, int, uint32_t*,
+                          int64_t, uint32_t*, hipStream_t);
+hipError_t launch_tile_list(const uint32_t*, int64_t, int64_t, const uint32_t*, uint2*, unsigned long long*,
+                            hipStream_t);
+// sort.hip
+hipError_t launch_exclusive_scan(const uint32_t*, int64_t, uint32_t*, uint32_t*, hipStream_t);
+int64_t scan_scratch_words(int64_t);
 hipError_t launch_cand_band(dl_prec, CandParams, hipStream_t);
 hipError_t launch_recheck_eps(const RecheckParams&, hipStream_t, int);
 hipError_t launch_pair_d2(const float*, int64_t, int64_t, const float*, int64_t, int64_t, int, const uint32_t*,
                           const uint32_t*, int64_t, double*, int*, hipStream_t, int);
 hipError_t launch_topk_select(const SelectParams&, bool, hipStream_t);
+hipError_t launch_topk_select_wide(const SelectParams&, hipStream_t);
 bool topk_select_small(int);
 int64_t row_sort_words(int64_t);
 hipError_t row_sort_pairs(const unsigned long long*, const float*, int64_t, int64_t, int, unsigned long long*, float*,
@@ -130,6 +146,8 @@ struct TopkLayout {
   uint32_t* gkey;  // per row: best band threshold of any split so far (order key)
   uint2* band;
   int* bcount;
+  int* rstate;  // per row: the band buffers hold float32 d2 (selection state)
+  int* wide;    // per row: more near-tie contenders than the selection holds
   size_t bytes;
 };
 
@@ -174,6 +192,8 @@ static TopkLayout layout_topk(void* ws, int64_t nR, int64_t nS, int d, dl_prec p
   L.gkey = b.take<uint32_t>(L.pr.npad);
   L.band = b.take<uint2>((nR < 1 ? 1 : nR) * (int64_t)P * cap);
   L.bcount = b.take<int>((nR < 1 ? 1 : nR) * (int64_t)P);
+  L.rstate = b.take<int>(nR < 1 ? 1 : nR);
+  L.wide = b.take<int>(nR < 1 ? 1 : nR);
   L.bytes = round_up((int64_t)b.off, 256);
   return L;
 }
@@ -629,6 +649,8 @@ dl_status topk_core(dl_ctx* c, const TopkJob& J, void* ws, size_t ws_bytes, uint
   }
   hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(L.cnt),
                      (int64_t)(sizeof(Counters) / 4));
+  hipLaunchKernelGGL(zero_words_kernel, dim3(64), dim3(256), 0, st, reinterpret_cast<uint32_t*>(L.rstate), R.n);
+  hipLaunchKernelGGL(zero_words_kernel, dim3(64), dim3(256), 0, st, reinterpret_cast<uint32_t*>(L.wide), R.n);
   if (S.n == 0) {
     // nothing to match: every row is padding
     hipLaunchKernelGGL(zero_words_kernel, dim3(256), dim3(256), 0, st, reinterpret_cast<uint32_t*>(L.bcount),
@@ -685,6 +707,8 @@ dl_status topk_core(dl_ctx* c, const TopkJob& J, void* ws, size_t ws_bytes, uint
     q.out_j = out_j; q.out_dist = out_dist;
     q.nband = &L.cnt->band; q.nties = &L.cnt->ties; q.too_many = &L.cnt->too_many;
     q.gate = &L.cnt->invalid;
+    q.rstate = L.rstate;
+    q.wide = L.wide;
     DL_HIP(c, launch_topk_select(q, small_sel, st));
   }
   DL_HIP(c, readback(c, L.cnt, L.sr, L.ss, st));
@@ -696,9 +720,22 @@ dl_status topk_core(dl_ctx* c, const TopkJob& J, void* ws, size_t ws_bytes, uint
                        (int64_t)4);  // ties and band
     hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(&L.cnt->too_many),
                        (int64_t)1);
+    hipLaunchKernelGGL(zero_words_kernel, dim3(64), dim3(256), 0, st, reinterpret_cast<uint32_t*>(L.wide), R.n);
     {
       StageTimer t(c, 5, st);
       DL_HIP(c, launch_topk_select(q, false, st));
+    }
+    DL_HIP(c, readback(c, L.cnt, L.sr, L.ss, st));
+    hc = *reinterpret_cast<const Counters*>(c->pinned);
+  }
+  if (hc.too_many && !hc.overflow) {
+    // rows with more near-tie contenders than the selection holds: the wide
+    // selection works on their band buffers in memory (the others are done)
+    hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(&L.cnt->too_many),
+                       (int64_t)1);
+    {
+      StageTimer t(c, 5, st);
+      DL_HIP(c, launch_topk_select_wide(q, st));
     }
     DL_HIP(c, readback(c, L.cnt, L.sr, L.ss, st));
     hc = *reinterpret_cast<const Counters*>(c->pinned);
@@ -713,6 +750,310 @@ dl_status topk_core(dl_ctx* c, const TopkJob& J, void* ws, size_t ws_bytes, uint
     return fail(c, DL_ERR_WORKSPACE, "top-k band exceeded its capacity (%s); retry with band_cap %d",
                 hc.overflow ? "band buffer" : "near-tie contenders", band_cap * 2);
   }
+  return DL_OK;
+}
+
+// ------------------------------------------------------------ indexed eps-join
+// The index-pruned eps-join (index.hip): pivot assignment and ordering, block
+// balls, a bound pass on the matrix cores, and the candidate pass over the
+// surviving tiles only; the recheck and the output are the plain join's.
+
+// Pivots: a strided sample of S, about one per 1,024 rows (16 to 4,096).
+static int64_t index_pivots(int64_t nS, int32_t want) {
+  int64_t p = want > 0 ? want : nS / 1024;
+  if (p < 16) p = 16;
+  if (p > 4096) p = 4096;
+  if (p > nS) p = nS;
+  return p;
+}
+constexpr int64_t kAssignChunk = 1 << 17;  // rows per pivot-assignment call
+constexpr int32_t kAssignBand = 320;       // band entries per row of that top-1 join
+
+struct IndexLayout {
+  uint32_t *permR, *permS;          // operand row -> row of R / S
+  float* piv;                       // pivots (P x d)
+  uint32_t* cid;                    // nearest pivot of each row (one relation at a time)
+  float* cdist;
+  uint8_t* aws;                     // workspace of the assignment top-1 joins
+  size_t aws_bytes;
+  unsigned long long *keys, *pk;    // ordering by pivot
+  float *vals, *pv, *od;
+  uint32_t *oi, *words;
+  float *centS, *centR;             // block centroids
+  double *TbS, *TbR;                // (eps + r)^2 per block
+  Prep pcS, pcR;                    // their operand copies
+  RelStats *scS, *scR;
+  float *thrS, *thrR;
+  uint32_t *m1, *m2, *surv, *cnt, *off, *sums;
+  int64_t m1w, m2w, sw;
+  uint2* tiles;
+  unsigned long long* ntiles;
+  size_t bytes;
+};
+
+static IndexLayout layout_index(void* base, int64_t nR, int64_t nS, int d, dl_prec prec, bool self, int64_t P,
+                                int cu) {
+  IndexLayout X{};
+  Bump b(base);
+  const int64_t n = nR > nS ? nR : nS;
+  const int64_t nTR = (nR + kTile - 1) / kTile, nTS = (nS + kTile - 1) / kTile;
+  X.permR = b.take<uint32_t>(nR);
+  X.permS = self ? X.permR : b.take<uint32_t>(nS);
+  X.piv = b.take<float>(P * (int64_t)d);
+  X.cid = b.take<uint32_t>(n);
+  X.cdist = b.take<float>(n);
+  const int64_t chunk = n < kAssignChunk ? n : kAssignChunk;
+  X.aws_bytes = topk_workspace(chunk, P, d, DL_BF16, false, false, 1, kAssignBand, cu);
+  X.aws = b.take<uint8_t>((int64_t)X.aws_bytes);
+  X.keys = b.take<unsigned long long>(n);
+  X.pk = b.take<unsigned long long>(n);
+  X.vals = b.take<float>(n);
+  X.pv = b.take<float>(n);
+  X.od = b.take<float>(n);
+  X.oi = b.take<uint32_t>(n);
+  X.words = b.take<uint32_t>(row_sort_words(P));
+  X.centS = b.take<float>(nTS * (int64_t)d);
+  X.TbS = b.take<double>(nTS);
+  X.pcS = carve_prep(b, nTS, d, prec);
+  X.scS = b.take<RelStats>(1);
+  X.thrS = b.take<float>(X.pcS.npad);
+  X.m1w = X.pcS.npad / 32;
+  X.m1 = b.take<uint32_t>(nTR * X.m1w);
+  if (self) {
+    X.centR = X.centS;
+    X.TbR = X.TbS;
+    X.pcR = X.pcS;
+    X.scR = X.scS;
+    X.thrR = X.thrS;
+    X.m2w = X.m1w;
+    X.m2 = X.m1;
+  } else {
+    X.centR = b.take<float>(nTR * (int64_t)d);
+    X.TbR = b.take<double>(nTR);
+    X.pcR = carve_prep(b, nTR, d, prec);
+    X.scR = b.take<RelStats>(1);
+    X.thrR = b.take<float>(X.pcR.npad);
+    X.m2w = X.pcR.npad / 32;
+    X.m2 = b.take<uint32_t>(nTS * X.m2w);
+  }
+  X.sw = (nTS + 31) / 32;
+  X.surv = b.take<uint32_t>(nTR * X.sw);
+  X.cnt = b.take<uint32_t>(nTR + 1);
+  X.off = b.take<uint32_t>(nTR + 1);
+  X.sums = b.take<uint32_t>(scan_scratch_words(nTR + 1) + 1);
+  X.tiles = b.take<uint2>(self ? nTR * (nTR + 1) / 2 : nTR * nTS);
+  X.ntiles = b.take<unsigned long long>(1);
+  X.bytes = round_up((int64_t)b.off, 256);
+  return X;
+}
+
+// The index-pruned join applies when eps is finite and each side spans at
+// least two tiles (and the tile list fits 32-bit counts).
+static bool index_applies(int64_t nR, int64_t nS, double eps) {
+  const int64_t nTR = (nR + kTile - 1) / kTile, nTS = (nS + kTile - 1) / kTile;
+  return std::isfinite(eps) && nTR >= 2 && nTS >= 2 && nTR * nTS < (1ll << 32) - 1;
+}
+
+size_t eps_indexed_workspace(int64_t nR, int64_t nS, int d, dl_prec prec, bool self, int64_t cap, int32_t pivots,
+                             int cu) {
+  const size_t main = layout_eps(nullptr, nR, nS, d, prec, self, cap).bytes;
+  if (!index_applies(nR, nS, 1.0)) return main;
+  return main + layout_index(nullptr, nR, nS, d, prec, self, index_pivots(nS, pivots), cu).bytes;
+}
+
+// Orders the rows of X (n x d) by nearest pivot: perm[q] = the q-th row in
+// (pivot, row) order.
+static dl_status order_by_pivot(dl_ctx* c, const dl_mat& X, const IndexLayout& I, int64_t P, uint32_t* perm,
+                                hipStream_t st) {
+  const dl_mat piv{I.piv, P, X.d, X.d};
+  for (int64_t r0 = 0; r0 < X.n; r0 += kAssignChunk) {
+    dl_mat part = X;
+    part.data = X.data + r0 * X.ld;
+    part.n = X.n - r0 < kAssignChunk ? X.n - r0 : kAssignChunk;
+    const TopkJob J{part, piv, false, false, DL_BF16, nullptr, nullptr, 1, kAssignBand};
+    const dl_status s = topk_core(c, J, I.aws, I.aws_bytes, I.cid + r0, I.cdist + r0, nullptr, st);
+    if (s != DL_OK) return s;
+  }
+  const int bj = bits_for(X.n);
+  DL_HIP(c, launch_pivot_keys(I.cid, X.n, P, bj, I.keys, I.vals, st, c->cu_count));
+  DL_HIP(c, row_sort_pairs(I.keys, I.vals, X.n, P, bj, I.pk, I.pv, I.words, X.n, I.oi, perm, I.od, st,
+                           c->cu_count));
+  return DL_OK;
+}
+
+// Bound pass: rows = the block centroids of one relation (their thresholds
+// Tb), columns = the ordered operand rows of the other (prep D, statistics
+// sD); marks bit (column tile, block) of m.
+static dl_status bound_pass(dl_ctx* c, const float* cent, int64_t nb, const double* Tb, int d, dl_prec prec,
+                            const Prep& pc, RelStats* sc, float* thr, const Prep& D, int64_t nD, const RelStats* sD,
+                            uint32_t* m, int64_t mw, const int* gate, hipStream_t st) {
+  const int64_t nTD = (nD + kTile - 1) / kTile;
+  hipLaunchKernelGGL(zero_words_kernel, dim3(256), dim3(256), 0, st, m, nTD * mw);
+  DL_HIP(c, launch_prep(cent, nb, d, d, prec, pc, sc, st, c->cu_count));
+  DL_HIP(c, launch_threshold(pc, nb, sD, d, 0.0, Tb, thr, nullptr, nullptr, nullptr, st));
+  CandParams q{};
+  q.qa = static_cast<const uint8_t*>(pc.q);
+  q.qb = static_cast<const uint8_t*>(D.q);
+  q.qld = pc.qld;
+  q.nchunks = (int)(pc.qld / kChunkBytes);
+  q.hb = D.h;
+  q.sexa = pc.sexp;
+  q.sexb = D.sexp;
+  q.nR = nb;
+  q.nS = nD;
+  q.thr = thr;
+  q.mark = m;
+  q.mark_words = mw;
+  q.gate = gate;
+  DL_HIP(c, launch_cand_mark(prec, q, st, c->cu_count));
+  return DL_OK;
+}
+
+dl_status eps_indexed_core(dl_ctx* c, const EpsJob& J, double eps, int32_t pivots, void* ws, size_t ws_bytes,
+                           dl_pairs* out, dl_index_info* info, hipStream_t st) {
+  const dl_mat &R = J.R, &S = J.S;
+  const bool self = J.self;
+  const dl_prec prec = J.prec;
+  const int d = R.d;
+  const int64_t nTR = (R.n + kTile - 1) / kTile, nTS = (S.n + kTile - 1) / kTile;
+  const int64_t all_tiles = self ? nTR * (nTR + 1) / 2 : nTR * nTS;
+  if (info) {
+    info->tiles_total = all_tiles;
+    info->tiles_computed = all_tiles;
+    info->pivots = 0;
+  }
+  if (!index_applies(R.n, S.n, eps)) return eps_core(c, J, ws, ws_bytes, out, st);
+  out->count = out->candidates = out->ties = 0;
+  const int64_t P = index_pivots(S.n, pivots);
+  const size_t xbytes = layout_index(nullptr, R.n, S.n, d, prec, self, P, c->cu_count).bytes;
+  // candidate capacity from what the workspace leaves beside the index
+  const size_t fixed = layout_eps(nullptr, R.n, S.n, d, prec, self, 1).bytes + xbytes;
+  if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(c, DL_ERR_INVALID, "workspace is not 256-byte aligned");
+  if (!ws || ws_bytes < fixed) {
+    c->required_ws = eps_indexed_workspace(R.n, S.n, d, prec, self, 1 << 20, pivots, c->cu_count);
+    return fail(c, DL_ERR_WORKSPACE, "workspace of %zu bytes below the minimum %zu", ws_bytes, fixed);
+  }
+  const size_t per = layout_eps(nullptr, R.n, S.n, d, prec, self, 1 << 16).bytes -
+                     layout_eps(nullptr, R.n, S.n, d, prec, self, 1).bytes;
+  int64_t cap = (int64_t)((double)(ws_bytes - fixed) / ((double)per / (1 << 16))) - 1024;
+  while (cap > 1 && layout_eps(nullptr, R.n, S.n, d, prec, self, cap).bytes + xbytes > ws_bytes) cap = cap * 63 / 64;
+  if (cap < 1) cap = 1;
+  if (cap > kMaxPairs) cap = kMaxPairs;
+  EpsLayout L = layout_eps(ws, R.n, S.n, d, prec, self, cap);
+  IndexLayout I = layout_index(static_cast<uint8_t*>(ws) + L.bytes, R.n, S.n, d, prec, self, P, c->cu_count);
+  if (info) info->pivots = (int32_t)P;
+
+  {
+    StageTimer t(c, 6, st);
+    // pivots, nearest-pivot order of each relation
+    DL_HIP(c, launch_gather_rows(S.data, S.ld, S.n / P, P, d, I.piv, st, c->cu_count));
+    dl_status s = order_by_pivot(c, R, I, P, I.permR, st);
+    if (s == DL_OK && !self) s = order_by_pivot(c, S, I, P, I.permS, st);
+    // a pivot assignment that outgrew its band buffers costs the pruning,
+    // not the call: the plain join has the same result
+    if (s == DL_ERR_WORKSPACE) {
+      if (info) info->pivots = 0;
+      return eps_core(c, J, ws, ws_bytes, out, st);
+    }
+    if (s != DL_OK) return s;
+  }
+  hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(L.cnt),
+                     (int64_t)(sizeof(Counters) / 4));
+  {
+    StageTimer t(c, 1, st);
+    DL_HIP(c, launch_prep(R.data, R.n, d, R.ld, prec, L.pr, L.sr, st, c->cu_count, I.permR));
+    if (!self) DL_HIP(c, launch_prep(S.data, S.n, d, S.ld, prec, L.ps, L.ss, st, c->cu_count, I.permS));
+    hipLaunchKernelGGL(input_gate_kernel, dim3(1), dim3(64), 0, st, L.sr, L.ss, &L.cnt->invalid);
+    DL_HIP(c, launch_threshold(L.pr, R.n, L.ss, d, J.T, nullptr, L.thr, nullptr, L.pex, nullptr, st));
+  }
+  {
+    StageTimer t(c, 6, st);
+    // block balls and the bound passes (both directions), then the tile list
+    DL_HIP(c, launch_block_balls(S.data, S.ld, I.permS, S.n, d, eps, I.centS, I.TbS, st));
+    dl_status s = bound_pass(c, I.centS, nTS, I.TbS, d, prec, I.pcS, I.scS, I.thrS, L.pr, R.n, L.sr, I.m1, I.m1w,
+                             &L.cnt->invalid, st);
+    if (s == DL_OK && !self) {
+      DL_HIP(c, launch_block_balls(R.data, R.ld, I.permR, R.n, d, eps, I.centR, I.TbR, st));
+      s = bound_pass(c, I.centR, nTR, I.TbR, d, prec, I.pcR, I.scR, I.thrR, L.ps, S.n, L.ss, I.m2, I.m2w,
+                     &L.cnt->invalid, st);
+    }
+    if (s != DL_OK) return s;
+    hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, st, I.cnt + nTR, (int64_t)1);
+    DL_HIP(c, launch_survive(I.m1, I.m1w, I.m2, I.m2w, nTR, nTS, self ? 1 : 0, I.surv, I.sw, I.cnt, st));
+    DL_HIP(c, launch_exclusive_scan(I.cnt, nTR + 1, I.off, I.sums, st));
+    DL_HIP(c, launch_tile_list(I.surv, I.sw, nTR, I.off, I.tiles, I.ntiles, st));
+  }
+  {
+    StageTimer t(c, 2, st);
+    CandParams p{};
+    p.qa = static_cast<const uint8_t*>(L.pr.q);
+    p.qb = static_cast<const uint8_t*>(L.ps.q);
+    p.qld = L.pr.qld;
+    p.nchunks = (int)(L.pr.qld / kChunkBytes);
+    p.hb = L.ps.h;
+    p.sexa = L.pr.sexp;
+    p.sexb = L.ps.sexp;
+    p.nR = R.n;
+    p.nS = S.n;
+    p.self_join = self;
+    p.thr = L.thr;
+    p.ccount = &L.cnt->cand;
+    p.cand = L.cand;
+    p.candp = prec == DL_FP8 ? nullptr : L.candp;
+    p.ccap = cap;
+    p.gate = &L.cnt->invalid;
+    p.tiles = I.tiles;
+    p.ntiles = I.ntiles;
+    DL_HIP(c, launch_cand_list(prec, p, st, c->cu_count));
+  }
+  const int bj = bits_for(S.n);
+  {
+    StageTimer t(c, 3, st);
+    RecheckParams q{};
+    q.R = R.data; q.ldr = R.ld;
+    q.S = S.data; q.lds = S.ld;
+    q.d = d;
+    q.cand = L.cand; q.ccount = &L.cnt->cand; q.ccap = cap;
+    q.candp = prec == DL_FP8 ? nullptr : L.candp;
+    q.pexR = L.pex;
+    q.nrm2R = L.pr.nrm2;
+    q.xnR = L.pr.xnorm; q.mlR = L.pr.mlsb;
+    q.xnS = L.ps.xnorm; q.mlS = L.ps.mlsb;
+    q.T = J.T;
+    q.bj = bj;
+    q.keys = L.k0; q.dist = L.v0; q.ocount = &L.cnt->out; q.nties = &L.cnt->ties;
+    q.permR = I.permR;
+    q.permS = I.permS;
+    q.swap = self ? 1 : 0;
+    DL_HIP(c, launch_recheck_eps(q, st, c->cu_count));
+  }
+  // the tile count rides along with the counters' readback
+  DL_HIP(c, hipMemcpyAsync(c->pinned + 28, I.ntiles, 8, hipMemcpyDeviceToHost, st));
+  DL_HIP(c, readback(c, L.cnt, L.sr, L.ss, st));
+  const Counters hc = *reinterpret_cast<const Counters*>(c->pinned);
+  if (info) info->tiles_computed = c->pinned[28];
+  if (dl_status bad = check_inputs(c)) return bad;
+  out->candidates = (int64_t)hc.cand;
+  out->ties = (int64_t)hc.ties;
+  if ((int64_t)hc.cand > cap && cap == kMaxPairs)
+    return fail(c, DL_ERR_CAPACITY, "%llu candidates exceed the %lld one call can order; split R", hc.cand,
+                (long long)kMaxPairs);
+  if ((int64_t)hc.cand > cap) {
+    c->required_ws = eps_indexed_workspace(R.n, S.n, d, prec, self, (int64_t)hc.cand + (int64_t)hc.cand / 8 + 1024,
+                                           pivots, c->cu_count);
+    return fail(c, DL_ERR_WORKSPACE, "%llu candidates exceed the workspace capacity %lld", hc.cand, (long long)cap);
+  }
+  const int64_t m = (int64_t)hc.out;
+  out->count = m;
+  {
+    StageTimer t(c, 4, st);
+    const int64_t w = m < out->capacity ? m : out->capacity;
+    DL_HIP(c, row_sort_pairs(L.k0, L.v0, m, R.n, bj, L.k1, L.v1, L.rows, w, out->i, out->j, out->dist, st,
+                             c->cu_count));
+  }
+  if (m > out->capacity)
+    return fail(c, DL_ERR_CAPACITY, "%lld pairs exceed the output capacity %lld", (long long)m,
+                (long long)out->capacity);
   return DL_OK;
 }
 
@@ -783,6 +1124,36 @@ dl_status dl_join_eps_noalloc(dl_ctx* c, dl_mat R, dl_mat S, int self_join, doub
   c->timing = timing;
   if (r == DL_ERR_WORKSPACE) c->required_ws = 0;  // a larger workspace is not an option here
   return r;
+}
+
+size_t dl_join_eps_indexed_workspace(int64_t nR, int64_t nS, int32_t d, dl_prec prec, int self_join,
+                                     int64_t max_cand, int32_t pivots) {
+  if (nR < 0 || nS < 0 || d < 1 || d > kMaxDim || !prec_ok(prec) || max_cand < 0) return 0;
+  if (self_join) nS = nR;
+  int cu = 256, dev;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) cu = prop.multiProcessorCount;
+  return eps_indexed_workspace(nR, nS, d, prec, self_join != 0, max_cand < 1 ? 1 : max_cand, pivots, cu);
+}
+
+dl_status dl_join_eps_indexed(dl_ctx* c, dl_mat R, dl_mat S, int self_join, double eps, dl_prec prec,
+                              int32_t pivots, void* ws, size_t ws_bytes, dl_pairs* out, dl_index_info* info,
+                              void* stream) {
+  if (!c) return DL_ERR_INVALID;
+  c->err.clear();
+  c->required_ws = 0;
+  if (self_join) S = R;
+  dl_status s;
+  if ((s = check_mat(c, R, "R")) != DL_OK || (s = check_mat(c, S, "S")) != DL_OK) return s;
+  if (R.d != S.d) return fail(c, DL_ERR_INVALID, "R.d %d != S.d %d", R.d, S.d);
+  if (std::isnan(eps) || eps < 0) return fail(c, DL_ERR_INVALID, "eps must be >= 0 (got %g)", eps);
+  if (!prec_ok(prec)) return fail(c, DL_ERR_INVALID, "unknown precision %d", (int)prec);
+  if (pivots < 0) return fail(c, DL_ERR_INVALID, "pivots = %d < 0", pivots);
+  if (!out || out->capacity < 0) return fail(c, DL_ERR_INVALID, "bad output struct");
+  if (out->capacity > 0 && (!out->i || !out->j || !out->dist)) return fail(c, DL_ERR_INVALID, "null output array");
+  DL_HIP(c, hipSetDevice(c->device));
+  EpsJob J{R, S, self_join != 0, prec, nullptr, nullptr, threshold_from_eps(eps), nullptr};
+  return eps_indexed_core(c, J, eps, pivots, ws, ws_bytes, out, info, static_cast<hipStream_t>(stream));
 }
 
 size_t dl_join_topk_workspace(int64_t nR, int64_t nS, int32_t d, dl_prec prec, int self_join, int32_t k,

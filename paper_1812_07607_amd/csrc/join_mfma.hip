@@ -89,7 +89,10 @@ __device__ inline int lds_off(int r, int c) {
   else return r * 64 + ((c ^ ((r >> 2) & 3)) << 4);
 }
 
-enum : int { kModeEps = 0, kModeBand = 1 };
+// eps: append candidates; band: top-k band; mark: the bound pass of the
+// index-pruned join (rows are block centroids, columns data rows; a hit sets
+// the block's bit for the data row's tile).
+enum : int { kModeEps = 0, kModeBand = 1, kModeMark = 2 };
 
 // Waves that issue the operand transfers (waves w and w + 4 share a SIMD).
 // Fewer issuing waves leave more waves free of transfers to feed the matrix
@@ -98,7 +101,7 @@ enum : int { kModeEps = 0, kModeBand = 1 };
 // mode, whose epilogue and tightening already load waves unevenly, is 1%
 // faster with four.
 template <int kMode>
-constexpr int dma_waves() { return kMode == kModeEps ? 2 : 4; }
+constexpr int dma_waves() { return kMode == kModeBand ? 4 : 2; }
 template <int kMode>
 constexpr int dma_per_op(int rows_per_dma) { return kTile / rows_per_dma / dma_waves<kMode>(); }
 
@@ -191,22 +194,31 @@ __device__ inline int fresh_lane() {
   return l;
 }
 
-// Block-uniform iterator over this workgroup's tiles: eps mode walks
-// logical tiles slot, slot + G, ... (G workgroups; slot = the workgroup's
-// place in the XCD dealing); band mode walks the S tiles of one (row tile,
-// split) work item, fixed at the first call.
+// Block-uniform iterator over this workgroup's tiles: eps (and mark) mode
+// walks logical tiles slot, slot + G, ... (G workgroups; slot = the
+// workgroup's place in the XCD dealing), either all tiles in the group order
+// or the entries of a tile list (p.tiles, *p.ntiles of them); band mode walks
+// the S tiles of one (row tile, split) work item, fixed at the first call.
 struct TileIter {
   int64_t step = 0;                              // eps: logical round
+  int64_t lim = -1;                              // eps: logical tiles
   int64_t ti = 0, split = 0, t = 0, t_end = 0;   // band
   __device__ bool next(const CandParams& p, int mode, int64_t& oti, int64_t& otj) {
     const int64_t G = gridDim.x;
     const int64_t slot = (int64_t)(blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
-    if (mode == kModeEps) {
+    if (mode != kModeBand) {
+      if (lim < 0) lim = p.tiles ? uniform64((int64_t)*p.ntiles) : p.nlogical;
       for (;;) {
         const int64_t L = step * G + slot;
         ++step;
-        if (L >= p.nlogical) return false;
+        if (L >= lim) return false;
         int64_t ti_, tj_;
+        if (p.tiles) {
+          const uint2 t2 = p.tiles[L];
+          oti = uniform64((int64_t)t2.x);
+          otj = uniform64((int64_t)t2.y);
+          return true;
+        }
         if (tile_of(p, L, ti_, tj_)) {
           oti = uniform64(ti_);
           otj = uniform64(tj_);
@@ -293,7 +305,7 @@ __device__ inline void issue_side(const CandParams& p, int64_t ti, int64_t tj, c
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) - (kDmaWaves < 8 ? kDmaWaves : 0);
   const int e = 4 * fresh_lane();
   if (w == 0) lds_dma16(p.hb + tj * kTile + e, d.hb);
-  if constexpr (kMode == kModeEps)
+  if constexpr (kMode != kModeBand)
     if (w == 1) lds_dma16(p.thr + ti * kTile + e, d.thr);
   if constexpr (kPrec == DL_FP8) {
     if (w == 2) lds_dma16(p.sexa + ti * kTile + e, d.sa);
@@ -541,6 +553,49 @@ __device__ inline bool epilogue_eps(const CandParams& p, int64_t ti, int64_t tj,
   return wrote;
 }
 
+// Mark epilogue (the bound pass of the index-pruned join).  Rows of the
+// tile are block centroids, columns the data rows of tile tj; every row with
+// a hit in any valid column sets its bit in tj's row of p.mark.  A lane's
+// outputs of (mb, r) lie on row mb*16 + 4*(lane/16) + r of the wave, so each
+// 16-lane group of a hit mask is one row.  Rows past the centroids have an
+// infinite threshold and never hit.
+__device__ inline void epilogue_mark(const CandParams& p, int64_t ti, int64_t tj, const f32x4 (&acc)[8][4],
+                                     const float* thr_tile) {
+  const int lane = fresh_lane(), wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wm = wave >> 2, wn = wave & 3;
+  const int lrow0 = wm * kWaveM + 4 * (lane >> 4);
+  const int lcol0 = wn * kWaveN + (lane & 15);
+  const int crem = (int)min(p.nS - tj * kTile, (int64_t)kTile);
+  uint64_t colok[4];
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) colok[nb] = __builtin_amdgcn_ballot_w64(lcol0 + nb * 16 < crem);
+  uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;  // the wave's 128 rows
+#pragma unroll
+  for (int mb = 0; mb < 8; ++mb) {
+    const float4 th = *reinterpret_cast<const float4*>(thr_tile + lrow0 + mb * 16);
+    const float tv[4] = {th.x, th.y, th.z, th.w};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      uint64_t m = 0;
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) m |= mask_ge(acc[mb][nb][r], tv[r]) & colok[nb];
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        if ((m >> (16 * g)) & 0xffffull) {
+          const int q = mb * 16 + 4 * g + r;  // row in the wave
+          const uint32_t bit = 1u << (q & 31);
+          if ((q >> 5) == 0) w0 |= bit;
+          else if ((q >> 5) == 1) w1 |= bit;
+          else if ((q >> 5) == 2) w2 |= bit;
+          else w3 |= bit;
+        }
+      }
+    }
+  }
+  const uint32_t mine = lane == 0 ? w0 : lane == 1 ? w1 : lane == 2 ? w2 : w3;
+  if (lane < 4 && mine)
+    atomicOr(p.mark + tj * p.mark_words + ((ti * kTile + wm * kWaveM) >> 5) + lane, mine);
+}
 
 constexpr int kSelPerLane = 8;  // entries per lane in the k-selection subset
 constexpr int kSelBits = 24;    // key bits resolved by the selection
@@ -828,7 +883,10 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
   // flight per later step)
   constexpr int kPerStep = 2 * dma_per_op<kMode>(Q::kRowsPerDma);
   static_assert((Q::kStages - 2) * kPerStep <= 8, "wait_and_sync covers two later steps at most");
-  constexpr bool kFp8 = kPrec == DL_FP8, kEps = kMode == kModeEps;
+  // kEps: the eps-like modes (eps and mark), one tile per pass with per-row
+  // thresholds; kQueue_: candidates staged in LDS (eps only)
+  constexpr bool kFp8 = kPrec == DL_FP8, kEps = kMode != kModeBand, kMark = kMode == kModeMark;
+  constexpr bool kQ = kMode == kModeEps;
   // the ring: kStages x (A step, B step)
   __shared__ __attribute__((aligned(1024))) uint8_t lds_ab[Q::kStages][2][Q::kStageBytes];
   // per-tile side data, three tiles deep (the loader runs at most two tiles
@@ -839,9 +897,9 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
   __shared__ __attribute__((aligned(16))) int side_sb[kFp8 ? 3 : 1][kFp8 ? kTile : 4];
   __shared__ __attribute__((aligned(16))) uint8_t lds_band_raw[kEps ? 16 : sizeof(BandLds)];
   BandLds& band = *reinterpret_cast<BandLds*>(lds_band_raw);
-  __shared__ __attribute__((aligned(16))) uint2 lds_eq[kEps ? kThreads / 64 : 1][kEps ? kQueue : 1];
+  __shared__ __attribute__((aligned(16))) uint2 lds_eq[kQ ? kThreads / 64 : 1][kQ ? kQueue : 1];
   // eps, except E4M3 (LDS budget): the staged candidates' P~
-  constexpr bool kStageP = kEps && !kFp8;
+  constexpr bool kStageP = kQ && !kFp8;
   __shared__ uint32_t lds_eqp[kStageP ? kThreads / 64 : 1][kStageP ? kQueue : 1];
 
   // invalid input (non-finite values, norms out of range): no work at all
@@ -950,7 +1008,12 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
       }
       mma_tail<kPrec>(acc, fr);
       // ---- epilogue
-      dirty |= epilogue_eps<kStageP>(p, ti, tj, acc, side_thr[sbuf], lds_eq[wave], lds_eqp[kStageP ? wave : 0], eq);
+      if constexpr (kMark) {
+        epilogue_mark(p, ti, tj, acc, side_thr[sbuf]);
+        dirty = true;  // atomics to global memory
+      } else {
+        dirty |= epilogue_eps<kStageP>(p, ti, tj, acc, side_thr[sbuf], lds_eq[wave], lds_eqp[kStageP ? wave : 0], eq);
+      }
       if (!more) break;
       ti = iti;  // the step just issued opens the next tile
       tj = itj;
@@ -1006,9 +1069,9 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
       }
     }
   }
-  if constexpr (kEps) {
+  if constexpr (kQ) {
     if (eq) flush_eps<kStageP>(p, lds_eq[wave], lds_eqp[kStageP ? wave : 0], eq);
-  } else {
+  } else if constexpr (!kEps) {
     __syncthreads();
     tighten_rows(p, ti, split, band, true);
     for (int r = threadIdx.x; r < kTile; r += kThreads) {
@@ -1049,7 +1112,33 @@ static void div_magic(uint32_t d, uint32_t& m, uint32_t& s1, uint32_t& s2) {
   s2 = l > 1 ? l - 1 : 0;
 }
 
+// eps mode over a device tile list (p.tiles, *p.ntiles entries): persistent
+// workgroups, one per CU, walk the list; mark = the bound pass (every tile).
+hipError_t launch_cand_list(dl_prec prec, CandParams p, hipStream_t st, int cu_count) {
+  p.nTR = (p.nR + kTile - 1) / kTile;
+  p.nTS = (p.nS + kTile - 1) / kTile;
+  if (p.nTR == 0 || p.nTS == 0 || !p.tiles) return hipSuccess;
+  p.GM = 1;
+  p.ngroups = p.nTR;
+  p.nlogical = 0;
+  p.small32 = 0;
+  const int64_t G = (cu_count + 7) / 8 * 8;
+  return launch_mode<kModeEps>(prec, p, dim3((unsigned)G), st);
+}
+
+static hipError_t launch_eps_like(dl_prec prec, CandParams p, hipStream_t st, int cu_count, bool mark);
+
+hipError_t launch_cand_mark(dl_prec prec, CandParams p, hipStream_t st, int cu_count) {
+  p.tiles = nullptr;
+  return launch_eps_like(prec, p, st, cu_count, true);
+}
+
 hipError_t launch_cand_eps(dl_prec prec, CandParams p, hipStream_t st, int cu_count) {
+  p.tiles = nullptr;
+  return launch_eps_like(prec, p, st, cu_count, false);
+}
+
+static hipError_t launch_eps_like(dl_prec prec, CandParams p, hipStream_t st, int cu_count, bool mark) {
   p.nTR = (p.nR + kTile - 1) / kTile;
   p.nTS = (p.nS + kTile - 1) / kTile;
   if (p.nTR == 0 || p.nTS == 0) return hipSuccess;
@@ -1074,6 +1163,7 @@ hipError_t launch_cand_eps(dl_prec prec, CandParams p, hipStream_t st, int cu_co
   const int64_t need = (p.nlogical + 7) / 8 * 8;
   if (G > need) G = need;
   G = (G + 7) / 8 * 8;
+  if (mark) return launch_mode<kModeMark>(prec, p, dim3((unsigned)G), st);
   return launch_mode<kModeEps>(prec, p, dim3((unsigned)G), st);
 }
 

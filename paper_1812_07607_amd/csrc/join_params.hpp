@@ -50,6 +50,13 @@ struct CandParams {
   int* bcount;         // [row * P + split]
   int* overflow;       // set when a band exceeds cap - 256
   const int* gate;     // nonzero: invalid input, the kernel does nothing
+  // eps mode over a tile list (index-pruned join): (ti, tj) entries and the
+  // device-side count; null = every tile
+  const uint2* tiles;
+  const unsigned long long* ntiles;
+  // mark mode: bit (tile tj, row i) at mark[tj * mark_words + i / 32]
+  uint32_t* mark;
+  int64_t mark_words;
 };
 
 // eps-join recheck (recheck.hip).
@@ -68,6 +75,11 @@ struct RecheckParams {
   int bj;  // bits of j in the output key
   unsigned long long* keys; float* dist; unsigned long long* ocount;
   unsigned long long* nties;
+  // index-pruned join: candidates are rows of the permuted operand copies;
+  // permR / permS give each one's row in R / S (null: no permutation), and
+  // swap orders a self-join's pair as (min, max)
+  const uint32_t* permR; const uint32_t* permS;
+  int swap;
 };
 
 // top-k exact selection (recheck.hip).
@@ -82,6 +94,11 @@ struct SelectParams {
   uint32_t* out_j; float* out_dist;
   unsigned long long* nband; unsigned long long* nties; int* too_many;
   const int* gate;  // nonzero: invalid input, every row is written as padding
+  // per row (nullable): rstate 1 once a selection over memory has replaced
+  // the row's band P~ by float32 d2; wide 1 when the row had more near-tie
+  // contenders than the selection holds (the wide selection takes it)
+  int* rstate;
+  int* wide;
 };
 
 }  // namespace dl

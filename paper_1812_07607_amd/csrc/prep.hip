@@ -35,15 +35,16 @@ __device__ inline int wave_min(int v) {
 }
 
 // One wave per row; rows in [n, npad) get zero operands and zero statistics.
+// perm (nullable): operand row r holds row perm[r] of X.
 template <int kPrec>
 __global__ __launch_bounds__(256) void prep_kernel(const float* __restrict__ X, int64_t n, int32_t d,
                                                    int64_t ld, int64_t dpad, Prep P,
-                                                   RelStats* __restrict__ rs) {
+                                                   RelStats* __restrict__ rs, const uint32_t* __restrict__ perm) {
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= P.npad) return;
   const bool real = row < n;
-  const float* x = X + (real ? row * ld : 0);
+  const float* x = X + (real ? (perm ? (int64_t)perm[row] : row) * ld : 0);
   int sexp = 0;
   if (kPrec == DL_FP8 && real) {
     float amax = 0.0f;
@@ -303,15 +304,15 @@ hipError_t launch_band_seed(const Prep& R, int64_t nR, const float* dist, int k,
 }
 
 hipError_t launch_prep(const float* X, int64_t n, int32_t d, int64_t ld, dl_prec prec, const Prep& P,
-                       RelStats* rs, hipStream_t st, int cu_count) {
+                       RelStats* rs, hipStream_t st, int cu_count, const uint32_t* perm) {
   hipLaunchKernelGGL(stats_init_kernel, dim3(1), dim3(64), 0, st, rs);
   const int64_t dpad = dpad_of(d, prec);
   const dim3 grid((unsigned)((P.npad + 3) / 4)), block(256);
   switch (prec) {
-    case DL_FP32: hipLaunchKernelGGL(prep_kernel<DL_FP32>, grid, block, 0, st, X, n, d, ld, dpad, P, rs); break;
-    case DL_BF16: hipLaunchKernelGGL(prep_kernel<DL_BF16>, grid, block, 0, st, X, n, d, ld, dpad, P, rs); break;
-    case DL_FP16: hipLaunchKernelGGL(prep_kernel<DL_FP16>, grid, block, 0, st, X, n, d, ld, dpad, P, rs); break;
-    case DL_FP8: hipLaunchKernelGGL(prep_kernel<DL_FP8>, grid, block, 0, st, X, n, d, ld, dpad, P, rs); break;
+    case DL_FP32: hipLaunchKernelGGL(prep_kernel<DL_FP32>, grid, block, 0, st, X, n, d, ld, dpad, P, rs, perm); break;
+    case DL_BF16: hipLaunchKernelGGL(prep_kernel<DL_BF16>, grid, block, 0, st, X, n, d, ld, dpad, P, rs, perm); break;
+    case DL_FP16: hipLaunchKernelGGL(prep_kernel<DL_FP16>, grid, block, 0, st, X, n, d, ld, dpad, P, rs, perm); break;
+    case DL_FP8: hipLaunchKernelGGL(prep_kernel<DL_FP8>, grid, block, 0, st, X, n, d, ld, dpad, P, rs, perm); break;
   }
   if (n > 0) {
     int64_t blocks = (n + 1023) / 1024;

@@ -110,12 +110,16 @@ __global__ __launch_bounds__(256) void recheck_eps_kernel(RecheckParams p) {
           mys = (float)(p.nrm2R[mine[c].x] - 2.0 * (double)p.candp[base + lane]);
         }
       }
+      // the candidate's rows of R and S (through the permutations of an
+      // index-pruned join; statistics stay indexed by the operand row)
+      const uint32_t oi = lane < cnt && p.permR ? p.permR[mine[c].x] : mine[c].x;
+      const uint32_t oj = lane < cnt && p.permS ? p.permS[mine[c].y] : mine[c].y;
+      const float* a = p.R + (int64_t)oi * p.ldr;
+      const float* b = p.S + (int64_t)oj * p.lds;
       // each lane sums its own candidate's row pair: the value depends on
       // the pair alone, not on which candidates share the wave
-      if (lane < cnt && !quick) {
-        const float* a = p.R + (int64_t)mine[c].x * p.ldr;
-        mys = lane_d2(a, p.S + (int64_t)mine[c].y * p.lds, p.d, vec4 && (reinterpret_cast<uintptr_t>(a) & 15) == 0);
-      }
+      if (lane < cnt && !quick)
+        mys = lane_d2(a, b, p.d, vec4 && (reinterpret_cast<uintptr_t>(a) & 15) == 0);
       in[c] = false;
       tie[c] = false;
       dist[c] = 0.0f;
@@ -131,11 +135,14 @@ __global__ __launch_bounds__(256) void recheck_eps_kernel(RecheckParams p) {
         dist[c] = sqrtf(mys);
         if (!in[c] && !(lo > T)) {  // boundary tie: the canonical float64 value decides
           tie[c] = true;
-          const double d64 = canonical_d2(p.R + (int64_t)mine[c].x * p.ldr, p.S + (int64_t)mine[c].y * p.lds, p.d);
+          const double d64 = canonical_d2(a, b, p.d);
           in[c] = d64 <= T;
           dist[c] = (float)sqrt(d64);
         }
       }
+      // the output names the pair by its rows of R and S (a self-join's
+      // smaller row first)
+      mine[c] = p.swap && oi > oj ? make_uint2(oj, oi) : make_uint2(oi, oj);
     }
     // one atomic for the whole span
     uint64_t mi[kRecheckChunks];
@@ -306,11 +313,14 @@ __global__ __launch_bounds__(64 * kSelWaves, kSelMax == kSelSmall ? 6 : 4) void 
     }
   };
   uint32_t key[kSelRegs], jv[kSelRegs];
+  // A row whose buffers an earlier selection over memory rewrote holds d2
+  // (not P~) in its entries: it goes to the memory path with the band known.
+  const bool in_d2 = p.rstate && __builtin_amdgcn_readfirstlane(p.rstate[i]);
   // A union too large for the registers is first filtered with the band of
   // its first entries: any lower bound of its k-th largest P~ keeps the
   // whole exact band, so the entries above it carry the same answer.
-  int kept = stage(-INFINITY);
-  if (kept > 64 * kSelRegs) {
+  int kept = in_d2 ? 64 * kSelRegs + 1 : stage(-INFINITY);
+  if (!in_d2 && kept > 64 * kSelRegs) {
     load_keys(key, jv, 64 * kSelRegs);
     kept = stage(band_of(key, 64 * kSelRegs));
   }
@@ -383,28 +393,36 @@ __global__ __launch_bounds__(64 * kSelWaves, kSelMax == kSelSmall ? 6 : 4) void 
       }
       return c;
     };
-    float bt = -INFINITY;
-    if (total >= k) {
-      uint32_t t = 0;
-      for (int b = 31; b >= 0; --b) {
-        const uint32_t cand = t | (1u << b);
-        if (count([&](uint32_t w) { return ord_f(__uint_as_float(w)) >= cand; }) >= k) t = cand;
+    if (!in_d2) {
+      float bt = -INFINITY;
+      if (total >= k) {
+        uint32_t t = 0;
+        for (int b = 31; b >= 0; --b) {
+          const uint32_t cand = t | (1u << b);
+          if (count([&](uint32_t w) { return ord_f(__uint_as_float(w)) >= cand; }) >= k) t = cand;
+        }
+        const float pk = __uint_as_float((t & 0x80000000u) ? (t & 0x7fffffffu) : ~t);
+        bt = f32_down((double)pk - (double)p.marg[i]);
       }
-      const float pk = __uint_as_float((t & 0x80000000u) ? (t & 0x7fffffffu) : ~t);
-      bt = f32_down((double)pk - (double)p.marg[i]);
-    }
-    for (int s = 0; s < p.P; ++s) {
-      uint2* e = p.band + (i * p.P + s) * (int64_t)p.cap;
-      const int n = p.bcount[i * p.P + s];
-      for (int base = 0; base < n; base += 64) {
-        const int t = base + lane;
-        const uint2 v = t < n ? e[t] : make_uint2(0, 0);
-        const bool inband = t < n && __uint_as_float(v.x) >= bt;
-        float d2 = INFINITY;
-        if (inband) d2 = lane_d2(a, p.S + (int64_t)v.y * p.lds, p.d, vec4);
-        if (t < n) e[t].x = __float_as_uint(d2);
-        nb += __popcll(__ballot(inband));
+      // each entry's P~ is replaced by its float32 d2 (+inf outside the
+      // band): the steps below, and any later selection of the row, read that
+      for (int s = 0; s < p.P; ++s) {
+        uint2* e = p.band + (i * p.P + s) * (int64_t)p.cap;
+        const int n = p.bcount[i * p.P + s];
+        for (int base = 0; base < n; base += 64) {
+          const int t = base + lane;
+          const uint2 v = t < n ? e[t] : make_uint2(0, 0);
+          const bool inband = t < n && __uint_as_float(v.x) >= bt;
+          float d2 = INFINITY;
+          if (inband) d2 = lane_d2(a, p.S + (int64_t)v.y * p.lds, p.d, vec4);
+          if (t < n) e[t].x = __float_as_uint(d2);
+          nb += __popcll(__ballot(inband));
+        }
       }
+      __builtin_amdgcn_s_waitcnt(0);
+      if (p.rstate && lane == 0) p.rstate[i] = 1;
+    } else {
+      nb = count([](uint32_t w) { return w < 0x7f800000u; });
     }
     uint64_t dk = 0;
     for (int b = 31; b >= 0; --b) {
@@ -433,7 +451,10 @@ __global__ __launch_bounds__(64 * kSelWaves, kSelMax == kSelSmall ? 6 : 4) void 
   }
   if (lane == 0) atomicAdd(p.nband, (unsigned long long)nb);
   if (nc > kSelMax) {
-    if (lane == 0) atomicOr(p.too_many, 1);
+    if (lane == 0) {
+      atomicOr(p.too_many, 1);
+      if (p.wide) p.wide[i] = 1;
+    }
     for (int t = lane; t < k; t += 64) {
       p.out_j[i * k + t] = 0xffffffffu;
       p.out_dist[i * k + t] = INFINITY;
@@ -485,6 +506,163 @@ __global__ __launch_bounds__(64 * kSelWaves, kSelMax == kSelSmall ? 6 : 4) void 
     p.out_j[i * k + r] = 0xffffffffu;
     p.out_dist[i * k + r] = INFINITY;
   }
+}
+
+// Rows with more near-tie contenders than the selection's LDS holds (p.wide
+// set): one wave per such row works on the row's band buffers in memory.
+// Every contender (float32 d2 within the cut) gets its float64 canonical key,
+// recomputed wherever it is needed instead of stored; the k-th smallest
+// (key, j) is found bit by bit over the 96-bit pair (64 key bits, then 32
+// index bits), counting the contenders below each trial value, and the k
+// contenders at or below it are ranked in LDS.  Slow (96 counting passes,
+// each d float64 operations per contender) but bounded by the row's band,
+// so a row of many exact duplicates still gets its exact answer.
+__global__ __launch_bounds__(64 * kSelWaves) void topk_select_wide_kernel(SelectParams p) {
+  __shared__ double s_key[kSelWaves][256];
+  __shared__ uint32_t s_j[kSelWaves][256];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t i = (int64_t)blockIdx.x * kSelWaves + wave;
+  if (i >= p.nR || !__builtin_amdgcn_readfirstlane(p.wide[i])) return;
+  const float* a = p.R + i * p.ldr;
+  const int k = p.k;
+  const uint64_t lt = __lanemask_lt();
+  const bool vec4 = ((reinterpret_cast<uintptr_t>(p.S) | reinterpret_cast<uintptr_t>(a)) & 15) == 0 &&
+                    (p.lds & 3) == 0;
+  int total = 0;
+  for (int s = 0; s < p.P; ++s) total += p.bcount[i * p.P + s];
+  auto count = [&](auto pred) {
+    int c = 0;
+    for (int s = 0; s < p.P; ++s) {
+      const uint2* e = p.band + (i * p.P + s) * (int64_t)p.cap;
+      const int n = p.bcount[i * p.P + s];
+      for (int base = 0; base < n; base += 64) {
+        const int t = base + lane;
+        c += __popcll(__ballot(t < n && pred(e[t])));
+      }
+    }
+    return c;
+  };
+  // (1) the row's entries as float32 d2 (+inf outside the band)
+  if (!__builtin_amdgcn_readfirstlane(p.rstate[i])) {
+    float bt = -INFINITY;
+    if (total >= k) {
+      uint32_t t = 0;
+      for (int b = 31; b >= 0; --b) {
+        const uint32_t cand = t | (1u << b);
+        if (count([&](uint2 v) { return ord_f(__uint_as_float(v.x)) >= cand; }) >= k) t = cand;
+      }
+      const float pk = __uint_as_float((t & 0x80000000u) ? (t & 0x7fffffffu) : ~t);
+      bt = f32_down((double)pk - (double)p.marg[i]);
+    }
+    for (int s = 0; s < p.P; ++s) {
+      uint2* e = p.band + (i * p.P + s) * (int64_t)p.cap;
+      const int n = p.bcount[i * p.P + s];
+      for (int base = 0; base < n; base += 64) {
+        const int t = base + lane;
+        const uint2 v = t < n ? e[t] : make_uint2(0, 0);
+        float d2 = INFINITY;
+        if (t < n && __uint_as_float(v.x) >= bt) d2 = lane_d2(a, p.S + (int64_t)v.y * p.lds, p.d, vec4);
+        if (t < n) e[t].x = __float_as_uint(d2);
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    if (lane == 0) p.rstate[i] = 1;
+  }
+  // (2) D_k and the cut, as in the selection
+  const double xsum = (double)p.xnR[i] + (double)p.sS->xnorm_max;
+  const bool ex = exact32(min(p.mlR[i], p.sS->mlsb_min), xsum);
+  const double c1 = ex ? 0.0 : 2.0 * gamma_n((double)p.d + 2.0, 0x1p-24);
+  const double c0 = ex ? 0.0 : ((double)p.d + 2.0) * 0x1p-148 + ((double)p.d + 4.0) * 0x1p-52 * xsum * xsum;
+  uint64_t dk = 0;
+  for (int b = 31; b >= 0; --b) {
+    const uint64_t lim = dk + (1ull << b);
+    if (count([&](uint2 v) { return (uint64_t)v.x < lim; }) < k) dk = lim;
+  }
+  const double Dk = dk >= 0x7f800000ull ? INFINITY : (double)__uint_as_float((uint32_t)dk);
+  const double cut = isinf(Dk) ? INFINITY : (Dk * (1.0 + c1) + 2.0 * c0) / (1.0 - c1) * (1.0 + 0x1p-50);
+  auto contender = [&](uint2 v) {
+    const float d2 = __uint_as_float(v.x);
+    return !isinf(d2) && (double)d2 <= cut;
+  };
+  auto key_of = [&](uint2 v) { return canonical_d2(a, p.S + (int64_t)v.y * p.lds, p.d); };
+  const int nc = count(contender);
+  const int want = nc < k ? nc : k;
+  // (3) the want-th smallest (key, j): largest (K, J) with fewer than want
+  // contenders below it
+  uint64_t K = 0;
+  uint32_t J = 0;
+  if (want > 0) {
+    for (int b = 63; b >= 0; --b) {
+      const uint64_t cand = K | (1ull << b);
+      const int c = count([&](uint2 v) {
+        return contender(v) && (uint64_t)__double_as_longlong(key_of(v)) < cand;
+      });
+      if (c < want) K = cand;
+    }
+    for (int b = 31; b >= 0; --b) {
+      const uint32_t cand = J | (1u << b);
+      const int c = count([&](uint2 v) {
+        if (!contender(v)) return false;
+        const uint64_t kv = (uint64_t)__double_as_longlong(key_of(v));
+        return kv < K || (kv == K && v.y < cand);
+      });
+      if (c < want) J = cand;
+    }
+  }
+  // (4) the want contenders at or below (K, J) into LDS, then ranked
+  int g = 0;
+  for (int s = 0; s < p.P; ++s) {
+    const uint2* e = p.band + (i * p.P + s) * (int64_t)p.cap;
+    const int n = p.bcount[i * p.P + s];
+    for (int base = 0; base < n; base += 64) {
+      const int t = base + lane;
+      const uint2 v = t < n ? e[t] : make_uint2(0x7f800000u, 0);
+      double kd = 0.0;
+      bool in = false;
+      if (t < n && contender(v)) {
+        kd = key_of(v);
+        const uint64_t kv = (uint64_t)__double_as_longlong(kd);
+        in = kv < K || (kv == K && v.y <= J);
+      }
+      const uint64_t m = __ballot(in);
+      const int pos = g + __popcll(m & lt);
+      if (in && pos < want) {
+        s_key[wave][pos] = kd;
+        s_j[wave][pos] = v.y;
+      }
+      g += __popcll(m);
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_wave_barrier();
+  for (int t = lane; t < want; t += 64) {
+    const double kt = s_key[wave][t];
+    const uint32_t jt = s_j[wave][t];
+    int rank = 0;
+    for (int u = 0; u < want; ++u) {
+      const double ku = s_key[wave][u];
+      rank += ku < kt || (ku == kt && s_j[wave][u] < jt);
+    }
+    p.out_j[i * k + rank] = jt;
+    p.out_dist[i * k + rank] = (float)sqrt(kt);
+  }
+  for (int r = want + lane; r < k; r += 64) {
+    p.out_j[i * k + r] = 0xffffffffu;
+    p.out_dist[i * k + r] = INFINITY;
+  }
+  const int nt = want;
+  if (lane == 0) {
+    atomicAdd(p.nties, (unsigned long long)nt);
+    p.wide[i] = 0;
+  }
+}
+
+hipError_t launch_topk_select_wide(const SelectParams& p, hipStream_t st) {
+  if (p.nR == 0 || !p.wide || !p.rstate) return hipSuccess;
+  const dim3 grid((unsigned)((p.nR + kSelWaves - 1) / kSelWaves)), block(64 * kSelWaves);
+  hipLaunchKernelGGL(topk_select_wide_kernel, grid, block, 0, st, p);
+  return hipGetLastError();
 }
 
 hipError_t launch_topk_select(const SelectParams& p, bool small, hipStream_t st) {

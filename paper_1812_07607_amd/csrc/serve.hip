@@ -17,7 +17,12 @@
 // that arrive while batches are on the GPU are admitted by the next worker
 // that frees up: continuous batching.  Per-pair arithmetic does not depend on
 // which rows share a batch, so a request's result is the same alone and in a
-// mix.
+// mix.  So is its status: a batch that outgrows its output, candidate or band
+// capacity does not fail its requests; they go back to the head of the queue
+// to run alone, and a request that outgrows them alone runs again with the
+// capacity its own run reported.  With two or more streams, the first one is
+// a lane for small requests (at most `small_rows` rows): it packs only those,
+// so they do not queue behind a long batch.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -101,6 +106,12 @@ struct Req {
   int64_t row_off = 0;
   std::shared_ptr<Batch> batch;
   bool released = false;
+  // after a capacity failure: run in a batch of its own, with at least these
+  // capacities (0 = the defaults for its rows)
+  bool solo = false;
+  int retries = 0;
+  int64_t pair_hint = 0, cand_hint = 0;  // eps output pairs and candidates
+  int32_t band_hint = 0;                 // top-k band entries per row and split
 };
 
 struct Batch {
@@ -112,6 +123,12 @@ struct Batch {
   size_t out_off = 0, out_bytes = 0;    // freed when every request is released
   bool work_held = false;
   int live = 0;                         // requests not yet released
+  int64_t pair_cap = 0, cand_cap = 0;   // eps capacities of this batch
+  int32_t band_cap = 0;                 // top-k band capacity (0 = library default)
+  // what a failed run reported: pairs and candidates it found (eps), a band
+  // buffer that overflowed (top-k)
+  int64_t need_pairs = 0, need_cands = 0;
+  bool band_full = false;
 };
 
 // Device helpers for one eps batch: start of each request's pairs in the
@@ -166,6 +183,7 @@ struct dl_server {
   // statistics
   int64_t submitted = 0, completed = 0, rejected = 0, cancelled = 0, batches = 0, batch_reqs = 0;
   double pairs_done = 0, t_first = -1, t_last = 0;
+  double batch_ms = 0, batch_pairs = 0;  // summed over successful batch runs
   std::vector<double> lat;
 
   ArenaAlloc& A() { return alloc; }
@@ -193,9 +211,28 @@ struct BatchLayout {
   size_t work_bytes = 0, out_bytes = 0;
 };
 
-void caps_for(dl_server* S, int64_t rows, int64_t* pair_cap, int64_t* cand_cap);
+// Capacities of a batch: the defaults for its rows, raised to what its
+// requests' earlier runs reported they need.
+struct Caps {
+  int64_t pairs = 0, cands = 0;
+  int32_t band = 0;
+};
+Caps caps_for(const dl_server* S, int64_t rows, const std::vector<Req*>& reqs) {
+  const int64_t ppr = S->cfg.pairs_per_row > 0 ? S->cfg.pairs_per_row : 64;
+  Caps c;
+  c.pairs = std::max<int64_t>(1 << 16, rows * ppr);
+  c.cands = std::max<int64_t>(1 << 17, 2 * rows * ppr);
+  c.band = S->cfg.band_cap;
+  for (const Req* r : reqs) {
+    c.pairs = std::max(c.pairs, r->pair_hint);
+    c.cands = std::max(c.cands, r->cand_hint);
+    c.band = std::max(c.band, r->band_hint);
+  }
+  return c;
+}
 
-BatchLayout carve_batch(dl_server* S, void* work, void* outb, int mode, int k, int64_t rows, int nreq) {
+BatchLayout carve_batch(dl_server* S, void* work, void* outb, int mode, int k, int64_t rows, int nreq,
+                        const Caps& caps) {
   const dl_store* st = S->store;
   const int d = st->base.d;
   BatchLayout L;
@@ -204,8 +241,7 @@ BatchLayout carve_batch(dl_server* S, void* work, void* outb, int mode, int k, i
   L.row_off = b.take<int64_t>((int64_t)nreq + 1);
   L.starts = b.take<int64_t>((int64_t)nreq + 1);
   if (mode == DL_MODE_EPS) {
-    int64_t pc, cc;
-    caps_for(S, rows, &pc, &cc);
+    const int64_t pc = caps.pairs, cc = caps.cands;
     L.pair_cap = pc;
     L.Trow = b.take<double>(rows);
     L.ws_bytes = eps_workspace(rows, st->base.n, d, st->prec, false, true, cc);
@@ -214,7 +250,7 @@ BatchLayout carve_batch(dl_server* S, void* work, void* outb, int mode, int k, i
     L.oj = o.take<uint32_t>(pc);
     L.od = o.take<float>(pc);
   } else {
-    L.ws_bytes = topk_workspace(rows, st->base.n, d, st->prec, false, true, k, S->cfg.band_cap, S->cu);
+    L.ws_bytes = topk_workspace(rows, st->base.n, d, st->prec, false, true, k, caps.band, S->cu);
     L.ws = b.take<uint8_t>((int64_t)L.ws_bytes);
     L.oj = o.take<uint32_t>(rows * (int64_t)k);
     L.od = o.take<float>(rows * (int64_t)k);
@@ -222,12 +258,6 @@ BatchLayout carve_batch(dl_server* S, void* work, void* outb, int mode, int k, i
   L.work_bytes = (size_t)round_up((int64_t)b.off, 256);
   L.out_bytes = (size_t)round_up((int64_t)o.off, 256);
   return L;
-}
-
-void caps_for(dl_server* S, int64_t rows, int64_t* pair_cap, int64_t* cand_cap) {
-  const int64_t ppr = S->cfg.pairs_per_row > 0 ? S->cfg.pairs_per_row : 64;
-  *pair_cap = std::max<int64_t>(1 << 16, rows * ppr);
-  *cand_cap = std::max<int64_t>(1 << 17, 2 * rows * ppr);
 }
 
 void finish(dl_server* S, Req* r, dl_status st, double t) {
@@ -242,17 +272,26 @@ void finish(dl_server* S, Req* r, dl_status st, double t) {
   S->t_last = t;
 }
 
+bool small_req(const dl_server* S, const Req* r) { return S->cfg.small_rows > 0 && rows_of(r) <= S->cfg.small_rows; }
+
 // Under the lock: form the next batch (or return null).  Requests whose
-// memory can never fit are rejected here.
-std::shared_ptr<Batch> take_batch(dl_server* S) {
-  while (!S->queue.empty()) {
-    Req* head = S->queue.front();
+// memory can never fit are rejected here.  small_only: the small-request
+// lane, which starts from the first small request in the queue and packs
+// only small ones.
+std::shared_ptr<Batch> take_batch(dl_server* S, bool small_only) {
+  for (;;) {
+    size_t h = 0;
+    if (small_only)
+      while (h < S->queue.size() && !small_req(S, S->queue[h])) ++h;
+    if (h >= S->queue.size()) return nullptr;
+    Req* head = S->queue[h];
     const int mode = head->rq.mode, k = head->rq.k;
     std::vector<Req*> pick{head};
     int64_t rows = rows_of(head);
-    for (size_t q = 1; q < S->queue.size(); ++q) {
+    for (size_t q = h + 1; q < S->queue.size() && !head->solo; ++q) {
       Req* r = S->queue[q];
       if ((int)pick.size() >= S->cfg.max_batch_requests) break;
+      if (r->solo || (small_only && !small_req(S, r))) continue;
       if (r->rq.mode != mode || (mode == DL_MODE_TOPK && r->rq.k != k)) continue;
       if (rows + rows_of(r) > S->cfg.max_batch_rows) continue;
       pick.push_back(r);
@@ -260,7 +299,8 @@ std::shared_ptr<Batch> take_batch(dl_server* S) {
     }
     // shrink until the arena has room
     for (;;) {
-      const BatchLayout need = carve_batch(S, nullptr, nullptr, mode, k, rows, (int)pick.size());
+      const Caps caps = caps_for(S, rows, pick);
+      const BatchLayout need = carve_batch(S, nullptr, nullptr, mode, k, rows, (int)pick.size(), caps);
       size_t woff = 0, ooff = 0;
       bool ok = S->alloc.alloc(need.work_bytes, &woff);
       if (ok && !S->alloc.alloc(need.out_bytes, &ooff)) {
@@ -280,6 +320,9 @@ std::shared_ptr<Batch> take_batch(dl_server* S) {
         b->out_bytes = need.out_bytes;
         b->work_held = true;
         b->live = (int)pick.size();
+        b->pair_cap = caps.pairs;
+        b->cand_cap = caps.cands;
+        b->band_cap = caps.band;
         for (Req* r : pick) {
           S->queue.erase(std::find(S->queue.begin(), S->queue.end(), r));
           r->state = 1;
@@ -296,7 +339,7 @@ std::shared_ptr<Batch> take_batch(dl_server* S) {
       // that could waits for running batches and released results
       if (round_up((int64_t)need.work_bytes, 256) + round_up((int64_t)need.out_bytes, 256) >
           (int64_t)S->alloc.size()) {
-        S->queue.pop_front();
+        S->queue.erase(S->queue.begin() + (std::ptrdiff_t)h);
         ++S->rejected;
         finish(S, head, DL_ERR_OOM, now_ms());
         S->cv_done.notify_all();
@@ -305,7 +348,6 @@ std::shared_ptr<Batch> take_batch(dl_server* S) {
       return nullptr;  // wait for memory
     }
   }
-  return nullptr;
 }
 
 // Runs one batch on the worker's stream (outside the lock).
@@ -313,7 +355,11 @@ dl_status run_batch(dl_server* S, dl_ctx* ctx, hipStream_t st, Batch& b, std::st
   const dl_store* store = S->store;
   const int d = store->base.d;
   const int nreq = (int)b.reqs.size();
-  BatchLayout L = carve_batch(S, S->arena + b.work_off, S->arena + b.out_off, b.mode, b.k, b.rows, nreq);
+  Caps caps;
+  caps.pairs = b.pair_cap;
+  caps.cands = b.cand_cap;
+  caps.band = b.band_cap;
+  BatchLayout L = carve_batch(S, S->arena + b.work_off, S->arena + b.out_off, b.mode, b.k, b.rows, nreq, caps);
   if (L.work_bytes > b.work_bytes || L.out_bytes > b.out_bytes)
     return *err = "batch layout exceeds its blocks", DL_ERR_OOM;
   std::vector<int64_t> hoff(nreq + 1, 0);
@@ -330,9 +376,13 @@ dl_status run_batch(dl_server* S, dl_ctx* ctx, hipStream_t st, Batch& b, std::st
   const dl_mat Rm{L.R, b.rows, d, d};
   if (b.mode == DL_MODE_TOPK) {
     const int k = b.k;
-    TopkJob J{Rm, store->base, false, false, store->prec, &store->prep, store->stats, k, S->cfg.band_cap};
+    TopkJob J{Rm, store->base, false, false, store->prec, &store->prep, store->stats, k, b.band_cap};
     dl_status s = topk_core(ctx, J, L.ws, L.ws_bytes, L.oj, L.od, nullptr, st);
-    if (s != DL_OK) return *err = dl_last_error(ctx), s;
+    if (s != DL_OK) {
+      *err = dl_last_error(ctx);
+      b.band_full = s == DL_ERR_WORKSPACE && err->find("band buffer") != std::string::npos;
+      return s;
+    }
     for (Req* r : b.reqs) {
       r->oj = L.oj + r->row_off * k;
       r->od = L.od + r->row_off * k;
@@ -348,7 +398,11 @@ dl_status run_batch(dl_server* S, dl_ctx* ctx, hipStream_t st, Batch& b, std::st
   dl_pairs P{L.oi, L.oj, L.od, L.pair_cap, 0, 0, 0};
   EpsJob J{Rm, store->base, false, store->prec, &store->prep, store->stats, 0.0, L.Trow};
   dl_status s = eps_core(ctx, J, L.ws, L.ws_bytes, &P, st);
-  if (s != DL_OK) return *err = dl_last_error(ctx), s;
+  if (s != DL_OK) {
+    b.need_pairs = P.count;
+    b.need_cands = P.candidates;
+    return *err = dl_last_error(ctx), s;
+  }
   hipLaunchKernelGGL(eps_demux_starts, dim3((nreq + 1 + 63) / 64), dim3(64), 0, st, L.oi, P.count, L.row_off, nreq,
                      L.starts);
   if (P.count > 0)
@@ -368,8 +422,42 @@ dl_status run_batch(dl_server* S, dl_ctx* ctx, hipStream_t st, Batch& b, std::st
   return DL_OK;
 }
 
+// Under the lock, after a run that failed for lack of capacity: put the
+// batch's requests back at the head of the queue, each to run alone, with
+// the capacity a request's own failed run reported.  Returns false (the
+// failure stands) for a request that has run alone too often or whose needs
+// did not grow.
+bool requeue_alone(dl_server* S, Batch& b, dl_status s) {
+  const bool eps = b.mode == DL_MODE_EPS;
+  if (!(eps ? (s == DL_ERR_CAPACITY || s == DL_ERR_WORKSPACE) : b.band_full)) return false;
+  if (b.reqs.size() == 1) {
+    // alone already: again with what this run reported
+    Req* r = b.reqs[0];
+    const int64_t pairs = b.need_pairs + b.need_pairs / 8 + 1024, cands = b.need_cands + b.need_cands / 8 + 1024;
+    const int32_t band = std::max<int32_t>(2 * std::max<int32_t>(b.band_cap, 512), 1024);
+    const bool grows = eps ? (pairs > b.pair_cap || cands > b.cand_cap) : band > b.band_cap;
+    if (++r->retries > 4 || !grows) return false;
+    if (eps) {
+      r->pair_hint = std::max(r->pair_hint, pairs);
+      r->cand_hint = std::max(r->cand_hint, cands);
+    } else {
+      r->band_hint = band;
+    }
+  }
+  for (auto it = b.reqs.rbegin(); it != b.reqs.rend(); ++it) {
+    Req* r = *it;
+    r->solo = true;
+    r->state = 0;
+    r->t_start = 0;
+    r->batch.reset();
+    S->queue.push_front(r);
+  }
+  return true;
+}
+
 void worker_main(dl_server* S, int idx) {
-  (void)idx;
+  // with two or more streams, the first is the small-request lane
+  const bool small_lane = idx == 0 && S->cfg.n_streams >= 2 && S->cfg.small_rows > 0;
   if (hipSetDevice(S->device) != hipSuccess) return;
   dl_ctx* ctx = nullptr;
   if (dl_create(S->device, &ctx) != DL_OK) return;
@@ -381,7 +469,7 @@ void worker_main(dl_server* S, int idx) {
   std::unique_lock<std::mutex> lk(S->mu);
   for (;;) {
     std::shared_ptr<Batch> b;
-    while (!S->stopping && !(b = take_batch(S))) S->cv_work.wait(lk);
+    while (!S->stopping && !(b = take_batch(S, small_lane))) S->cv_work.wait(lk);
     if (!b) break;
     ++S->busy;
     ++S->batches;
@@ -394,7 +482,16 @@ void worker_main(dl_server* S, int idx) {
     if (s == DL_OK && hipStreamSynchronize(st) != hipSuccess) s = DL_ERR_DEVICE;
     const double t1 = now_ms();
     lk.lock();
-    for (Req* r : b->reqs) finish(S, r, s, t1);
+    if (s != DL_OK && !S->stopping && requeue_alone(S, *b, s)) {
+      // nothing of this run is kept: both blocks are free again
+      S->alloc.release(b->out_off, b->out_bytes);
+    } else {
+      for (Req* r : b->reqs) finish(S, r, s, t1);
+      if (s == DL_OK) {
+        S->batch_ms += t1 - t0;
+        S->batch_pairs += (double)b->rows * (double)S->store->base.n;
+      }
+    }
     // the workspace is free as soon as the batch is done; results stay
     S->alloc.release(b->work_off, b->work_bytes);
     b->work_held = false;
@@ -434,6 +531,7 @@ dl_status dl_server_create(int device, const dl_store* store, const dl_server_co
   if (c.max_batch_requests <= 0) c.max_batch_requests = 64;
   if (c.max_batch_rows <= 0) c.max_batch_rows = 1 << 16;
   if (c.pairs_per_row <= 0) c.pairs_per_row = 64;
+  if (c.small_rows == 0) c.small_rows = 4096;
   dl_server* S = new (std::nothrow) dl_server();
   if (!S) return DL_ERR_OOM;
   S->store = store;
@@ -472,7 +570,7 @@ dl_status dl_server_submit(dl_server* S, const dl_request* rq, uint64_t* ticket)
     finish(S, r, DL_OK, r->t_submit);
   } else {
     S->queue.push_back(r);
-    S->cv_work.notify_one();
+    S->cv_work.notify_all();  // the small-request lane may not take it
   }
   *ticket = r->ticket;
   return DL_OK;
@@ -542,6 +640,8 @@ dl_status dl_server_stats(dl_server* S, dl_server_info* out) {
   out->mean_batch_requests = S->batches ? (double)S->batch_reqs / (double)S->batches : 0.0;
   out->pairs_done = S->pairs_done;
   out->span_ms = S->t_first >= 0 ? S->t_last - S->t_first : 0.0;
+  out->batch_ms = S->batch_ms;
+  out->batch_pairs = S->batch_pairs;
   out->arena_in_use = S->alloc.used();
   out->arena_peak = S->alloc.peak();
   out->queued = (int64_t)S->queue.size();
@@ -564,6 +664,7 @@ dl_status dl_server_reset_stats(dl_server* S) {
   std::lock_guard<std::mutex> lk(S->mu);
   S->submitted = S->completed = S->rejected = S->cancelled = S->batches = S->batch_reqs = 0;
   S->pairs_done = 0;
+  S->batch_ms = S->batch_pairs = 0;
   S->t_first = -1;
   S->t_last = 0;
   S->lat.clear();

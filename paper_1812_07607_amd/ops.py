@@ -197,6 +197,52 @@ def join_eps(R: torch.Tensor, S: torch.Tensor | None, eps: float, prec: str = "b
     raise RuntimeError("join_eps did not converge on workspace / capacity")
 
 
+@dataclass
+class IndexInfo:
+    tiles_total: int     # 256 x 256 tiles of the join (self-join: upper triangle)
+    tiles_computed: int  # tiles the candidate pass ran on
+    pivots: int          # 0: no index was built (the plain join ran)
+
+
+def join_eps_indexed(R: torch.Tensor, S: torch.Tensor | None, eps: float, prec: str = "bf16", pivots: int = 0,
+                     max_candidates: int | None = None, capacity: int | None = None, stream=None,
+                     workspace: Workspace | None = None):
+    """eps-join with an index built on the fly (block balls over rows ordered
+    by nearest pivot; tiles that cannot hold a result pair are skipped).  Same
+    result as join_eps; returns (EpsResult, IndexInfo)."""
+    self_join = S is None
+    Sm = R if self_join else S
+    c = context(R.device.index)
+    ws = workspace or _workspace(R.device)
+    p = _lib.PREC[prec]
+    nR, nS, d = R.shape[0], Sm.shape[0], R.shape[1]
+    if max_candidates is None:
+        max_candidates = max(1 << 20, 4 * (nR + nS))
+    cap = capacity if capacity is not None else max(1 << 16, nR + nS)
+    info = _lib.dl_index_info()
+    for _ in range(8):
+        need = c.L.dl_join_eps_indexed_workspace(nR, nS, d, p, int(self_join), max_candidates, pivots)
+        buf = ws.get(need)
+        oi = torch.empty(cap, dtype=torch.int32, device=R.device)
+        oj = torch.empty(cap, dtype=torch.int32, device=R.device)
+        od = torch.empty(cap, dtype=torch.float32, device=R.device)
+        pr = _lib.dl_pairs(oi.data_ptr(), oj.data_ptr(), od.data_ptr(), cap, 0, 0, 0)
+        st = c.L.dl_join_eps_indexed(c.h, _mat(R), _mat(Sm), int(self_join), float(eps), p, int(pivots),
+                                     ctypes.c_void_p(buf.data_ptr()), buf.numel(), ctypes.byref(pr),
+                                     ctypes.byref(info), _stream_ptr(stream))
+        if st == _lib.DL_ERR_WORKSPACE:
+            max_candidates = max(2 * max_candidates, int(pr.candidates * 1.25) + 1024)
+            continue
+        if st == _lib.DL_ERR_CAPACITY:
+            cap = int(pr.count)
+            continue
+        c.check(st)
+        m = int(pr.count)
+        return (EpsResult(oi[:m], oj[:m], od[:m], m, int(pr.candidates), int(pr.ties)),
+                IndexInfo(int(info.tiles_total), int(info.tiles_computed), int(info.pivots)))
+    raise RuntimeError("join_eps_indexed did not converge on workspace / capacity")
+
+
 # ---------------------------------------------------------------- top-k
 @dataclass
 class TopkResult:
@@ -335,13 +381,13 @@ class Server:
     """Batching request loop over a Store (see dl_server_* in dlmi.h)."""
 
     def __init__(self, store: Store, arena_bytes: int, n_streams: int = 2, max_batch_requests: int = 64,
-                 max_batch_rows: int = 1 << 16, pairs_per_row: int = 64, band_cap: int = 0):
+                 max_batch_rows: int = 1 << 16, pairs_per_row: int = 64, band_cap: int = 0, small_rows: int = 0):
         self.store = store
         self.c = store.c
         self.L = self.c.L
         self.device = store.base.device
         self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
-        cfg = _lib.dl_server_config(n_streams, max_batch_requests, max_batch_rows, pairs_per_row, band_cap)
+        cfg = _lib.dl_server_config(n_streams, max_batch_requests, max_batch_rows, pairs_per_row, band_cap, small_rows)
         h = ctypes.c_void_p()
         st = self.L.dl_server_create(self.device.index or 0, store.h, ctypes.byref(cfg),
                                      ctypes.c_void_p(self.arena.data_ptr()), self.arena.numel(), ctypes.byref(h))

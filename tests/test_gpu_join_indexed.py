@@ -1,0 +1,105 @@
+"""GPU parity of the index-pruned eps-join against the float64 oracle: the
+same pairs, in the same order, as the plain join, while tiles that cannot
+hold a result pair are skipped."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import assert_eps_equal, dev, host
+from paper_1812_07607_amd import ops, synth
+
+pytestmark = pytest.mark.gpu
+PRECS = ["fp32", "bf16", "fp16", "fp8"]
+
+
+def eps_quantile(orc, R, S, pairs, q):
+    d2 = orc.pair_d2(R, S, pairs[0], pairs[1])
+    return float(np.sqrt(synth.order_statistic(d2, q)))
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_histogram_self_join_indexed(orc, prec):
+    """8,000 palette-patch histograms (16 base colours): the 0.01% and 1%
+    quantile self-joins; most tiles pair different colours and are pruned."""
+    cfg = synth.config2(0.08)
+    H = orc.hist_rgb8(cfg["patches"], 8)
+    for q in (cfg["q"], 0.01):
+        eps = eps_quantile(orc, H, H, cfg["pairs"], q)
+        ref = orc.eps_join(H, None, eps)
+        got, info = ops.join_eps_indexed(dev(H), None, eps, prec)
+        assert_eps_equal(got, ref, 512, "indexed histograms q=%g/%s" % (q, prec))
+        assert info.pivots > 0 and info.tiles_total == 32 * 33 // 2
+        if q == cfg["q"]:
+            assert info.tiles_computed < info.tiles_total // 2, info
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_mixture_join_indexed(orc, prec):
+    """R 3,000 x S 5,000 rows of a tight 12-centre mixture, d = 64: eps at
+    several quantiles, from below the nearest pair to above the largest
+    cluster diameter (every tile survives)."""
+    R = synth.gaussian_mixture_unit(3000, 64, 12, sigma=0.02, seed=61)
+    S = synth.gaussian_mixture_unit(5000, 64, 12, sigma=0.02, seed=61, stream=1)
+    S[4321] = R[17]  # a duplicate
+    pairs = synth.sample_pairs(3000, 5000, 20000, False, seed=62)
+    for q in (0.0, 0.0005, 0.02, 0.2, 1.0):
+        eps = eps_quantile(orc, R, S, pairs, q) if q > 0 else 0.0
+        ref = orc.eps_join(R, S, eps)
+        got, info = ops.join_eps_indexed(dev(R), dev(S), eps, prec)
+        assert_eps_equal(got, ref, 64, "indexed mixture q=%g/%s" % (q, prec))
+        assert info.tiles_computed <= info.tiles_total == 12 * 20
+
+
+@pytest.mark.parametrize("shape", [(513, 1000, 1), (700, 2049, 129), (1500, 600, 300)])
+def test_ragged_shapes_indexed(orc, shape):
+    nR, nS, d = shape
+    R = synth.gaussian_mixture_unit(nR, d, 9, seed=nR + d) if d > 1 else synth.uniform_rows(nR, 1, seed=3)
+    S = synth.gaussian_mixture_unit(nS, d, 9, seed=nR + d, stream=1) if d > 1 else synth.uniform_rows(nS, 1, seed=4)
+    pairs = synth.sample_pairs(nR, nS, 4000, False, seed=5)
+    eps = eps_quantile(orc, R, S, pairs, 0.01)
+    ref = orc.eps_join(R, S, eps)
+    got, info = ops.join_eps_indexed(dev(R), dev(S), eps, "bf16", pivots=20)
+    assert_eps_equal(got, ref, d, "indexed %s" % (shape,))
+    assert info.pivots == 20
+
+
+def test_self_join_with_duplicates_indexed(orc):
+    X = synth.gaussian_mixture_unit(2600, 48, 7, sigma=0.03, seed=9)
+    X[100] = X[50]
+    X[2500] = X[50]
+    X[1200:1210] = X[3]
+    pairs = synth.sample_pairs(2600, 2600, 20000, True, seed=2)
+    for eps in (0.0, eps_quantile(orc, X, X, pairs, 0.005)):
+        ref = orc.eps_join(X, None, eps)
+        got, info = ops.join_eps_indexed(dev(X), None, eps, "fp16")
+        assert_eps_equal(got, ref, 48, "indexed self eps=%g" % eps)
+
+
+def test_fallbacks_run_the_plain_join(orc):
+    # infinite eps, and a relation within one 256-row tile: no index, same result
+    X = synth.gaussian_mixture_unit(700, 16, 4, seed=10)
+    Y = synth.gaussian_mixture_unit(200, 16, 4, seed=10, stream=1)
+    ref = orc.eps_join(X, Y, float("inf"))
+    got, info = ops.join_eps_indexed(dev(X), dev(Y), float("inf"), "bf16")
+    assert info.pivots == 0 and got.count == 700 * 200
+    assert_eps_equal(got, ref, 16, "eps = inf")
+    eps = 0.3
+    ref = orc.eps_join(X, Y, eps)
+    got, info = ops.join_eps_indexed(dev(X), dev(Y), eps, "bf16")
+    assert info.pivots == 0
+    assert_eps_equal(got, ref, 16, "200-row S")
+
+
+def test_full_histogram_workload_equals_plain_join():
+    """100,000 patches at the 0.01% quantile: the indexed join's arrays equal
+    the plain join's (which the oracle tests pin) and most tiles are pruned."""
+    cfg = synth.config2(1.0)
+    H = ops.featurize_rgb8(dev(cfg["patches"]), 8)
+    pi, pj = cfg["pairs"]
+    d2 = host(ops.pair_d2(H, H, torch.from_numpy(pi), torch.from_numpy(pj)))
+    eps = float(np.sqrt(synth.order_statistic(d2, cfg["q"])))
+    plain = ops.join_eps(H, None, eps, "fp16")
+    got, info = ops.join_eps_indexed(H, None, eps, "fp16")
+    assert got.count == plain.count > 0
+    assert torch.equal(got.i, plain.i) and torch.equal(got.j, plain.j) and torch.equal(got.dist, plain.dist)
+    assert info.tiles_computed < info.tiles_total // 4, info

@@ -124,3 +124,20 @@ def test_many_exact_ties_use_the_large_selection(orc):
     ref_j, _, ref_dist = orc.topk(R, S, 10)
     got = ops.join_topk(dev(R), dev(S), 10, prec="bf16")
     assert_topk_equal(got, ref_j, ref_dist, 48, "300 exact ties")
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+def test_more_exact_ties_than_the_selection_holds(orc, prec):
+    """1,000 copies of one row in S: every query row has 1,000 contenders at
+    its k-th distance, more than the selection holds in LDS (512), so those
+    rows are selected over their band buffers in memory; ties go to the
+    smaller index.  A second query set keeps only some rows on the ties."""
+    rng = np.random.default_rng(78)
+    S = rng.standard_normal((6000, 40)).astype(np.float32)
+    S[2000:3000] = S[7]
+    R = (S[7] + 0.01 * rng.standard_normal((24, 40))).astype(np.float32)
+    R[10:] = rng.standard_normal((14, 40)).astype(np.float32)  # rows far from the copies
+    for k in (10, 200):
+        ref_j, _, ref_dist = orc.topk(R, S, k)
+        got = ops.join_topk(dev(R), dev(S), k, prec=prec)
+        assert_topk_equal(got, ref_j, ref_dist, 40, "1,000 exact ties k=%d/%s" % (k, prec))

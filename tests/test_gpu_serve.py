@@ -133,3 +133,38 @@ def test_cancel_and_invalid(store_data):
         assert srv.wait(t, WAIT_MS)["status"] == DL_OK
     finally:
         srv.close()
+
+
+def test_batch_capacity_overflow_does_not_fail_batch_mates(orc, store_data):
+    """Requests whose pairs fit the per-batch output capacity alone but not
+    together (and one that does not fit it even alone): every request still
+    succeeds, with the result it has alone, equal to the oracle's."""
+    S = store_data
+    st = ops.Store(dev(S), "bf16")
+    probe = synth.gaussian_mixture_unit(64, D, 200, seed=505, stream=98)
+    pi, pj = np.meshgrid(np.arange(64), np.arange(S.shape[0]), indexing="ij")
+    d2 = orc.pair_d2(probe, S, pi.ravel(), pj.ravel())
+    # about 20,000 store rows per query row: four rows overflow 65,536 pairs
+    eps = float(np.sqrt(np.sort(d2)[int(len(d2) * 20000 / S.shape[0])]))
+    qs = [synth.gaussian_mixture_unit(n, D, 200, seed=505, stream=300 + t) for t, n in enumerate([1, 1, 1, 1, 1, 5, 2])]
+    srv = ops.Server(st, arena_bytes=2 << 30, n_streams=1, max_batch_requests=16, pairs_per_row=64)
+    try:
+        tq = [dev(q) for q in qs]
+        # one worker: the first request runs while the rest queue up and are batched
+        tickets = [srv.submit(q, "eps", eps=eps) for q in tq]
+        mixed = [srv.wait(t, WAIT_MS) for t in tickets]
+        alone = []
+        for q in tq:
+            t = srv.submit(q, "eps", eps=eps)
+            alone.append(srv.wait(t, WAIT_MS))
+    finally:
+        srv.close()
+    for t, (a, b) in enumerate(zip(alone, mixed)):
+        assert a["status"] == DL_OK and b["status"] == DL_OK, "request %d: %d alone, %d in the mix" % (
+            t, a["status"], b["status"])
+        assert _same(a, b), "request %d changed when batched" % t
+        ref = orc.eps_join(qs[t], S, eps)
+        res = ops.EpsResult(b["i"].view(torch.int32), b["j"].view(torch.int32), b["dist"], b["count"], 0, 0)
+        assert_eps_equal(res, ref, D, "overflowing eps request %d" % t)
+    assert sum(r["count"] for r in mixed) > 65536
+    assert max(r["count"] for r in mixed) > 65536  # the 5-row request alone outgrows the default
