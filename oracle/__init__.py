@@ -49,6 +49,8 @@ def lib():
         i64, i32, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
         L.orc_hist_rgb8.argtypes = [P, i64, i32, i32, i32, P, P, i32]
         L.orc_hist_rgb8.restype = ctypes.c_int
+        L.orc_hist_crops.argtypes = [P, i64, i32, i32, P, i64, i32, P, i32]
+        L.orc_hist_crops.restype = ctypes.c_int
         L.orc_d2.argtypes = [P, P, i32]
         L.orc_d2.restype = f64
         L.orc_pair_d2.argtypes = [P, i64, P, i64, i32, P, P, i64, P, i32]
@@ -97,6 +99,26 @@ def hist_rgb8(patches: np.ndarray, bins: int = 8, nthreads: int = 0, counts: boo
     if rc != 0:
         raise ValueError("orc_hist_rgb8 failed with code %d" % rc)
     return (out, cnt) if counts else out
+
+
+def hist_crops(frames: np.ndarray, boxes, bins: int = 8, nthreads: int = 0) -> np.ndarray:
+    """Colour histograms of bounding boxes over frames (section "Iterator API
+    for Patches": a patch is a region of an image; section "Visual ETL").
+
+    frames: (nframes, height, width, 3) uint8; boxes: (m, 5) int (frame, x0,
+    y0, x1, y1), pixels x0 <= x < x1, y0 <= y < y1.  Returns (m, bins**3)
+    float32, each count divided by the box's pixel count.
+    """
+    f = np.ascontiguousarray(frames, dtype=np.uint8)
+    if f.ndim != 4 or f.shape[3] != 3:
+        raise ValueError("frames must be (nframes, height, width, 3)")
+    bx = np.ascontiguousarray(boxes, dtype=np.int32).reshape(-1, 5)
+    out = np.empty((bx.shape[0], bins ** 3), np.float32)
+    rc = lib().orc_hist_crops(_ptr(f), f.shape[0], f.shape[1], f.shape[2], _ptr(bx), bx.shape[0], bins,
+                              _ptr(out), nthreads)
+    if rc != 0:
+        raise ValueError("orc_hist_crops failed with code %d" % rc)
+    return out
 
 
 def d2(a: np.ndarray, b: np.ndarray) -> float:

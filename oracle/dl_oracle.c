@@ -13,6 +13,10 @@
  *                   (section "Visual ETL", Transformers; Example 2 of
  *                   section "Iterator API for Patches" names colour
  *                   histograms as the matching feature).
+ *   orc_hist_crops  the same histogram over the pixels of bounding boxes cut
+ *                   from full frames (a patch refers to a region of an image:
+ *                   section "Iterator API for Patches"; ETL crops patches
+ *                   out of frames: section "Visual ETL", Patch Generators).
  *   orc_d2          Euclidean distance between two patch vectors
  *                   (section "Derived Data": Euclidean threshold queries on
  *                   image features).
@@ -98,6 +102,57 @@ int orc_hist_rgb8(const uint8_t* patches, int64_t n, int32_t h, int32_t w,
         out[p * nb + k] = (float)((double)cnt[k] / (double)npx);
         if (counts) counts[p * nb + k] = cnt[k];
       }
+    }
+    free(cnt);
+  }
+  return err;
+}
+
+/* ---------------------------------------------------------------------------
+ * Colour histogram of crops.  frames: nframes x height x width x 3 uint8,
+ * contiguous, HWC, R,G,B.  boxes: nboxes x 5 int32 (frame, x0, y0, x1, y1),
+ * the pixels x0 <= x < x1, y0 <= y < y1 of the frame.  out: nboxes x bins^3
+ * floats, each count divided by the box's pixel count (in double, rounded
+ * once to float).  A box outside its frame is an argument error.
+ * ------------------------------------------------------------------------- */
+int orc_hist_crops(const uint8_t* frames, int64_t nframes, int32_t height,
+                   int32_t width, const int32_t* boxes, int64_t nboxes,
+                   int32_t bins, float* out, int32_t nthreads) {
+  if (nframes < 0 || nboxes < 0 || height <= 0 || width <= 0 || bins <= 0 ||
+      bins > 256 || 256 % bins != 0)
+    return ORC_ERR_ARG;
+  for (int64_t b = 0; b < nboxes; ++b) {
+    const int32_t* bx = boxes + 5 * b;
+    if (bx[0] < 0 || bx[0] >= nframes || bx[1] < 0 || bx[1] >= bx[3] ||
+        bx[3] > width || bx[2] < 0 || bx[2] >= bx[4] || bx[4] > height)
+      return ORC_ERR_ARG;
+  }
+  const int64_t nb = (int64_t)bins * bins * bins;
+  const int32_t bw = 256 / bins;
+  set_threads(nthreads);
+  int err = ORC_OK;
+#pragma omp parallel
+  {
+    int32_t* cnt = (int32_t*)malloc((size_t)nb * sizeof(int32_t));
+    if (!cnt) {
+#pragma omp atomic write
+      err = ORC_ERR_NOMEM;
+    }
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t b = 0; b < nboxes; ++b) {
+      if (!cnt) continue;
+      const int32_t* bx = boxes + 5 * b;
+      memset(cnt, 0, (size_t)nb * sizeof(int32_t));
+      for (int32_t y = bx[2]; y < bx[4]; ++y) {
+        for (int32_t x = bx[1]; x < bx[3]; ++x) {
+          const uint8_t* px =
+              frames + (((int64_t)bx[0] * height + y) * width + x) * 3;
+          cnt[((px[0] / bw) * bins + px[1] / bw) * bins + px[2] / bw] += 1;
+        }
+      }
+      const int64_t npx = (int64_t)(bx[3] - bx[1]) * (bx[4] - bx[2]);
+      for (int64_t k = 0; k < nb; ++k)
+        out[b * nb + k] = (float)((double)cnt[k] / (double)npx);
     }
     free(cnt);
   }

@@ -106,3 +106,79 @@ def test_empty_batch(orc):
 def test_rejects_bad_bins(orc):
     with pytest.raises(ValueError):
         orc.hist_rgb8(np.zeros((1, 2, 2, 3), np.uint8), 3)
+
+
+# ----------------------------------------------------------------- crops
+def read_crop_golden():
+    rows = read_golden("crop_hand.txt")
+    bins = int([r for r in rows if r[0] == "bins"][0][1])
+    h, w = map(int, [r for r in rows if r[0] == "frame"][0][1:])
+    px = [list(map(int, r[1:])) for r in rows if r[0] == "row"]
+    frame = np.array(px, np.uint8).reshape(1, h, w, 3)
+    boxes, expects = [], []
+    for r in rows:
+        if r[0] == "box":
+            boxes.append(list(map(int, r[1:])))
+            expects.append([])
+        elif r[0] == "expect":
+            num, den = map(int, r[2].split("/"))
+            expects[-1].append((int(r[1]), num, den, int(r[3], 16)))
+    return bins, frame, np.array(boxes, np.int32), expects
+
+
+def test_crop_hand_example(orc):
+    bins, frame, boxes, expects = read_crop_golden()
+    got = orc.hist_crops(frame, boxes, bins)
+    for b, ex in enumerate(expects):
+        want = np.zeros(bins ** 3, np.float32)
+        for k, num, den, bits in ex:
+            # the stated bits are the correctly rounded float32 of num/den
+            assert (np.float32(num) / np.float32(den)).view(np.uint32) == bits
+            want[k] = np.uint32(bits).view(np.float32)
+        assert np.array_equal(got[b], want), "box %d" % b
+
+
+def random_boxes(rng, nframes, height, width, m):
+    f = rng.integers(0, nframes, size=m)
+    x0 = rng.integers(0, width, size=m)
+    y0 = rng.integers(0, height, size=m)
+    x1 = x0 + 1 + rng.integers(0, width - x0)
+    y1 = y0 + 1 + rng.integers(0, height - y0)
+    return np.stack([f, x0, y0, x1, y1], axis=1).astype(np.int32)
+
+
+@pytest.mark.parametrize("bins", [8, 4])
+def test_crops_equal_histograms_of_sliced_patches(orc, bins):
+    """A crop's histogram is the patch histogram of the cut-out pixels
+    (numpy slicing, then the patch routine, itself pinned to histogramdd)."""
+    rng = np.random.default_rng(31 + bins)
+    frames = rng.integers(0, 256, size=(3, 23, 37, 3), dtype=np.uint8)
+    boxes = random_boxes(rng, 3, 23, 37, 60)
+    boxes[0] = (1, 0, 0, 37, 23)  # a whole frame
+    boxes[1] = (2, 36, 22, 37, 23)  # the last pixel
+    got = orc.hist_crops(frames, boxes, bins)
+    for b, (f, x0, y0, x1, y1) in enumerate(boxes):
+        patch = np.ascontiguousarray(frames[f, y0:y1, x0:x1][None])
+        assert np.array_equal(got[b], orc.hist_rgb8(patch, bins)[0]), "box %d" % b
+
+
+def test_crop_division_is_correctly_rounded(orc):
+    """Pixel counts that are not powers of two: every bin is the IEEE single
+    division count / area (correctly rounded), and the counts add up to the
+    area."""
+    rng = np.random.default_rng(5)
+    frames = rng.integers(0, 256, size=(2, 31, 29, 3), dtype=np.uint8)
+    boxes = random_boxes(rng, 2, 31, 29, 40)
+    got = orc.hist_crops(frames, boxes, 8)
+    for b, (f, x0, y0, x1, y1) in enumerate(boxes):
+        area = (x1 - x0) * (y1 - y0)
+        cnt = histogramdd_reference(np.ascontiguousarray(frames[f, y0:y1, x0:x1][None]), 8)[0]
+        assert cnt.sum() == area
+        assert np.array_equal(got[b], cnt.astype(np.float32) / np.float32(area))
+
+
+def test_crop_outside_frame_is_rejected(orc):
+    frames = np.zeros((2, 4, 5, 3), np.uint8)
+    for bad in [(2, 0, 0, 1, 1), (0, 0, 0, 6, 1), (0, 3, 0, 3, 1), (0, 0, 2, 1, 5), (-1, 0, 0, 1, 1)]:
+        with pytest.raises(ValueError):
+            orc.hist_crops(frames, [bad], 8)

@@ -27,6 +27,8 @@ MUTANTS = {
     "tie_larger_j_first": ("return da < db || (da == db && ja < jb);", "return da < db || (da == db && ja > jb);"),
     "reverse_order": ("for (int32_t k = 0; k < d; ++k) {", "for (int32_t k = d - 1; k >= 0; --k) {"),
     "fma_contract": ("d2 = d2 + t * t;", "d2 = fma(t, t, d2);"),
+    "crop_area_off_by_one": ("(int64_t)(bx[3] - bx[1]) * (bx[4] - bx[2]);", "(int64_t)(bx[3] - bx[1] + 1) * (bx[4] - bx[2]);"),
+    "crop_skips_first_row": ("for (int32_t y = bx[2]; y < bx[4]; ++y) {", "for (int32_t y = bx[2] + 1; y < bx[4]; ++y) {"),
     "self_join_keeps_diagonal": ("for (int64_t j = self ? gi + 1 : 0; j < nS; ++j) {",
                                  "for (int64_t j = self ? gi : 0; j < nS; ++j) {"),
 }
@@ -35,6 +37,8 @@ PINS = [
     H.test_hand_example,
     lambda o: H.test_matches_histogramdd(o, 8, (7, 5)),
     H.test_mass_and_permutation,
+    H.test_crop_hand_example,
+    lambda o: H.test_crops_equal_histograms_of_sliced_patches(o, 8),
     J.test_hand_eps_join,
     J.test_pythagorean_closed_form,
     J.test_identity_and_bitwise_symmetry,
