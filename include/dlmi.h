@@ -116,6 +116,34 @@ dl_status dl_featurize_rgb8(dl_ctx* ctx, const uint8_t* patches, int64_t n,
                             int32_t h, int32_t w, int32_t bins,
                             float* out_hist, void* stream);
 
+/* A patch given as a bounding box over a frame (section "Iterator API for
+ * Patches": a patch refers to a region of an image): pixels x0 <= x < x1,
+ * y0 <= y < y1 of frame `frame`. */
+typedef struct dl_box {
+  int32_t frame;
+  int32_t x0, y0, x1, y1;
+} dl_box;
+
+/* Colour histograms of boxes cut from full frames (section "Visual ETL",
+ * Transformers, over the patches a detector's boxes define).
+ *   frames    device, nframes * height * width * 3 uint8, frame-major, pixels
+ *             row-major, channels R,G,B interleaved (HWC), contiguous.
+ *   boxes     device, nboxes boxes; each must lie inside its frame
+ *             (0 <= x0 < x1 <= width, 0 <= y0 < y1 <= height, 0 <= frame <
+ *             nframes).
+ *   out_hist  device, nboxes * bins^3 float32: as dl_featurize_rgb8 for the
+ *             box's pixels, each count divided by the box's pixel count
+ *             (correctly rounded, whatever the count).
+ * Errors: DL_ERR_INVALID for null pointers, bad sizes (height * width must be
+ * below 2^24), bins as for dl_featurize_rgb8, or any box outside its frame
+ * (checked on the GPU; such a box's row is all zero).  Synchronises
+ * `stream` (to report bad boxes). */
+dl_status dl_featurize_crops_rgb8(dl_ctx* ctx, const uint8_t* frames,
+                                  int64_t nframes, int32_t height,
+                                  int32_t width, const dl_box* boxes,
+                                  int64_t nboxes, int32_t bins,
+                                  float* out_hist, void* stream);
+
 /* -------------------------------------------------------- pair distances */
 
 /* Squared Euclidean distance in float64 for listed pairs, summed over
@@ -276,12 +304,35 @@ dl_status dl_store_create(dl_ctx* ctx, dl_mat base, dl_prec prec, void* mem, siz
 void dl_store_destroy(dl_store* store);
 int64_t dl_store_rows(const dl_store* store);
 
+/* Featurise and materialise in one pass (section "Visual ETL": transformers
+ * whose output is materialised for later queries): the colour histograms of
+ * n patches of h x w pixels (boxes == NULL; pixels as dl_featurize_rgb8) or
+ * of nboxes boxes over nframes frames of h x w pixels (pixels and boxes as
+ * dl_featurize_crops_rgb8) are written to out_hist (device, rows x bins^3
+ * float32) and, from the same LDS counts without reading them back, the
+ * store's operand copy and statistics into `mem` (dl_store_bytes(rows,
+ * bins^3, prec) bytes).  The store borrows out_hist as its float32 rows.
+ * Same histograms as the featurise calls; same store as dl_store_create on
+ * out_hist.  Errors as those calls.  Synchronises `stream`. */
+dl_status dl_store_featurize_rgb8(dl_ctx* ctx, const uint8_t* pixels,
+                                  int64_t n, int32_t h, int32_t w,
+                                  const dl_box* boxes, int64_t nboxes,
+                                  int32_t bins, dl_prec prec, float* out_hist,
+                                  void* mem, size_t bytes, dl_store** out,
+                                  void* stream);
+
 /* The eps-join and top-k join of R against a store (S = the store's rows,
  * operand format = the store's).  Same semantics, outputs and errors as
  * dl_join_eps / dl_join_topk with self_join = 0. */
 size_t dl_join_eps_store_workspace(int64_t nR, const dl_store* store, int64_t max_candidates);
 dl_status dl_join_eps_store(dl_ctx* ctx, dl_mat R, const dl_store* store, double eps, void* ws,
                             size_t ws_bytes, dl_pairs* out, void* stream);
+/* The eps self-join of a store's rows (i < j; query q4's deduplication),
+ * using the store's operand copy for both sides (no prep pass).  Same
+ * semantics, outputs and errors as dl_join_eps with self_join = 1. */
+size_t dl_join_eps_store_self_workspace(const dl_store* store, int64_t max_candidates);
+dl_status dl_join_eps_store_self(dl_ctx* ctx, const dl_store* store, double eps, void* ws, size_t ws_bytes,
+                                 dl_pairs* out, void* stream);
 size_t dl_join_topk_store_workspace(int64_t nR, const dl_store* store, int32_t k, int32_t band_cap);
 dl_status dl_join_topk_store(dl_ctx* ctx, dl_mat R, const dl_store* store, int32_t k, int32_t band_cap,
                              void* ws, size_t ws_bytes, uint32_t* out_j, float* out_dist,

@@ -29,6 +29,11 @@ class dl_pairs(ctypes.Structure):
                 ("ties", ctypes.c_int64)]
 
 
+class dl_box(ctypes.Structure):
+    _fields_ = [("frame", ctypes.c_int32), ("x0", ctypes.c_int32), ("y0", ctypes.c_int32), ("x1", ctypes.c_int32),
+                ("y1", ctypes.c_int32)]
+
+
 class dl_index_info(ctypes.Structure):
     _fields_ = [("tiles_total", ctypes.c_int64), ("tiles_computed", ctypes.c_int64), ("pivots", ctypes.c_int32)]
 
@@ -76,6 +81,7 @@ SIGNATURES = {
     "dl_set_timing": (ctypes.c_int, [P, ctypes.c_int]),
     "dl_get_timing": (ctypes.c_int, [P, P, P, ctypes.c_int]),
     "dl_featurize_rgb8": (ctypes.c_int, [P, P, i64, i32, i32, i32, P, P]),
+    "dl_featurize_crops_rgb8": (ctypes.c_int, [P, P, i64, i32, i32, P, i64, i32, P, P]),
     "dl_pair_d2": (ctypes.c_int, [P, dl_mat, dl_mat, P, P, i64, P, P]),
     "dl_join_eps_workspace": (sz, [i64, i64, i32, ctypes.c_int, ctypes.c_int, i64]),
     "dl_join_eps": (ctypes.c_int, [P, dl_mat, dl_mat, ctypes.c_int, f64, ctypes.c_int, P, sz,
@@ -95,6 +101,10 @@ SIGNATURES = {
     "dl_store_rows": (i64, [P]),
     "dl_join_eps_store_workspace": (sz, [i64, P, i64]),
     "dl_join_eps_store": (ctypes.c_int, [P, dl_mat, P, f64, P, sz, ctypes.POINTER(dl_pairs), P]),
+    "dl_store_featurize_rgb8": (ctypes.c_int, [P, P, i64, i32, i32, P, i64, i32, ctypes.c_int, P, P, sz,
+                                               ctypes.POINTER(P), P]),
+    "dl_join_eps_store_self_workspace": (sz, [P, i64]),
+    "dl_join_eps_store_self": (ctypes.c_int, [P, P, f64, P, sz, ctypes.POINTER(dl_pairs), P]),
     "dl_join_topk_store_workspace": (sz, [i64, P, i32, i32]),
     "dl_join_topk_store": (ctypes.c_int, [P, dl_mat, P, i32, i32, P, sz, P, P, ctypes.POINTER(dl_topk_info), P]),
     "dl_server_create": (ctypes.c_int, [ctypes.c_int, P, ctypes.POINTER(dl_server_config), P, sz, ctypes.POINTER(P)]),

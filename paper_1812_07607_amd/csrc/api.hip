@@ -12,7 +12,13 @@
 namespace dl {
 // featurize.hip
 hipError_t launch_hist_rgb8(const uint8_t*, int64_t, int32_t, int32_t, int32_t, float*, hipStream_t, int);
+hipError_t launch_hist_crops(const uint8_t*, int64_t, int32_t, int32_t, const dl_box*, int64_t, int32_t, float*, int*,
+                             hipStream_t, int);
+hipError_t launch_hist_prep(const uint8_t*, int64_t, int32_t, int32_t, const dl_box*, int64_t, int32_t, float*, int*,
+                            dl_prec, const Prep&, RelStats*, hipStream_t, int);
 // prep.hip
+hipError_t launch_stats_init(RelStats*, hipStream_t);
+hipError_t launch_stats_reduce(const Prep&, int64_t, RelStats*, hipStream_t, int);
 hipError_t launch_prep(const float*, int64_t, int32_t, int64_t, dl_prec, const Prep&, RelStats*, hipStream_t, int,
                        const uint32_t* perm = nullptr);
 hipError_t launch_threshold(const Prep&, int64_t, const RelStats*, int, double, const double*, float*, float*, int*,
@@ -26,15 +32,19 @@ namespace dl {
 hipError_t launch_cand_eps(dl_prec, CandParams, hipStream_t, int);
 hipError_t launch_cand_list(dl_prec, CandParams, hipStream_t, int);
 hipError_t launch_cand_mark(dl_prec, CandParams, hipStream_t, int);
+hipError_t launch_cand_nearest(dl_prec, CandParams, hipStream_t, int);
 // index.hip
 hipError_t launch_gather_rows(const float*, int64_t, int64_t, int64_t, int, float*, hipStream_t, int);
-hipError_t launch_pivot_keys(const uint32_t*, int64_t, int64_t, int, unsigned long long*, float*, hipStream_t, int);
+hipError_t launch_pivot_keys(const unsigned long long*, int64_t, int64_t, int, unsigned long long*, float*,
+                             hipStream_t, int);
 hipError_t launch_block_balls(const float*, int64_t, const uint32_t*, int64_t, int, double, float*, double*,
                               hipStream_t);
 hipError_t launch_survive(const uint32_t*, int64_t, const uint32_t*, int64_t, int64_t, int64_t, int, uint32_t*,
-                          int64_t, uint32_t*, hipStream_t);
-hipError_t launch_tile_list(const uint32_t*, int64_t, int64_t, const uint32_t*, uint2*, unsigned long long*,
-                            hipStream_t);
+                          int64_t, hipStream_t);
+hipError_t launch_group_count(const uint32_t*, int64_t, int64_t, int64_t, int64_t, uint32_t*, hipStream_t, int);
+hipError_t launch_group_list(const uint32_t*, int64_t, int64_t, int64_t, int64_t, const uint32_t*, uint2*,
+                             unsigned long long*, hipStream_t, int);
+int cand_group_rows(int64_t qld, int64_t nTR);
 // sort.hip
 hipError_t launch_exclusive_scan(const uint32_t*, int64_t, uint32_t*, uint32_t*, hipStream_t);
 int64_t scan_scratch_words(int64_t);
@@ -116,13 +126,18 @@ struct EpsLayout {
 // s_ext: the S side (operand copy and statistics) comes from a store and is
 // not carved from the workspace.
 static EpsLayout layout_eps(void* ws, int64_t nR, int64_t nS, int d, dl_prec prec, bool self, int64_t cap,
-                            bool s_ext = false) {
+                            bool s_ext = false, bool r_ext = false) {
   EpsLayout L;
   Bump b(ws);
   L.cnt = b.take<Counters>(1);
   L.sr = b.take<RelStats>(1);
   L.ss = (self || s_ext) ? L.sr : b.take<RelStats>(1);
-  L.pr = carve_prep(b, nR, d, prec);
+  if (r_ext) {  // R's operand copy comes from a store: only its row count matters below
+    L.pr = Prep{};
+    L.pr.npad = round_up(nR < 1 ? 1 : nR, kTile);
+  } else {
+    L.pr = carve_prep(b, nR, d, prec);
+  }
   L.ps = (self || s_ext) ? L.pr : carve_prep(b, nS, d, prec);
   L.thr = b.take<float>(L.pr.npad);
   L.pex = b.take<int>(L.pr.npad);
@@ -422,6 +437,37 @@ dl_status dl_featurize_rgb8(dl_ctx* c, const uint8_t* patches, int64_t n, int32_
   return DL_OK;
 }
 
+static dl_status check_bins(dl_ctx* c, int32_t bins) {
+  if (bins < 1 || bins > 256 || 256 % bins != 0 || bins * bins * bins > 4096)
+    return fail(c, DL_ERR_INVALID, "bins = %d must divide 256 with bins^3 <= 4096", bins);
+  return DL_OK;
+}
+
+dl_status dl_featurize_crops_rgb8(dl_ctx* c, const uint8_t* frames, int64_t nframes, int32_t height, int32_t width,
+                                  const dl_box* boxes, int64_t nboxes, int32_t bins, float* out_hist, void* stream) {
+  if (!c) return DL_ERR_INVALID;
+  c->err.clear();
+  if (nframes < 0 || nboxes < 0) return fail(c, DL_ERR_INVALID, "negative count");
+  if (height < 1 || width < 1 || (int64_t)height * width >= (1 << 24))
+    return fail(c, DL_ERR_INVALID, "bad frame size %dx%d", height, width);
+  if (dl_status s = check_bins(c, bins)) return s;
+  if (nboxes > 0 && (!frames || !boxes || !out_hist)) return fail(c, DL_ERR_INVALID, "null pointer");
+  if (nboxes == 0) return DL_OK;
+  DL_HIP(c, hipSetDevice(c->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // bad-box flag: a plain store into the context's pinned host block
+  volatile int* bad = reinterpret_cast<volatile int*>(c->pinned + 30);
+  *bad = 0;
+  {
+    StageTimer t(c, 0, st);
+    DL_HIP(c, launch_hist_crops(frames, nframes, height, width, boxes, nboxes, bins, out_hist, (int*)bad, st,
+                                c->cu_count));
+  }
+  DL_HIP(c, hipStreamSynchronize(st));
+  if (*bad) return fail(c, DL_ERR_INVALID, "a box lies outside its frame (its histogram is all zero)");
+  return DL_OK;
+}
+
 dl_status dl_pair_d2(dl_ctx* c, dl_mat R, dl_mat S, const uint32_t* pi, const uint32_t* pj, int64_t m, double* out,
                      void* stream) {
   if (!c) return DL_ERR_INVALID;
@@ -475,8 +521,8 @@ static int retight_of(int k, int limit) {
   return x > limit ? limit : x;
 }
 
-size_t eps_workspace(int64_t nR, int64_t nS, int d, dl_prec prec, bool self, bool s_ext, int64_t cap) {
-  return layout_eps(nullptr, nR, nS, d, prec, self, cap, s_ext).bytes;
+size_t eps_workspace(int64_t nR, int64_t nS, int d, dl_prec prec, bool self, bool s_ext, int64_t cap, bool r_ext) {
+  return layout_eps(nullptr, nR, nS, d, prec, self, cap, s_ext, r_ext).bytes;
 }
 
 // E4M3 top-k pilot.  The E4M3 margin E_i (about 0.1 on unit vectors) is
@@ -505,25 +551,33 @@ size_t topk_workspace(int64_t nR, int64_t nS, int d, dl_prec prec, bool self, bo
 
 dl_status eps_core(dl_ctx* c, const EpsJob& J, void* ws, size_t ws_bytes, dl_pairs* out, hipStream_t st) {
   const dl_mat &R = J.R, &S = J.S;
-  const bool self = J.self, sx = J.ps_ext != nullptr;
+  const bool self = J.self, sx = J.ps_ext != nullptr, rx = J.pr_ext != nullptr;
   const dl_prec prec = J.prec;
   out->count = out->candidates = out->ties = 0;
   // candidate capacity from the workspace size
-  const size_t fixed = layout_eps(nullptr, R.n, S.n, R.d, prec, self, 1, sx).bytes;
+  const size_t fixed = layout_eps(nullptr, R.n, S.n, R.d, prec, self, 1, sx, rx).bytes;
   if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(c, DL_ERR_INVALID, "workspace is not 256-byte aligned");
   if (!ws || ws_bytes < fixed) {
-    c->required_ws = layout_eps(nullptr, R.n, S.n, R.d, prec, self, 1 << 20, sx).bytes;
+    c->required_ws = layout_eps(nullptr, R.n, S.n, R.d, prec, self, 1 << 20, sx, rx).bytes;
     return fail(c, DL_ERR_WORKSPACE, "workspace of %zu bytes below the minimum %zu", ws_bytes, fixed);
   }
-  const size_t per = layout_eps(nullptr, R.n, S.n, R.d, prec, self, 1 << 16, sx).bytes - fixed;
+  const size_t per = layout_eps(nullptr, R.n, S.n, R.d, prec, self, 1 << 16, sx, rx).bytes - fixed;
   int64_t cap = (int64_t)((double)(ws_bytes - fixed) / ((double)per / (1 << 16))) - 1024;
-  while (cap > 1 && layout_eps(nullptr, R.n, S.n, R.d, prec, self, cap, sx).bytes > ws_bytes) cap = cap * 63 / 64;
+  while (cap > 1 && layout_eps(nullptr, R.n, S.n, R.d, prec, self, cap, sx, rx).bytes > ws_bytes) cap = cap * 63 / 64;
   if (cap < 1) cap = 1;
   // the canonical ordering keeps per-row offsets in 32 bits
   if (cap > kMaxPairs) cap = kMaxPairs;
   if (R.n == 0 || S.n == 0) return DL_OK;
 
-  EpsLayout L = layout_eps(ws, R.n, S.n, R.d, prec, self, cap, sx);
+  EpsLayout L = layout_eps(ws, R.n, S.n, R.d, prec, self, cap, sx, rx);
+  if (rx) {
+    L.pr = *J.pr_ext;
+    L.sr = J.sr_ext;
+    if (self) {
+      L.ps = L.pr;
+      L.ss = L.sr;
+    }
+  }
   if (sx) {
     L.ps = *J.ps_ext;
     L.ss = J.ss_ext;
@@ -532,7 +586,7 @@ dl_status eps_core(dl_ctx* c, const EpsJob& J, void* ws, size_t ws_bytes, dl_pai
                      (int64_t)(sizeof(Counters) / 4));
   {
     StageTimer t(c, 1, st);
-    DL_HIP(c, launch_prep(R.data, R.n, R.d, R.ld, prec, L.pr, L.sr, st, c->cu_count));
+    if (!rx) DL_HIP(c, launch_prep(R.data, R.n, R.d, R.ld, prec, L.pr, L.sr, st, c->cu_count));
     if (!self && !sx) DL_HIP(c, launch_prep(S.data, S.n, S.d, S.ld, prec, L.ps, L.ss, st, c->cu_count));
     hipLaunchKernelGGL(input_gate_kernel, dim3(1), dim3(64), 0, st, L.sr, L.ss, &L.cnt->invalid);
     DL_HIP(c, launch_threshold(L.pr, R.n, L.ss, R.d, J.T, J.Trow, L.thr, nullptr, L.pex, nullptr, st));
@@ -766,16 +820,12 @@ static int64_t index_pivots(int64_t nS, int32_t want) {
   if (p > nS) p = nS;
   return p;
 }
-constexpr int64_t kAssignChunk = 1 << 17;  // rows per pivot-assignment call
-constexpr int32_t kAssignBand = 320;       // band entries per row of that top-1 join
-
 struct IndexLayout {
   uint32_t *permR, *permS;          // operand row -> row of R / S
   float* piv;                       // pivots (P x d)
-  uint32_t* cid;                    // nearest pivot of each row (one relation at a time)
-  float* cdist;
-  uint8_t* aws;                     // workspace of the assignment top-1 joins
-  size_t aws_bytes;
+  Prep ppiv;                        // their operand copy
+  RelStats* spiv;
+  unsigned long long* argkey;       // nearest pivot of each row (one relation at a time)
   unsigned long long *keys, *pk;    // ordering by pivot
   float *vals, *pv, *od;
   uint32_t *oi, *words;
@@ -785,7 +835,7 @@ struct IndexLayout {
   RelStats *scS, *scR;
   float *thrS, *thrR;
   uint32_t *m1, *m2, *surv, *cnt, *off, *sums;
-  int64_t m1w, m2w, sw;
+  int64_t m1w, m2w, sw, gm;
   uint2* tiles;
   unsigned long long* ntiles;
   size_t bytes;
@@ -800,11 +850,9 @@ static IndexLayout layout_index(void* base, int64_t nR, int64_t nS, int d, dl_pr
   X.permR = b.take<uint32_t>(nR);
   X.permS = self ? X.permR : b.take<uint32_t>(nS);
   X.piv = b.take<float>(P * (int64_t)d);
-  X.cid = b.take<uint32_t>(n);
-  X.cdist = b.take<float>(n);
-  const int64_t chunk = n < kAssignChunk ? n : kAssignChunk;
-  X.aws_bytes = topk_workspace(chunk, P, d, DL_BF16, false, false, 1, kAssignBand, cu);
-  X.aws = b.take<uint8_t>((int64_t)X.aws_bytes);
+  X.ppiv = carve_prep(b, P, d, prec);
+  X.spiv = b.take<RelStats>(1);
+  X.argkey = b.take<unsigned long long>(n);
   X.keys = b.take<unsigned long long>(n);
   X.pk = b.take<unsigned long long>(n);
   X.vals = b.take<float>(n);
@@ -838,9 +886,11 @@ static IndexLayout layout_index(void* base, int64_t nR, int64_t nS, int d, dl_pr
   }
   X.sw = (nTS + 31) / 32;
   X.surv = b.take<uint32_t>(nTR * X.sw);
-  X.cnt = b.take<uint32_t>(nTR + 1);
-  X.off = b.take<uint32_t>(nTR + 1);
-  X.sums = b.take<uint32_t>(scan_scratch_words(nTR + 1) + 1);
+  X.gm = cand_group_rows(dpad_of(d, prec) * elem_bytes(prec), nTR);
+  const int64_t ncnt = (nTR + X.gm - 1) / X.gm * nTS + 1;  // (group, column tile) counts and the total
+  X.cnt = b.take<uint32_t>(ncnt);
+  X.off = b.take<uint32_t>(ncnt);
+  X.sums = b.take<uint32_t>(scan_scratch_words(ncnt) + 1);
   X.tiles = b.take<uint2>(self ? nTR * (nTR + 1) / 2 : nTR * nTS);
   X.ntiles = b.take<unsigned long long>(1);
   X.bytes = round_up((int64_t)b.off, 256);
@@ -862,20 +912,27 @@ size_t eps_indexed_workspace(int64_t nR, int64_t nS, int d, dl_prec prec, bool s
 }
 
 // Orders the rows of X (n x d) by nearest pivot: perm[q] = the q-th row in
-// (pivot, row) order.
-static dl_status order_by_pivot(dl_ctx* c, const dl_mat& X, const IndexLayout& I, int64_t P, uint32_t* perm,
-                                hipStream_t st) {
-  const dl_mat piv{I.piv, P, X.d, X.d};
-  for (int64_t r0 = 0; r0 < X.n; r0 += kAssignChunk) {
-    dl_mat part = X;
-    part.data = X.data + r0 * X.ld;
-    part.n = X.n - r0 < kAssignChunk ? X.n - r0 : kAssignChunk;
-    const TopkJob J{part, piv, false, false, DL_BF16, nullptr, nullptr, 1, kAssignBand};
-    const dl_status s = topk_core(c, J, I.aws, I.aws_bytes, I.cid + r0, I.cdist + r0, nullptr, st);
-    if (s != DL_OK) return s;
-  }
+// (pivot, row) order.  PX, sX: room for X's operand copy (in row order), used
+// by the nearest pass only.
+static dl_status order_by_pivot(dl_ctx* c, const dl_mat& X, const IndexLayout& I, int64_t P, dl_prec prec,
+                                const Prep& PX, RelStats* sX, uint32_t* perm, hipStream_t st) {
+  DL_HIP(c, launch_prep(X.data, X.n, X.d, X.ld, prec, PX, sX, st, c->cu_count));
+  hipLaunchKernelGGL(zero_words_kernel, dim3(256), dim3(256), 0, st, reinterpret_cast<uint32_t*>(I.argkey),
+                     2 * X.n);
+  CandParams q{};
+  q.qa = static_cast<const uint8_t*>(PX.q);
+  q.qb = static_cast<const uint8_t*>(I.ppiv.q);
+  q.qld = PX.qld;
+  q.nchunks = (int)(PX.qld / kChunkBytes);
+  q.hb = I.ppiv.h;
+  q.sexa = PX.sexp;
+  q.sexb = I.ppiv.sexp;
+  q.nR = X.n;
+  q.nS = P;
+  q.argkey = I.argkey;
+  DL_HIP(c, launch_cand_nearest(prec, q, st, c->cu_count));
   const int bj = bits_for(X.n);
-  DL_HIP(c, launch_pivot_keys(I.cid, X.n, P, bj, I.keys, I.vals, st, c->cu_count));
+  DL_HIP(c, launch_pivot_keys(I.argkey, X.n, P, bj, I.keys, I.vals, st, c->cu_count));
   DL_HIP(c, row_sort_pairs(I.keys, I.vals, X.n, P, bj, I.pk, I.pv, I.words, X.n, I.oi, perm, I.od, st,
                            c->cu_count));
   return DL_OK;
@@ -945,16 +1002,12 @@ dl_status eps_indexed_core(dl_ctx* c, const EpsJob& J, double eps, int32_t pivot
 
   {
     StageTimer t(c, 6, st);
-    // pivots, nearest-pivot order of each relation
+    // pivots, nearest-pivot order of each relation (its operand copy in row
+    // order goes where the ordered copy will be)
     DL_HIP(c, launch_gather_rows(S.data, S.ld, S.n / P, P, d, I.piv, st, c->cu_count));
-    dl_status s = order_by_pivot(c, R, I, P, I.permR, st);
-    if (s == DL_OK && !self) s = order_by_pivot(c, S, I, P, I.permS, st);
-    // a pivot assignment that outgrew its band buffers costs the pruning,
-    // not the call: the plain join has the same result
-    if (s == DL_ERR_WORKSPACE) {
-      if (info) info->pivots = 0;
-      return eps_core(c, J, ws, ws_bytes, out, st);
-    }
+    DL_HIP(c, launch_prep(I.piv, P, d, d, prec, I.ppiv, I.spiv, st, c->cu_count));
+    dl_status s = order_by_pivot(c, R, I, P, prec, L.pr, L.sr, I.permR, st);
+    if (s == DL_OK && !self) s = order_by_pivot(c, S, I, P, prec, L.ps, L.ss, I.permS, st);
     if (s != DL_OK) return s;
   }
   hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(L.cnt),
@@ -978,10 +1031,12 @@ dl_status eps_indexed_core(dl_ctx* c, const EpsJob& J, double eps, int32_t pivot
                      &L.cnt->invalid, st);
     }
     if (s != DL_OK) return s;
-    hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, st, I.cnt + nTR, (int64_t)1);
-    DL_HIP(c, launch_survive(I.m1, I.m1w, I.m2, I.m2w, nTR, nTS, self ? 1 : 0, I.surv, I.sw, I.cnt, st));
-    DL_HIP(c, launch_exclusive_scan(I.cnt, nTR + 1, I.off, I.sums, st));
-    DL_HIP(c, launch_tile_list(I.surv, I.sw, nTR, I.off, I.tiles, I.ntiles, st));
+    const int64_t ncnt = (nTR + I.gm - 1) / I.gm * nTS;
+    hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, st, I.cnt + ncnt, (int64_t)1);
+    DL_HIP(c, launch_survive(I.m1, I.m1w, I.m2, I.m2w, nTR, nTS, self ? 1 : 0, I.surv, I.sw, st));
+    DL_HIP(c, launch_group_count(I.surv, I.sw, nTR, nTS, I.gm, I.cnt, st, c->cu_count));
+    DL_HIP(c, launch_exclusive_scan(I.cnt, ncnt + 1, I.off, I.sums, st));
+    DL_HIP(c, launch_group_list(I.surv, I.sw, nTR, nTS, I.gm, I.off, I.tiles, I.ntiles, st, c->cu_count));
   }
   {
     StageTimer t(c, 2, st);
@@ -1236,6 +1291,87 @@ dl_status dl_store_create(dl_ctx* c, dl_mat base, dl_prec prec, void* mem, size_
   }
   *out = S;
   return DL_OK;
+}
+
+dl_status dl_store_featurize_rgb8(dl_ctx* c, const uint8_t* pixels, int64_t n, int32_t h, int32_t w,
+                                  const dl_box* boxes, int64_t nboxes, int32_t bins, dl_prec prec, float* out_hist,
+                                  void* mem, size_t bytes, dl_store** out, void* stream) {
+  if (!c) return DL_ERR_INVALID;
+  c->err.clear();
+  if (!out) return fail(c, DL_ERR_INVALID, "null output handle");
+  *out = nullptr;
+  if (n < 0 || nboxes < 0) return fail(c, DL_ERR_INVALID, "negative count");
+  if (h < 1 || w < 1 || (int64_t)h * w >= (1 << 24)) return fail(c, DL_ERR_INVALID, "bad patch size %dx%d", h, w);
+  if (dl_status s = check_bins(c, bins)) return s;
+  if (!prec_ok(prec)) return fail(c, DL_ERR_INVALID, "unknown precision %d", (int)prec);
+  const int64_t rows = boxes ? nboxes : n;
+  const int d = bins * bins * bins;
+  if (rows >= (1ll << 31)) return fail(c, DL_ERR_INVALID, "%lld rows out of range", (long long)rows);
+  if (rows > 0 && (!pixels || !out_hist)) return fail(c, DL_ERR_INVALID, "null pointer");
+  const size_t need = store_bytes(rows, d, prec);
+  if (reinterpret_cast<uintptr_t>(mem) & 255) return fail(c, DL_ERR_INVALID, "store memory is not 256-byte aligned");
+  if (!mem || bytes < need) {
+    c->required_ws = need;
+    return fail(c, DL_ERR_WORKSPACE, "store memory of %zu bytes below the %zu needed", bytes, need);
+  }
+  DL_HIP(c, hipSetDevice(c->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  dl_store* S = new (std::nothrow) dl_store();
+  if (!S) return fail(c, DL_ERR_OOM, "host allocation failed");
+  Bump b(mem);
+  S->stats = b.take<RelStats>(1);
+  S->prep = carve_prep(b, rows, d, prec);
+  S->base = dl_mat{out_hist, rows, d, d};
+  S->prec = prec;
+  S->device = c->device;
+  volatile int* bad = reinterpret_cast<volatile int*>(c->pinned + 30);
+  *bad = 0;
+  hipError_t e;
+  {
+    StageTimer t(c, 0, st);
+    e = launch_stats_init(S->stats, st);
+    if (e == hipSuccess)
+      e = launch_hist_prep(pixels, n, h, w, boxes, rows, bins, out_hist, (int*)bad, prec, S->prep, S->stats, st,
+                         c->cu_count);
+    if (e == hipSuccess) e = launch_stats_reduce(S->prep, rows, S->stats, st, c->cu_count);
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(c->pinned + 12, S->stats, sizeof(RelStats), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->pinned + 20, S->stats, sizeof(RelStats), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    delete S;
+    return fail(c, DL_ERR_DEVICE, "featurise into store: %s", hipGetErrorString(e));
+  }
+  if (*bad) {
+    delete S;
+    return fail(c, DL_ERR_INVALID, "a box lies outside its frame");
+  }
+  if (dl_status badin = check_inputs(c)) {
+    delete S;
+    return badin;
+  }
+  *out = S;
+  return DL_OK;
+}
+
+size_t dl_join_eps_store_self_workspace(const dl_store* s, int64_t max_cand) {
+  if (!s || max_cand < 0) return 0;
+  return eps_workspace(s->base.n, s->base.n, s->base.d, s->prec, true, false, max_cand, true);
+}
+
+dl_status dl_join_eps_store_self(dl_ctx* c, const dl_store* store, double eps, void* ws, size_t ws_bytes,
+                                 dl_pairs* out, void* stream) {
+  if (!c) return DL_ERR_INVALID;
+  c->err.clear();
+  c->required_ws = 0;
+  if (!store) return fail(c, DL_ERR_INVALID, "null store");
+  if (std::isnan(eps) || eps < 0) return fail(c, DL_ERR_INVALID, "eps must be >= 0 (got %g)", eps);
+  if (!out || out->capacity < 0) return fail(c, DL_ERR_INVALID, "bad output struct");
+  if (out->capacity > 0 && (!out->i || !out->j || !out->dist)) return fail(c, DL_ERR_INVALID, "null output array");
+  DL_HIP(c, hipSetDevice(c->device));
+  EpsJob J{store->base, store->base, true, store->prec, nullptr, nullptr, threshold_from_eps(eps), nullptr,
+           &store->prep, store->stats};
+  return eps_core(c, J, ws, ws_bytes, out, static_cast<hipStream_t>(stream));
 }
 
 void dl_store_destroy(dl_store* s) { delete s; }

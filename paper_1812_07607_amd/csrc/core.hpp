@@ -26,6 +26,10 @@ struct EpsJob {
   RelStats* ss_ext;
   double T;
   const double* Trow;
+  // R's operand copy and statistics from a store (a store's self-join): no
+  // prep of R
+  const Prep* pr_ext;
+  RelStats* sr_ext;
 };
 
 struct TopkJob {
@@ -38,7 +42,8 @@ struct TopkJob {
   int band_cap;
 };
 
-size_t eps_workspace(int64_t nR, int64_t nS, int d, dl_prec prec, bool self, bool s_ext, int64_t cap);
+size_t eps_workspace(int64_t nR, int64_t nS, int d, dl_prec prec, bool self, bool s_ext, int64_t cap,
+                     bool r_ext = false);
 size_t topk_workspace(int64_t nR, int64_t nS, int d, dl_prec prec, bool self, bool s_ext, int k, int band_cap,
                       int cu);
 size_t store_bytes(int64_t n, int d, dl_prec prec);

@@ -5,9 +5,10 @@
 // Data" answers Euclidean threshold queries with a Ball-tree over the feature
 // vectors.  Here the index is one level of balls over 256-row blocks, built
 // on the GPU for the matrix-core tiles:
-//   1. every row is assigned to its nearest pivot (a strided sample of S),
-//      and the rows of each relation are ordered by pivot, so consecutive
-//      rows are close and a 256-row block is a tight cluster;
+//   1. every row is assigned to its nearest pivot (a strided sample of S) by
+//      a pass of the matrix-core kernel whose epilogue keeps each row's best
+//      column, and the rows of each relation are ordered by pivot, so
+//      consecutive rows are close and a 256-row block is a tight cluster;
 //   2. every block gets a ball: its float32 centroid c and a radius r that
 //      bounds |x - c| from above for each of its rows;
 //   3. a bound pass on the matrix cores tests every row a of R against every
@@ -18,8 +19,9 @@
 //      (tile of a, block) in a bitmap;
 //   4. a (row tile, column tile) pair is computed only if both directions are
 //      marked (rows of the R tile near the S block's ball, rows of the S
-//      tile near the R tile's ball); the survivors form a tile list that the
-//      candidate pass walks instead of the full grid.
+//      tile near the R tile's ball); the survivors form a tile list, in the
+//      full grid's walk order, that the candidate pass walks instead of the
+//      full grid.
 // Pruning is exact: a pair with d2 <= eps^2 always lies in a surviving tile,
 // and the candidates of surviving tiles get the usual exact recheck.
 #include "core.hpp"
@@ -37,11 +39,13 @@ __global__ void gather_rows_kernel(const float* __restrict__ X, int64_t ld, int6
 }
 
 // Sort keys (pivot << bj | row) of a relation's rows, for the row-bucketed
-// ordering (which is then a stable counting sort by pivot).
-__global__ void pivot_keys_kernel(const uint32_t* __restrict__ pivot, int64_t n, uint32_t npiv, int bj,
+// ordering (which is then a stable counting sort by pivot).  argkey: per row
+// the nearest pass's key, whose low word is the complement of the pivot.
+__global__ void pivot_keys_kernel(const unsigned long long* __restrict__ argkey, int64_t n, uint32_t npiv, int bj,
                                   unsigned long long* __restrict__ keys, float* __restrict__ vals) {
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t pv = pivot[t] < npiv ? pivot[t] : npiv - 1;  // any pivot is a valid bucket
+    const uint32_t c = 0xffffffffu - (uint32_t)(argkey[t] & 0xffffffffull);
+    const uint32_t pv = c < npiv ? c : npiv - 1;  // a row no pivot won (NaN input) goes to the last
     keys[t] = ((unsigned long long)pv << bj) | (unsigned long long)t;
     vals[t] = 0.0f;
   }
@@ -62,9 +66,21 @@ __global__ __launch_bounds__(256) void block_ball_kernel(const float* __restrict
   const int64_t b = blockIdx.x;
   const int64_t r0 = b * kTile;
   const int rows = (int)min((int64_t)kTile, n - r0);
+  __shared__ int64_t roff[kTile];  // the block's row offsets in X
+  for (int r = threadIdx.x; r < rows; r += blockDim.x) roff[r] = (int64_t)perm[r0 + r] * ld;
+  __syncthreads();
   for (int k = threadIdx.x; k < d; k += blockDim.x) {
+    // eight rows' loads in flight, added in row order
     double s = 0.0;
-    for (int r = 0; r < rows; ++r) s += (double)X[(int64_t)perm[r0 + r] * ld + k];
+    int r = 0;
+    for (; r + 8 <= rows; r += 8) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = X[roff[r + u] + k];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += (double)v[u];
+    }
+    for (; r < rows; ++r) s += (double)X[roff[r] + k];
     const float c = (float)(s / (double)rows);
     c_lds[k] = c;
     cent[b * (int64_t)d + k] = c;
@@ -74,7 +90,7 @@ __global__ __launch_bounds__(256) void block_ball_kernel(const float* __restrict
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double r2max = 0.0;
   for (int r = wave; r < rows; r += 4) {
-    const float* x = X + (int64_t)perm[r0 + r] * ld;
+    const float* x = X + roff[r];
     double s = 0.0;
     for (int k = lane; k < d; k += 64) {
       const double t = (double)x[k] - (double)c_lds[k];
@@ -98,15 +114,13 @@ __global__ __launch_bounds__(256) void block_ball_kernel(const float* __restrict
 // column tiles 32 w .. 32 w + 31 whose pair with ti is marked in both
 // directions: m1[ti][tj] (a row of tile ti near the ball of block tj) and
 // m2[tj][ti] (a row of tile tj near the ball of block ti).  A self-join keeps
-// tj >= ti only.  cnt[ti] = survivors of the row tile.
+// tj >= ti only.
 __global__ __launch_bounds__(256) void survive_kernel(const uint32_t* __restrict__ m1, int64_t m1w,
                                                       const uint32_t* __restrict__ m2, int64_t m2w, int64_t nTR,
-                                                      int64_t nTS, int self, uint32_t* __restrict__ surv, int64_t sw,
-                                                      uint32_t* __restrict__ cnt) {
+                                                      int64_t nTS, int self, uint32_t* __restrict__ surv, int64_t sw) {
   const int lane = threadIdx.x & 63;
   const int64_t ti = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   if (ti >= nTR) return;
-  uint32_t c = 0;
   for (int64_t w = lane; w < sw; w += 64) {
     uint32_t word = m1[ti * m1w + w];
     uint32_t keep = 0;
@@ -117,45 +131,44 @@ __global__ __launch_bounds__(256) void survive_kernel(const uint32_t* __restrict
       if ((m2[tj * m2w + (ti >> 5)] >> (ti & 31)) & 1u) keep |= 1u << bit;
     }
     surv[ti * sw + w] = keep;
-    c += (uint32_t)__popc(keep);
   }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
-  if (lane == 0) cnt[ti] = c;
 }
 
-// One wave per row tile: its survivors (ti, tj), tj ascending, at off[ti]...
-// in the tile list; the list length (off[nTR]) goes to *ntiles.
-__global__ __launch_bounds__(256) void tile_list_kernel(const uint32_t* __restrict__ surv, int64_t sw, int64_t nTR,
-                                                        const uint32_t* __restrict__ off, uint2* __restrict__ tiles,
-                                                        unsigned long long* __restrict__ ntiles) {
-  const int lane = threadIdx.x & 63;
-  const int64_t ti = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  if (ti > nTR) return;
-  if (ti == nTR) {
-    if (lane == 0) *ntiles = off[nTR];
-    return;
+// The tile list is ordered like the full grid's walk: groups of gm row tiles
+// (as many as keep their operand tiles in an XCD's L2), column tiles in
+// order within a group, the group's row tiles in order for each column tile;
+// consecutive workgroups then share row tiles while column tiles stream past.
+// One thread per (group, column tile): its survivors.
+__global__ void group_count_kernel(const uint32_t* __restrict__ surv, int64_t sw, int64_t nTR, int64_t nTS,
+                                   int64_t gm, uint32_t* __restrict__ cnt) {
+  const int64_t ng = (nTR + gm - 1) / gm;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ng * nTS;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t g = t / nTS, tj = t - g * nTS;
+    const int64_t t1 = min(nTR, (g + 1) * gm);
+    uint32_t c = 0;
+    for (int64_t ti = g * gm; ti < t1; ++ti) c += (surv[ti * sw + (tj >> 5)] >> (tj & 31)) & 1u;
+    cnt[t] = c;
   }
-  uint32_t base = off[ti];
-  for (int64_t w0 = 0; w0 < sw; w0 += 64) {
-    const int64_t w = w0 + lane;
-    uint32_t word = w < sw ? surv[ti * sw + w] : 0u;
-    // exclusive prefix of the popcounts across the wave
-    const uint32_t pc = (uint32_t)__popc(word);
-    uint32_t pre = pc;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t y = __shfl_up(pre, o, 64);
-      if (lane >= o) pre += y;
+}
+
+// Writes each (group, column tile)'s survivors at its offset; the list length
+// (off[ng * nTS]) goes to *ntiles.
+__global__ void group_list_kernel(const uint32_t* __restrict__ surv, int64_t sw, int64_t nTR, int64_t nTS, int64_t gm,
+                                  const uint32_t* __restrict__ off, uint2* __restrict__ tiles,
+                                  unsigned long long* __restrict__ ntiles) {
+  const int64_t ng = (nTR + gm - 1) / gm;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t <= ng * nTS;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    if (t == ng * nTS) {
+      *ntiles = off[t];
+      continue;
     }
-    const uint32_t total = __shfl(pre, 63, 64);
-    uint32_t at = base + pre - pc;
-    while (word) {
-      const int bit = __ffs(word) - 1;
-      word &= word - 1;
-      tiles[at++] = make_uint2((uint32_t)ti, (uint32_t)(w * 32 + bit));
-    }
-    base += total;
+    const int64_t g = t / nTS, tj = t - g * nTS;
+    const int64_t t1 = min(nTR, (g + 1) * gm);
+    uint32_t at = off[t];
+    for (int64_t ti = g * gm; ti < t1; ++ti)
+      if ((surv[ti * sw + (tj >> 5)] >> (tj & 31)) & 1u) tiles[at++] = make_uint2((uint32_t)ti, (uint32_t)tj);
   }
 }
 
@@ -169,12 +182,12 @@ hipError_t launch_gather_rows(const float* X, int64_t ld, int64_t stride, int64_
   return hipGetLastError();
 }
 
-hipError_t launch_pivot_keys(const uint32_t* pivot, int64_t n, int64_t npiv, int bj, unsigned long long* keys,
-                             float* vals, hipStream_t st, int cu) {
+hipError_t launch_pivot_keys(const unsigned long long* argkey, int64_t n, int64_t npiv, int bj,
+                             unsigned long long* keys, float* vals, hipStream_t st, int cu) {
   if (n == 0) return hipSuccess;
   int64_t g = (n + 255) / 256;
   if (g > (int64_t)cu * 8) g = (int64_t)cu * 8;
-  hipLaunchKernelGGL(pivot_keys_kernel, dim3((unsigned)g), dim3(256), 0, st, pivot, n, (uint32_t)npiv, bj, keys,
+  hipLaunchKernelGGL(pivot_keys_kernel, dim3((unsigned)g), dim3(256), 0, st, argkey, n, (uint32_t)npiv, bj, keys,
                      vals);
   return hipGetLastError();
 }
@@ -189,17 +202,30 @@ hipError_t launch_block_balls(const float* X, int64_t ld, const uint32_t* perm, 
 }
 
 hipError_t launch_survive(const uint32_t* m1, int64_t m1w, const uint32_t* m2, int64_t m2w, int64_t nTR, int64_t nTS,
-                          int self, uint32_t* surv, int64_t sw, uint32_t* cnt, hipStream_t st) {
+                          int self, uint32_t* surv, int64_t sw, hipStream_t st) {
   if (nTR == 0) return hipSuccess;
   hipLaunchKernelGGL(survive_kernel, dim3((unsigned)((nTR + 3) / 4)), dim3(256), 0, st, m1, m1w, m2, m2w, nTR, nTS,
-                     self, surv, sw, cnt);
+                     self, surv, sw);
   return hipGetLastError();
 }
 
-hipError_t launch_tile_list(const uint32_t* surv, int64_t sw, int64_t nTR, const uint32_t* off, uint2* tiles,
-                            unsigned long long* ntiles, hipStream_t st) {
-  hipLaunchKernelGGL(tile_list_kernel, dim3((unsigned)((nTR + 1 + 3) / 4)), dim3(256), 0, st, surv, sw, nTR, off,
-                     tiles, ntiles);
+hipError_t launch_group_count(const uint32_t* surv, int64_t sw, int64_t nTR, int64_t nTS, int64_t gm, uint32_t* cnt,
+                              hipStream_t st, int cu) {
+  const int64_t m = (nTR + gm - 1) / gm * nTS;
+  if (m == 0) return hipSuccess;
+  int64_t g = (m + 255) / 256;
+  if (g > (int64_t)cu * 16) g = (int64_t)cu * 16;
+  hipLaunchKernelGGL(group_count_kernel, dim3((unsigned)g), dim3(256), 0, st, surv, sw, nTR, nTS, gm, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_list(const uint32_t* surv, int64_t sw, int64_t nTR, int64_t nTS, int64_t gm,
+                             const uint32_t* off, uint2* tiles, unsigned long long* ntiles, hipStream_t st, int cu) {
+  const int64_t m = (nTR + gm - 1) / gm * nTS + 1;
+  int64_t g = (m + 255) / 256;
+  if (g > (int64_t)cu * 16) g = (int64_t)cu * 16;
+  hipLaunchKernelGGL(group_list_kernel, dim3((unsigned)g), dim3(256), 0, st, surv, sw, nTR, nTS, gm, off, tiles,
+                     ntiles);
   return hipGetLastError();
 }
 

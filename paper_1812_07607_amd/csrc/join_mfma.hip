@@ -91,8 +91,9 @@ __device__ inline int lds_off(int r, int c) {
 
 // eps: append candidates; band: top-k band; mark: the bound pass of the
 // index-pruned join (rows are block centroids, columns data rows; a hit sets
-// the block's bit for the data row's tile).
-enum : int { kModeEps = 0, kModeBand = 1, kModeMark = 2 };
+// the block's bit for the data row's tile); nearest: each row's column of
+// largest P~ (the pivot assignment of the index-pruned join).
+enum : int { kModeEps = 0, kModeBand = 1, kModeMark = 2, kModeNearest = 3 };
 
 // Waves that issue the operand transfers (waves w and w + 4 share a SIMD).
 // Fewer issuing waves leave more waves free of transfers to feed the matrix
@@ -305,7 +306,7 @@ __device__ inline void issue_side(const CandParams& p, int64_t ti, int64_t tj, c
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) - (kDmaWaves < 8 ? kDmaWaves : 0);
   const int e = 4 * fresh_lane();
   if (w == 0) lds_dma16(p.hb + tj * kTile + e, d.hb);
-  if constexpr (kMode != kModeBand)
+  if constexpr (kMode == kModeEps || kMode == kModeMark)
     if (w == 1) lds_dma16(p.thr + ti * kTile + e, d.thr);
   if constexpr (kPrec == DL_FP8) {
     if (w == 2) lds_dma16(p.sexa + ti * kTile + e, d.sa);
@@ -595,6 +596,52 @@ __device__ inline void epilogue_mark(const CandParams& p, int64_t ti, int64_t tj
   const uint32_t mine = lane == 0 ? w0 : lane == 1 ? w1 : lane == 2 ? w2 : w3;
   if (lane < 4 && mine)
     atomicOr(p.mark + tj * p.mark_words + ((ti * kTile + wm * kWaveM) >> 5) + lane, mine);
+}
+
+// Nearest epilogue (pivot assignment): per row the column of largest P~ =
+// a.b - |b|^2/2, i.e. of smallest distance (ties to the smaller column),
+// reduced over the 16 lanes that share the row, then folded into the row's
+// 64-bit key (order bits of P~, then the complement of the column) with one
+// atomic maximum per row and wave.  An approximate answer is fine here: the
+// assignment only orders rows, and the pruning it enables is exact anyway.
+__device__ inline void epilogue_nearest(const CandParams& p, int64_t ti, int64_t tj, const f32x4 (&acc)[8][4]) {
+  const int lane = fresh_lane(), wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wm = wave >> 2, wn = wave & 3;
+  const int lrow0 = wm * kWaveM + 4 * (lane >> 4);
+  const int lcol0 = wn * kWaveN + (lane & 15);
+  const int rrem = (int)min(p.nR - ti * kTile, (int64_t)kTile);
+  const int crem = (int)min(p.nS - tj * kTile, (int64_t)kTile);
+#pragma unroll
+  for (int mb = 0; mb < 8; ++mb) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      float best = -INFINITY;
+      uint32_t bc = 0xffffffffu;
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) {
+        const float v = acc[mb][nb][r];
+        if (lcol0 + nb * 16 < crem && v > best) {  // a NaN never wins
+          best = v;
+          bc = (uint32_t)(lcol0 + nb * 16);
+        }
+      }
+#pragma unroll
+      for (int o = 1; o < 16; o <<= 1) {
+        const float ov = __shfl_xor(best, o, 64);
+        const uint32_t oc = __shfl_xor(bc, o, 64);
+        if (ov > best || (ov == best && oc < bc)) {
+          best = ov;
+          bc = oc;
+        }
+      }
+      const int lr = lrow0 + mb * 16 + r;
+      if ((lane & 15) == 0 && lr < rrem && bc != 0xffffffffu) {
+        const unsigned long long key =
+            ((unsigned long long)order_key(best) << 32) | (0xffffffffull - (uint64_t)(tj * kTile + bc));
+        atomicMax(p.argkey + ti * kTile + lr, key);
+      }
+    }
+  }
 }
 
 constexpr int kSelPerLane = 8;  // entries per lane in the k-selection subset
@@ -1011,6 +1058,9 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
       if constexpr (kMark) {
         epilogue_mark(p, ti, tj, acc, side_thr[sbuf]);
         dirty = true;  // atomics to global memory
+      } else if constexpr (kMode == kModeNearest) {
+        epilogue_nearest(p, ti, tj, acc);
+        dirty = true;
       } else {
         dirty |= epilogue_eps<kStageP>(p, ti, tj, acc, side_thr[sbuf], lds_eq[wave], lds_eqp[kStageP ? wave : 0], eq);
       }
@@ -1101,6 +1151,8 @@ static int group_rows(int64_t qld, int64_t nTR) {
   return (int)gm;
 }
 
+int cand_group_rows(int64_t qld, int64_t nTR) { return group_rows(qld, nTR); }
+
 // Multiplier and shifts for udiv32 by d >= 1 (Granlund and Montgomery):
 // l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1, s1 = min(l, 1),
 // s2 = max(l - 1, 0); exact for every 32-bit dividend.
@@ -1126,19 +1178,25 @@ hipError_t launch_cand_list(dl_prec prec, CandParams p, hipStream_t st, int cu_c
   return launch_mode<kModeEps>(prec, p, dim3((unsigned)G), st);
 }
 
-static hipError_t launch_eps_like(dl_prec prec, CandParams p, hipStream_t st, int cu_count, bool mark);
+static hipError_t launch_eps_like(dl_prec prec, CandParams p, hipStream_t st, int cu_count, int mode);
 
 hipError_t launch_cand_mark(dl_prec prec, CandParams p, hipStream_t st, int cu_count) {
   p.tiles = nullptr;
-  return launch_eps_like(prec, p, st, cu_count, true);
+  return launch_eps_like(prec, p, st, cu_count, kModeMark);
+}
+
+hipError_t launch_cand_nearest(dl_prec prec, CandParams p, hipStream_t st, int cu_count) {
+  p.tiles = nullptr;
+  p.self_join = 0;
+  return launch_eps_like(prec, p, st, cu_count, kModeNearest);
 }
 
 hipError_t launch_cand_eps(dl_prec prec, CandParams p, hipStream_t st, int cu_count) {
   p.tiles = nullptr;
-  return launch_eps_like(prec, p, st, cu_count, false);
+  return launch_eps_like(prec, p, st, cu_count, kModeEps);
 }
 
-static hipError_t launch_eps_like(dl_prec prec, CandParams p, hipStream_t st, int cu_count, bool mark) {
+static hipError_t launch_eps_like(dl_prec prec, CandParams p, hipStream_t st, int cu_count, int mode) {
   p.nTR = (p.nR + kTile - 1) / kTile;
   p.nTS = (p.nS + kTile - 1) / kTile;
   if (p.nTR == 0 || p.nTS == 0) return hipSuccess;
@@ -1163,7 +1221,8 @@ static hipError_t launch_eps_like(dl_prec prec, CandParams p, hipStream_t st, in
   const int64_t need = (p.nlogical + 7) / 8 * 8;
   if (G > need) G = need;
   G = (G + 7) / 8 * 8;
-  if (mark) return launch_mode<kModeMark>(prec, p, dim3((unsigned)G), st);
+  if (mode == kModeMark) return launch_mode<kModeMark>(prec, p, dim3((unsigned)G), st);
+  if (mode == kModeNearest) return launch_mode<kModeNearest>(prec, p, dim3((unsigned)G), st);
   return launch_mode<kModeEps>(prec, p, dim3((unsigned)G), st);
 }
 

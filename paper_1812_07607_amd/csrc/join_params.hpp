@@ -57,6 +57,8 @@ struct CandParams {
   // mark mode: bit (tile tj, row i) at mark[tj * mark_words + i / 32]
   uint32_t* mark;
   int64_t mark_words;
+  // nearest mode: per row, the maximum of (order key of P~ << 32 | ~column)
+  unsigned long long* argkey;
 };
 
 // eps-join recheck (recheck.hip).

@@ -14,25 +14,9 @@
 // Paper: the Euclidean threshold predicate of image matching (section
 // "Derived Data") evaluated as |a|^2 + |b|^2 - 2 a.b on matrix cores; the
 // margin and the recheck that restore exactness are this library's design.
-#include "dl_internal.hpp"
+#include "prep_row.hpp"
 
 namespace dl {
-
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-__device__ inline float wave_max(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-  return v;
-}
-__device__ inline int wave_min(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-  return v;
-}
 
 // One wave per row; rows in [n, npad) get zero operands and zero statistics.
 // perm (nullable): operand row r holds row perm[r] of X.
@@ -49,47 +33,9 @@ __global__ __launch_bounds__(256) void prep_kernel(const float* __restrict__ X, 
   if (kPrec == DL_FP8 && real) {
     float amax = 0.0f;
     for (int k = lane; k < d; k += 64) amax = fmaxf(amax, fabsf(x[k]));
-    amax = wave_max(amax);
-    if (amax > 0.0f && amax <= 3.4e38f) {
-      // smallest s with amax <= 448 * 2^s, clamped to the E8M0 range
-      int s = ilogbf(amax) - 8;
-      while (amax > ldexpf(448.0f, s)) ++s;
-      while (s > -127 && amax <= ldexpf(448.0f, s - 1)) --s;
-      sexp = s < -127 ? -127 : (s > 127 ? 127 : s);
-    }
+    sexp = e4m3_row_scale(wave_max(amax));
   }
-  const float inv_scale = ldexpf(1.0f, -sexp), scale = ldexpf(1.0f, sexp);
-  double nrm2 = 0.0, qn2 = 0.0, r2 = 0.0;
-  int qlsb = kLsbNone, mlsb = kLsbNone, bad = 0;
-  uint8_t* qrow = reinterpret_cast<uint8_t*>(P.q) + row * P.qld;
-  // one element: the operand copy and the row statistics (in index order per
-  // lane)
-  auto element = [&](float v, int64_t k) {
-    if (!isfinite(v)) { bad++; v = 0.0f; }
-    float qv;
-    if (kPrec == DL_FP32) {
-      qv = v;
-      reinterpret_cast<float*>(qrow)[k] = v;
-    } else if (kPrec == DL_BF16) {
-      uint16_t c = enc_bf16(v);
-      qv = dec_bf16(c);
-      reinterpret_cast<uint16_t*>(qrow)[k] = c;
-    } else if (kPrec == DL_FP16) {
-      uint16_t c = enc_f16(v);
-      qv = dec_f16(c);
-      reinterpret_cast<uint16_t*>(qrow)[k] = c;
-    } else {
-      uint8_t c = enc_e4m3(v * inv_scale);
-      qv = dec_e4m3(c) * scale;  // exact: power-of-two scale of a normal value
-      qrow[k] = c;
-    }
-    const double dv = v, dq = qv, dr = dv - dq;  // exact in float64
-    nrm2 += dv * dv;
-    qn2 += dq * dq;
-    r2 += dr * dr;
-    qlsb = min(qlsb, lsb_exp(qv));
-    mlsb = min(mlsb, lsb_exp(v));
-  };
+  RowPrep<kPrec> rp(P, row, sexp);
   constexpr bool k16 = kPrec == DL_BF16 || kPrec == DL_FP16;
   const bool vec = k16 && real && d == dpad && (d & 511) == 0 && (ld & 3) == 0 &&
                    (reinterpret_cast<uintptr_t>(X) & 15) == 0;
@@ -107,19 +53,14 @@ __global__ __launch_bounds__(256) void prep_kernel(const float* __restrict__ X, 
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         float t = v[u];
-        if (!isfinite(t)) { bad++; t = 0.0f; }
+        if (!isfinite(t)) { rp.bad++; t = 0.0f; }
         const uint16_t c = kPrec == DL_BF16 ? enc_bf16(t) : enc_f16(t);
         const float qv = kPrec == DL_BF16 ? dec_bf16(c) : dec_f16(c);
         if (u & 1) w[u >> 1] |= (uint32_t)c << 16;
         else w[u >> 1] = c;
-        const double dv = t, dq = qv, dr = dv - dq;  // exact in float64
-        nrm2 += dv * dv;
-        qn2 += dq * dq;
-        r2 += dr * dr;
-        qlsb = min(qlsb, lsb_exp(qv));
-        mlsb = min(mlsb, lsb_exp(t));
+        rp.stats(t, qv);
       }
-      *reinterpret_cast<uint4*>(qrow + 2 * k) = make_uint4(w[0], w[1], w[2], w[3]);
+      *reinterpret_cast<uint4*>(rp.qrow + 2 * k) = make_uint4(w[0], w[1], w[2], w[3]);
     }
   } else if (real) {
     // eight of the row's loads in flight per lane (clamped into the row,
@@ -135,34 +76,13 @@ __global__ __launch_bounds__(256) void prep_kernel(const float* __restrict__ X, 
         v[u] = kk < d ? t : 0.0f;
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) element(v[u], k + 64 * u);
+      for (int u = 0; u < 8; ++u) rp.element(v[u], k + 64 * u);
     }
-    for (; k < dpad; k += 64) element(k < d ? x[k] : 0.0f, k);
+    for (; k < dpad; k += 64) rp.element(k < d ? x[k] : 0.0f, k);
   } else {
-    for (int64_t k = lane; k < dpad; k += 64) element(0.0f, k);
+    for (int64_t k = lane; k < dpad; k += 64) rp.element(0.0f, k);
   }
-  nrm2 = wave_sum(nrm2);
-  qn2 = wave_sum(qn2);
-  r2 = wave_sum(r2);
-  qlsb = wave_min(qlsb);
-  mlsb = wave_min(mlsb);
-  bad = (int)wave_sum((double)bad);
-  if (lane == 0) {
-    // float64 sums of at most dpad exact squares: relative error <= gamma_dpad
-    const double g = gamma_n((double)dpad + 2.0, 0x1p-53);
-    const float h = ((float)nrm2) * 0.5f;
-    P.nrm2[row] = nrm2;
-    P.h[row] = h;
-    P.qnorm[row] = f32_up(sqrt(qn2 * (1.0 + g)) * (1.0 + 0x1p-50));
-    P.rho[row] = f32_up(sqrt(r2 * (1.0 + g)) * (1.0 + 0x1p-50));
-    P.xnorm[row] = f32_up(sqrt(nrm2 * (1.0 + g)) * (1.0 + 0x1p-50));
-    P.dh[row] = f32_up((fabs(nrm2 * 0.5 - (double)h) + g * nrm2) * (1.0 + 0x1p-50));
-    P.qlsb[row] = qlsb;
-    P.hlsb[row] = lsb_exp(h);
-    P.mlsb[row] = mlsb;
-    P.sexp[row] = sexp;
-    if (bad && real) atomicAdd(&rs->nonfinite, bad);
-  }
+  rp.finish(P, row, dpad, real, rs, lane);
 }
 
 __global__ void stats_init_kernel(RelStats* rs) {
@@ -314,6 +234,21 @@ hipError_t launch_prep(const float* X, int64_t n, int32_t d, int64_t ld, dl_prec
     case DL_FP16: hipLaunchKernelGGL(prep_kernel<DL_FP16>, grid, block, 0, st, X, n, d, ld, dpad, P, rs, perm); break;
     case DL_FP8: hipLaunchKernelGGL(prep_kernel<DL_FP8>, grid, block, 0, st, X, n, d, ld, dpad, P, rs, perm); break;
   }
+  if (n > 0) {
+    int64_t blocks = (n + 1023) / 1024;
+    if (blocks > (int64_t)cu_count) blocks = (int64_t)cu_count;
+    hipLaunchKernelGGL(stats_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, st, P, n, rs);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_stats_init(RelStats* rs, hipStream_t st) {
+  hipLaunchKernelGGL(stats_init_kernel, dim3(1), dim3(64), 0, st, rs);
+  return hipGetLastError();
+}
+
+// The relation maxima of rows [0, n) of P (after launch_stats_init).
+hipError_t launch_stats_reduce(const Prep& P, int64_t n, RelStats* rs, hipStream_t st, int cu_count) {
   if (n > 0) {
     int64_t blocks = (n + 1023) / 1024;
     if (blocks > (int64_t)cu_count) blocks = (int64_t)cu_count;

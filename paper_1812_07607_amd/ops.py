@@ -98,6 +98,25 @@ def featurize_rgb8(patches: torch.Tensor, bins: int = 8, out: torch.Tensor | Non
     return out
 
 
+def featurize_crops_rgb8(frames: torch.Tensor, boxes: torch.Tensor, bins: int = 8, out: torch.Tensor | None = None,
+                         stream=None) -> torch.Tensor:
+    """Colour histograms of boxes (int32 (m, 5): frame, x0, y0, x1, y1) over
+    uint8 (nframes, height, width, 3) frames."""
+    if frames.dtype != torch.uint8 or frames.dim() != 4 or frames.shape[3] != 3 or not frames.is_cuda:
+        raise TypeError("frames must be a (nframes, height, width, 3) uint8 CUDA tensor")
+    frames = frames.contiguous()
+    boxes = boxes.to(device=frames.device, dtype=torch.int32).contiguous().reshape(-1, 5)
+    nf, hh, ww, _ = frames.shape
+    m = boxes.shape[0]
+    if out is None:
+        out = torch.empty((m, bins ** 3), dtype=torch.float32, device=frames.device)
+    c = context(frames.device.index)
+    c.check(c.L.dl_featurize_crops_rgb8(c.h, ctypes.c_void_p(frames.data_ptr()), nf, hh, ww,
+                                        ctypes.c_void_p(boxes.data_ptr()), m, bins, ctypes.c_void_p(out.data_ptr()),
+                                        _stream_ptr(stream)))
+    return out
+
+
 # ---------------------------------------------------------------- distances
 def pair_d2(R: torch.Tensor, S: torch.Tensor, pi: torch.Tensor, pj: torch.Tensor, stream=None) -> torch.Tensor:
     """Canonical float64 squared distances of listed pairs."""
@@ -306,6 +325,38 @@ class Store:
                                        nbytes, ctypes.byref(h), _stream_ptr(stream)))
         self.h = h
 
+    @classmethod
+    def featurize(cls, pixels: torch.Tensor, bins: int = 8, prec: str = "bf16", boxes: torch.Tensor | None = None,
+                  stream=None) -> "Store":
+        """Featurise and materialise in one pass: the colour histograms of
+        uint8 (n, h, w, 3) patches, or of boxes (int32 (m, 5)) over uint8
+        (nframes, h, w, 3) frames, become the store's float32 rows (kept in
+        self.base) and its operand copy, without reading the rows back."""
+        if pixels.dtype != torch.uint8 or pixels.dim() != 4 or pixels.shape[3] != 3 or not pixels.is_cuda:
+            raise TypeError("pixels must be a (n, h, w, 3) uint8 CUDA tensor")
+        self = cls.__new__(cls)
+        self.c = context(pixels.device.index)
+        L = self.c.L
+        pixels = pixels.contiguous()
+        n, h, w, _ = pixels.shape
+        bptr, nb = None, 0
+        if boxes is not None:
+            boxes = boxes.to(device=pixels.device, dtype=torch.int32).contiguous().reshape(-1, 5)
+            bptr, nb = ctypes.c_void_p(boxes.data_ptr()), boxes.shape[0]
+        rows = nb if boxes is not None else n
+        self.base = torch.empty((rows, bins ** 3), dtype=torch.float32, device=pixels.device)
+        self.prec = prec
+        self.n, self.d = self.base.shape
+        nbytes = L.dl_store_bytes(self.n, self.d, _lib.PREC[prec])
+        self.mem = torch.empty(int(nbytes), dtype=torch.uint8, device=pixels.device)
+        hd = ctypes.c_void_p()
+        self.c.check(L.dl_store_featurize_rgb8(self.c.h, ctypes.c_void_p(pixels.data_ptr()), n, h, w, bptr, nb, bins,
+                                               _lib.PREC[prec], ctypes.c_void_p(self.base.data_ptr()),
+                                               ctypes.c_void_p(self.mem.data_ptr()), nbytes, ctypes.byref(hd),
+                                               _stream_ptr(stream)))
+        self.h = hd
+        return self
+
     def __del__(self):
         try:
             if getattr(self, "h", None):
@@ -313,6 +364,37 @@ class Store:
                 self.h = None
         except Exception:
             pass
+
+    def join_eps_self(self, eps: float, max_candidates: int | None = None, stream=None,
+                      workspace: Workspace | None = None, out: tuple | None = None) -> EpsResult:
+        """eps self-join (i < j) of the store's rows on its operand copy."""
+        c, L = self.c, self.c.L
+        ws = workspace or _workspace(self.base.device)
+        if max_candidates is None:
+            max_candidates = max(1 << 20, 4 * self.n)
+        cap = out[0].numel() if out is not None else max(1 << 16, 2 * self.n)
+        for _ in range(8):
+            buf = ws.get(L.dl_join_eps_store_self_workspace(self.h, max_candidates))
+            if out is not None and out[0].numel() >= cap:
+                oi, oj, od = out
+            else:
+                oi = torch.empty(cap, dtype=torch.int32, device=self.base.device)
+                oj = torch.empty(cap, dtype=torch.int32, device=self.base.device)
+                od = torch.empty(cap, dtype=torch.float32, device=self.base.device)
+            pr = _lib.dl_pairs(oi.data_ptr(), oj.data_ptr(), od.data_ptr(), cap, 0, 0, 0)
+            st = L.dl_join_eps_store_self(c.h, self.h, float(eps), ctypes.c_void_p(buf.data_ptr()), buf.numel(),
+                                          ctypes.byref(pr), _stream_ptr(stream))
+            if st == _lib.DL_ERR_WORKSPACE:
+                max_candidates = max(2 * max_candidates, int(pr.candidates * 1.25) + 1024)
+                continue
+            if st == _lib.DL_ERR_CAPACITY:
+                cap = int(pr.count)
+                out = None
+                continue
+            c.check(st)
+            m = int(pr.count)
+            return EpsResult(oi[:m], oj[:m], od[:m], m, int(pr.candidates), int(pr.ties))
+        raise RuntimeError("join_eps_self (store) did not converge")
 
     def join_eps(self, R: torch.Tensor, eps: float, max_candidates: int | None = None, stream=None,
                  workspace: Workspace | None = None) -> EpsResult:

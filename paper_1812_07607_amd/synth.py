@@ -80,6 +80,49 @@ def patches_palette(n, h=32, w=32, n_colours=16, sigma=20.0, seed=202):
     return out, colour
 
 
+def frames_with_boxes(nframes, height, width, nboxes, n_colours=16, sigma=20.0, min_side=4, max_side=96,
+                      seed=606):
+    """Frames with coloured objects, and bounding boxes over them.
+
+    Each frame is uniform noise with up to 12 axis-aligned rectangles, each
+    filled with one of n_colours base colours (drawn once from the seed) plus
+    N(0, sigma^2) noise per pixel and channel (rounded, clipped to 0..255).
+    Each box covers one object, cut at the frame's border, or, one time in
+    four, a random region; sides are log-uniform in [min_side, max_side], so
+    pixel counts are ragged and mostly not powers of two.
+
+    Returns (frames uint8 (nframes, height, width, 3), boxes int32 (nboxes, 5)
+    as (frame, x0, y0, x1, y1) with x0 <= x < x1, y0 <= y < y1).
+    """
+    rng = _rng(seed, 70)
+    base = rng.integers(0, 256, size=(n_colours, 3)).astype(np.float32)
+    frames = rng.integers(0, 256, size=(nframes, height, width, 3), dtype=np.uint8)
+    hi = min(max_side, height, width)
+    lo = min(min_side, hi)
+
+    def side():
+        return int(np.clip(np.rint(np.exp(rng.uniform(np.log(lo), np.log(hi)))), lo, hi))
+
+    objects = []
+    for f in range(nframes):
+        for _ in range(int(rng.integers(1, 13))):
+            w, h = side(), side()
+            x0, y0 = int(rng.integers(0, width - w + 1)), int(rng.integers(0, height - h + 1))
+            z = base[int(rng.integers(0, n_colours))] + sigma * rng.standard_normal((h, w, 3), dtype=np.float32)
+            frames[f, y0:y0 + h, x0:x0 + w] = np.clip(np.rint(z), 0, 255).astype(np.uint8)
+            objects.append((f, x0, y0, x0 + w, y0 + h))
+    boxes = np.empty((nboxes, 5), np.int32)
+    for b in range(nboxes):
+        if objects and rng.random() < 0.75:
+            boxes[b] = objects[int(rng.integers(0, len(objects)))]
+        else:
+            w, h = side(), side()
+            f = int(rng.integers(0, nframes))
+            x0, y0 = int(rng.integers(0, width - w + 1)), int(rng.integers(0, height - h + 1))
+            boxes[b] = (f, x0, y0, x0 + w, y0 + h)
+    return frames, boxes
+
+
 def patches_uniform(n, h, w, seed):
     """n patches of independent uniform uint8 pixels."""
     return _rng(seed, 2).integers(0, 256, size=(n, h, w, 3), dtype=np.uint8)
