@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-store", type=int, default=8000000, help="rows of the serving store")
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="open-loop seconds per offered rate")
+    ap.add_argument("--crossover", action="store_true",
+                    help="instead of the headline step, sweep the histogram self-join size and time the CPU oracle "
+                         "against the GPU join (device-resident and with the host transfers) (one JSON line)")
     ap.add_argument("--serving-only", action="store_true",
                     help="instead of the headline step, run the serving leg alone (profiling runs of the loop)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -479,6 +482,135 @@ def histogram_leg(args, prec_list, steps):
     return out, {"patches": cfg["patches"], "hist": hist, "eps": eps}
 
 
+def etl_index_plan_legs():
+    """On the 100,000-patch histogram workload: the fused featurise-into-store
+    pass and the store self-join against featurise + plain join; the
+    index-pruned join against the plain join (fp16 and fp32 candidates); the
+    label filter before and after the match; and crop featurisation of boxes
+    over frames.  ms per call (mean of 3 after one untimed call), each
+    result's pair arrays compared with the plain join's."""
+    import numpy as np
+    import torch
+
+    from paper_1812_07607_amd import ops, synth
+    ctx = ops.context()
+    cfg = synth.config2(1.0)
+    n = 100000
+    pairs = n * (n - 1) // 2
+    patches = torch.from_numpy(cfg["patches"]).cuda()
+    hist = ops.featurize_rgb8(patches, 8)
+    pi, pj = cfg["pairs"]
+    d2 = ops.pair_d2(hist, hist, torch.from_numpy(pi), torch.from_numpy(pj)).cpu().numpy()
+    eps = float(np.sqrt(synth.order_statistic(d2, cfg["q"])))
+    out = {"workload": "100000 palette patches, 8x8x8 histograms, eps self-join at the 0.01%% quantile (eps %.6g)" % eps}
+
+    def same(a, b):
+        return bool(a.count == b.count and torch.equal(a.i, b.i) and torch.equal(a.j, b.j))
+
+    # fused featurise-into-store + store self-join vs featurise + join
+    plain, rec_p = timed_calls(ctx, lambda: (ops.featurize_rgb8(patches, 8, out=hist),
+                                             ops.join_eps(hist, None, eps, "fp16"))[1], 3)
+    st_holder = {}
+    caps = {}
+
+    def fused():
+        st_holder["s"] = ops.Store.featurize(patches, 8, "fp16")
+        st_holder["s"]._eps_caps = caps  # the output size that sufficed carries over to the next store
+        return st_holder["s"].join_eps_self(eps)
+
+    r, rec_f = timed_calls(ctx, fused, 3)
+    out["fused_store"] = {"unfused_ms": rec_p["ms_per_call"], "fused_ms": rec_f["ms_per_call"],
+                          "unfused_stages": rec_p, "fused_stages": rec_f, "same_pairs": same(r, plain),
+                          "value_fused": pairs / (rec_f["ms_per_call"] * 1e-3) / 1e9}
+    progress("fused store: %s" % json.dumps(out["fused_store"]))
+    # the index-pruned join
+    out["index_join"] = {}
+    for prec in ("fp16", "fp32"):
+        ref, rec0 = timed_calls(ctx, lambda: ops.join_eps(hist, None, eps, prec), 3)
+        (r, info), rec1 = timed_calls(ctx, lambda: ops.join_eps_indexed(hist, None, eps, prec), 3)
+        out["index_join"][prec] = {"plain_ms": rec0["ms_per_call"], "indexed_ms": rec1["ms_per_call"],
+                                   "speedup": rec0["ms_per_call"] / rec1["ms_per_call"],
+                                   "tiles_computed": info.tiles_computed, "tiles_total": info.tiles_total,
+                                   "pivots": info.pivots, "indexed_stages": rec1, "same_pairs": same(r, ref),
+                                   "value_indexed": pairs / (rec1["ms_per_call"] * 1e-3) / 1e9}
+        progress("index %s: %s" % (prec, json.dumps(out["index_join"][prec])))
+    # filter before / after the match (the palette colour as the label)
+    labels = torch.from_numpy(cfg["colour"].astype(np.int32)).cuda()
+    res = {}
+    for plan in ("filter_first", "match_first"):
+        res[plan], rec = timed_calls(ctx, lambda: ops.join_eps_filtered(hist, None, eps, labels, None, 5, plan,
+                                                                         "fp16"), 3)
+        out.setdefault("plans", {})[plan] = {"ms": rec["ms_per_call"], "pairs": res[plan].count}
+    out["plans"]["same_pairs"] = same(res["filter_first"], res["match_first"])
+    progress("plans: %s" % json.dumps(out["plans"]))
+    del hist, patches
+    # crops: 20,000 boxes over 64 frames of 720 x 1280
+    frames, boxes = synth.frames_with_boxes(64, 720, 1280, 20000, seed=606)
+    ft, bt = torch.from_numpy(frames).cuda(), torch.from_numpy(boxes).cuda()
+    h2 = torch.empty((boxes.shape[0], 512), dtype=torch.float32, device="cuda")
+    _, rec = timed_calls(ctx, lambda: ops.featurize_crops_rgb8(ft, bt, 8, out=h2), 3)
+    area = int(((boxes[:, 3] - boxes[:, 1]) * (boxes[:, 4] - boxes[:, 2])).sum())
+    nbytes = area * 3 + boxes.shape[0] * 512 * 4
+    out["crops"] = {"boxes": int(boxes.shape[0]), "pixels": area, "ms": rec["featurize"],
+                    "GBps_algorithmic": nbytes / (rec["featurize"] * 1e-3) / 1e9}
+    progress("crops: %s" % json.dumps(out["crops"]))
+    return out
+
+
+def cpu_baseline_crossover():
+    """The CPU baseline as a sweep (the CPU-vs-GPU crossover of the paper's
+    matching discussion): the histogram self-join at growing sizes, timed as
+    the float64 oracle on all host cores against the GPU join on
+    device-resident rows and the GPU join with the rows copied in and the
+    pairs copied out (an offload from host memory).  The GPU featurises its
+    own rows (bit-identical to the oracle's, as the tests check).  One JSON
+    line."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1812_07607_amd import ops, synth
+    torch.cuda.set_device(0)
+    ctx = ops.context()
+    threads = oracle.max_threads()
+    cfg = synth.config2(0.4)
+    Hfull = oracle.hist_rgb8(cfg["patches"], 8, nthreads=threads)
+    Hgpu = ops.featurize_rgb8(torch.from_numpy(cfg["patches"]).cuda(), 8)
+    rows = []
+    for n in (16, 64, 256, 1024, 4096, 16384, 40000):
+        H = np.ascontiguousarray(Hfull[:n])
+        Hh = Hgpu[:n].cpu().numpy()  # the GPU's own rows, on the host for the offload timing
+        pi, pj = synth.sample_pairs(n, n, 20000, True, seed=n)
+        eps = float(np.sqrt(synth.order_statistic(oracle.pair_d2(H, H, pi, pj), 0.001)))
+        reps = max(1, min(20, int(2e7 / max(n * n, 1))))
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ref = oracle.eps_join(H, None, eps, nthreads=threads)
+        t_cpu = (time.perf_counter() - t0) / reps
+        Hd = Hgpu[:n].contiguous()
+        r = ops.join_eps(Hd, None, eps, "fp16")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = ops.join_eps(Hd, None, eps, "fp16")
+        torch.cuda.synchronize()
+        t_dev = (time.perf_counter() - t0) / reps
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            Hx = torch.from_numpy(Hh).cuda()
+            r = ops.join_eps(Hx, None, eps, "fp16")
+            got = (r.i.cpu(), r.j.cpu(), r.dist.cpu())
+        t_off = (time.perf_counter() - t0) / reps
+        same = bool(r.count == ref["count"] and np.array_equal(got[0].numpy().astype(np.int64), ref["i"]) and
+                    np.array_equal(got[1].numpy().astype(np.int64), ref["j"]))
+        rows.append({"n": n, "pairs": n * (n - 1) // 2, "cpu_ms": t_cpu * 1e3, "gpu_resident_ms": t_dev * 1e3,
+                     "gpu_offload_ms": t_off * 1e3, "same_pairs": same})
+        progress("crossover n=%d: %s" % (n, json.dumps(rows[-1])))
+    print(json.dumps({"crossover": rows, "cpu": cpu_model(), "cores": threads,
+                      "workload": "palette-patch histogram self-join at the 0.1% quantile of 20,000 sampled pairs; "
+                                  "GPU fp16 candidates"}))
+
+
 def store_leg():
     """Top-32 of 50,000 queries against a 4,000,000 x 256 store (4,096-centre
     mixture): E4M3 candidates (with their bf16 pilot) and bf16, ms per call
@@ -561,6 +693,9 @@ def main():
         return
     if args.serving_only:
         print(json.dumps({"serving": serving(args)}))
+        return
+    if args.crossover:
+        cpu_baseline_crossover()
         return
     n = args.n
     d = 128
@@ -658,6 +793,9 @@ def main():
     if not args.no_extras:
         progress("histogram leg")
         res["histogram_join"], _ = histogram_leg(args, ["fp32", "fp16"], 3)
+        torch.cuda.empty_cache()
+        progress("fused store, index, plan and crop legs")
+        res["etl_index_plans"] = etl_index_plan_legs()
         torch.cuda.empty_cache()
         progress("store leg")
         res["store_top32"] = store_leg()

@@ -252,6 +252,38 @@ dl_status dl_join_eps_indexed(dl_ctx* ctx, dl_mat R, dl_mat S, int self_join,
                               void* ws, size_t ws_bytes, dl_pairs* out,
                               dl_index_info* info, void* stream);
 
+/* ----------------------------------------------------- filtered eps-join */
+
+/* Scratch bytes for dl_join_eps_filtered (plan 0 or 1) with room for
+ * max_candidates candidates and, for plan 1, max_pairs unfiltered pairs. */
+size_t dl_join_eps_filtered_workspace(int64_t nR, int64_t nS, int32_t d,
+                                      dl_prec prec, int self_join,
+                                      int32_t plan, int64_t max_candidates,
+                                      int64_t max_pairs);
+
+/* The eps-join of the rows of R and S whose label equals `label` (section
+ * "Query Processing": a query's filter on patch metadata and its match, in
+ * either order; the paper's plan-order experiment).  The result -- pairs
+ * (i, j) of the original rows with both labels equal to `label` and
+ * sqrt(d2) <= eps, in (i, j) order, as dl_join_eps -- is the same for both
+ * plans; the work is not:
+ *   plan 0  filter first: select and gather each relation's matching rows,
+ *           join those, map the pairs back to the original rows;
+ *   plan 1  match first: join all rows into the workspace (at most
+ *           max_pairs pairs), then keep the pairs whose two labels match.
+ *   labels_R, labels_S  device int32 per row (labels_S ignored for a
+ *                       self-join).
+ * Errors as dl_join_eps; plan 1 returns DL_ERR_WORKSPACE when the
+ * unfiltered pairs exceed max_pairs (dl_required_workspace says how much
+ * would do).  Synchronises `stream`. */
+dl_status dl_join_eps_filtered(dl_ctx* ctx, dl_mat R, dl_mat S, int self_join,
+                               double eps, dl_prec prec,
+                               const int32_t* labels_R,
+                               const int32_t* labels_S, int32_t label,
+                               int32_t plan, int64_t max_candidates,
+                               int64_t max_pairs, void* ws, size_t ws_bytes,
+                               dl_pairs* out, void* stream);
+
 /* ---------------------------------------------------------------- top-k */
 
 typedef struct dl_topk_info {

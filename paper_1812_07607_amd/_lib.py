@@ -92,6 +92,9 @@ SIGNATURES = {
     "dl_join_eps_indexed_workspace": (sz, [i64, i64, i32, ctypes.c_int, ctypes.c_int, i64, i32]),
     "dl_join_eps_indexed": (ctypes.c_int, [P, dl_mat, dl_mat, ctypes.c_int, f64, ctypes.c_int, i32, P, sz,
                                            ctypes.POINTER(dl_pairs), ctypes.POINTER(dl_index_info), P]),
+    "dl_join_eps_filtered_workspace": (sz, [i64, i64, i32, ctypes.c_int, ctypes.c_int, i32, i64, i64]),
+    "dl_join_eps_filtered": (ctypes.c_int, [P, dl_mat, dl_mat, ctypes.c_int, f64, ctypes.c_int, P, P, i32, i32, i64,
+                                            i64, P, sz, ctypes.POINTER(dl_pairs), P]),
     "dl_join_topk_workspace": (sz, [i64, i64, i32, ctypes.c_int, ctypes.c_int, i32, i32]),
     "dl_join_topk": (ctypes.c_int, [P, dl_mat, dl_mat, ctypes.c_int, i32, ctypes.c_int, ctypes.c_int, i32, P, sz,
                                     P, P, ctypes.POINTER(dl_topk_info), P]),

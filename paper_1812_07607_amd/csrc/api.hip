@@ -45,6 +45,14 @@ hipError_t launch_group_count(const uint32_t*, int64_t, int64_t, int64_t, int64_
 hipError_t launch_group_list(const uint32_t*, int64_t, int64_t, int64_t, int64_t, const uint32_t*, uint2*,
                              unsigned long long*, hipStream_t, int);
 int cand_group_rows(int64_t qld, int64_t nTR);
+// plan.hip
+int64_t plan_scratch_words(int64_t);
+hipError_t launch_select_rows(const int32_t*, int64_t, int32_t, uint32_t*, uint32_t*, unsigned long long*, hipStream_t);
+hipError_t launch_filter_pairs(const uint32_t*, const uint32_t*, const float*, int64_t, const int32_t*,
+                               const int32_t*, int32_t, uint32_t*, uint32_t*, float*, int64_t, uint32_t*,
+                               unsigned long long*, hipStream_t);
+hipError_t launch_gather(const float*, int64_t, int, const uint32_t*, int64_t, float*, hipStream_t, int);
+hipError_t launch_remap(uint32_t*, uint32_t*, int64_t, const uint32_t*, const uint32_t*, hipStream_t, int);
 // sort.hip
 hipError_t launch_exclusive_scan(const uint32_t*, int64_t, uint32_t*, uint32_t*, hipStream_t);
 int64_t scan_scratch_words(int64_t);
@@ -1037,7 +1045,15 @@ dl_status eps_indexed_core(dl_ctx* c, const EpsJob& J, double eps, int32_t pivot
     DL_HIP(c, launch_group_count(I.surv, I.sw, nTR, nTS, I.gm, I.cnt, st, c->cu_count));
     DL_HIP(c, launch_exclusive_scan(I.cnt, ncnt + 1, I.off, I.sums, st));
     DL_HIP(c, launch_group_list(I.surv, I.sw, nTR, nTS, I.gm, I.off, I.tiles, I.ntiles, st, c->cu_count));
+    DL_HIP(c, hipMemcpyAsync(c->pinned + 28, I.ntiles, 8, hipMemcpyDeviceToHost, st));
+    DL_HIP(c, hipStreamSynchronize(st));
   }
+  // When most tiles survive, the full grid (its order needs no per-tile
+  // list reads, which for a list of many millions of entries miss every
+  // cache) beats the list; the ordered operand copies serve either.
+  const int64_t survivors = c->pinned[28];
+  if (info) info->tiles_computed = survivors;
+  const bool use_list = 2 * survivors < all_tiles;
   {
     StageTimer t(c, 2, st);
     CandParams p{};
@@ -1057,9 +1073,14 @@ dl_status eps_indexed_core(dl_ctx* c, const EpsJob& J, double eps, int32_t pivot
     p.candp = prec == DL_FP8 ? nullptr : L.candp;
     p.ccap = cap;
     p.gate = &L.cnt->invalid;
-    p.tiles = I.tiles;
-    p.ntiles = I.ntiles;
-    DL_HIP(c, launch_cand_list(prec, p, st, c->cu_count));
+    if (use_list) {
+      p.tiles = I.tiles;
+      p.ntiles = I.ntiles;
+      DL_HIP(c, launch_cand_list(prec, p, st, c->cu_count));
+    } else {
+      DL_HIP(c, launch_cand_eps(prec, p, st, c->cu_count));
+      if (info) info->tiles_computed = all_tiles;
+    }
   }
   const int bj = bits_for(S.n);
   {
@@ -1082,11 +1103,8 @@ dl_status eps_indexed_core(dl_ctx* c, const EpsJob& J, double eps, int32_t pivot
     q.swap = self ? 1 : 0;
     DL_HIP(c, launch_recheck_eps(q, st, c->cu_count));
   }
-  // the tile count rides along with the counters' readback
-  DL_HIP(c, hipMemcpyAsync(c->pinned + 28, I.ntiles, 8, hipMemcpyDeviceToHost, st));
   DL_HIP(c, readback(c, L.cnt, L.sr, L.ss, st));
   const Counters hc = *reinterpret_cast<const Counters*>(c->pinned);
-  if (info) info->tiles_computed = c->pinned[28];
   if (dl_status bad = check_inputs(c)) return bad;
   out->candidates = (int64_t)hc.cand;
   out->ties = (int64_t)hc.ties;
@@ -1106,6 +1124,100 @@ dl_status eps_indexed_core(dl_ctx* c, const EpsJob& J, double eps, int32_t pivot
     DL_HIP(c, row_sort_pairs(L.k0, L.v0, m, R.n, bj, L.k1, L.v1, L.rows, w, out->i, out->j, out->dist, st,
                              c->cu_count));
   }
+  if (m > out->capacity)
+    return fail(c, DL_ERR_CAPACITY, "%lld pairs exceed the output capacity %lld", (long long)m,
+                (long long)out->capacity);
+  return DL_OK;
+}
+
+// ------------------------------------------------------------ filtered eps-join
+// A label filter before or after the match (plan.hip).
+struct FilterLayout {
+  uint32_t *rowsR, *rowsS, *scratch;
+  unsigned long long* counts;  // rows kept of R and S, pairs kept
+  float *Rg, *Sg;              // gathered rows (filter first)
+  uint32_t *ti, *tj;           // unfiltered pairs (match first)
+  float* td;
+  uint8_t* jws;                // the join's workspace
+  size_t jws_bytes, bytes;
+};
+
+static FilterLayout layout_filter(void* base, int64_t nR, int64_t nS, int d, dl_prec prec, bool self, int plan,
+                                  int64_t max_cand, int64_t max_pairs) {
+  FilterLayout F{};
+  Bump b(base);
+  const int64_t n = nR > nS ? nR : nS;
+  F.counts = b.take<unsigned long long>(4);
+  F.scratch = b.take<uint32_t>(plan_scratch_words(plan == 0 ? n : (max_pairs < 1 ? 1 : max_pairs)));
+  if (plan == 0) {
+    F.rowsR = b.take<uint32_t>(nR);
+    F.rowsS = self ? F.rowsR : b.take<uint32_t>(nS);
+    F.Rg = b.take<float>(nR * (int64_t)d);
+    F.Sg = self ? F.Rg : b.take<float>(nS * (int64_t)d);
+  } else {
+    const int64_t m = max_pairs < 1 ? 1 : max_pairs;
+    F.ti = b.take<uint32_t>(m);
+    F.tj = b.take<uint32_t>(m);
+    F.td = b.take<float>(m);
+  }
+  F.jws_bytes = layout_eps(nullptr, nR, nS, d, prec, self, max_cand < 1 ? 1 : max_cand).bytes;
+  F.jws = b.take<uint8_t>((int64_t)F.jws_bytes);
+  F.bytes = round_up((int64_t)b.off, 256);
+  return F;
+}
+
+dl_status eps_filtered_core(dl_ctx* c, const EpsJob& J, const int32_t* labR, const int32_t* labS, int32_t want,
+                            int plan, int64_t max_cand, int64_t max_pairs, void* ws, size_t ws_bytes, dl_pairs* out,
+                            hipStream_t st) {
+  const dl_mat &R = J.R, &S = J.S;
+  const bool self = J.self;
+  const int d = R.d;
+  out->count = out->candidates = out->ties = 0;
+  const FilterLayout need = layout_filter(nullptr, R.n, S.n, d, J.prec, self, plan, max_cand, max_pairs);
+  if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(c, DL_ERR_INVALID, "workspace is not 256-byte aligned");
+  if (!ws || ws_bytes < need.bytes) {
+    c->required_ws = need.bytes;
+    return fail(c, DL_ERR_WORKSPACE, "workspace of %zu bytes below the %zu needed", ws_bytes, need.bytes);
+  }
+  const FilterLayout F = layout_filter(ws, R.n, S.n, d, J.prec, self, plan, max_cand, max_pairs);
+  if (plan == 0) {
+    // filter first: the rows whose label matches, gathered; the join of those;
+    // pairs mapped back to the original rows (increasing maps keep the order)
+    DL_HIP(c, launch_select_rows(labR, R.n, want, F.rowsR, F.scratch, F.counts, st));
+    if (!self) DL_HIP(c, launch_select_rows(labS, S.n, want, F.rowsS, F.scratch, F.counts + 1, st));
+    DL_HIP(c, hipMemcpyAsync(c->pinned + 24, F.counts, 16, hipMemcpyDeviceToHost, st));
+    DL_HIP(c, hipStreamSynchronize(st));
+    const int64_t mR = c->pinned[24], mS = self ? mR : c->pinned[25];
+    DL_HIP(c, launch_gather(R.data, R.ld, d, F.rowsR, mR, F.Rg, st, c->cu_count));
+    if (!self) DL_HIP(c, launch_gather(S.data, S.ld, d, F.rowsS, mS, F.Sg, st, c->cu_count));
+    EpsJob Jf = J;
+    Jf.R = dl_mat{F.Rg, mR, d, d};
+    Jf.S = self ? Jf.R : dl_mat{F.Sg, mS, d, d};
+    const dl_status s = eps_core(c, Jf, F.jws, F.jws_bytes, out, st);
+    if (s != DL_OK) return s;
+    const int64_t w = out->count < out->capacity ? out->count : out->capacity;
+    DL_HIP(c, launch_remap(out->i, out->j, w, F.rowsR, F.rowsS, st, c->cu_count));
+    DL_HIP(c, hipStreamSynchronize(st));
+    return DL_OK;
+  }
+  // match first: the whole join into the workspace, then the pairs whose two
+  // rows match the label, in order, into the output
+  dl_pairs all{F.ti, F.tj, F.td, max_pairs, 0, 0, 0};
+  const dl_status s = eps_core(c, J, F.jws, F.jws_bytes, &all, st);
+  if (s == DL_ERR_CAPACITY) {
+    c->required_ws = layout_filter(nullptr, R.n, S.n, d, J.prec, self, plan, max_cand, all.count + all.count / 8).bytes;
+    return fail(c, DL_ERR_WORKSPACE, "%lld unfiltered pairs exceed the workspace's %lld", (long long)all.count,
+                (long long)max_pairs);
+  }
+  if (s != DL_OK) return s;
+  out->candidates = all.candidates;
+  out->ties = all.ties;
+  DL_HIP(c, launch_filter_pairs(F.ti, F.tj, F.td, all.count, labR, self ? labR : labS, want, out->i, out->j,
+                                out->dist, out->capacity, F.scratch, F.counts + 2, st));
+  DL_HIP(c, hipMemcpyAsync(c->pinned + 26, F.counts + 2, 8, hipMemcpyDeviceToHost, st));
+  DL_HIP(c, hipStreamSynchronize(st));
+  const int64_t m = c->pinned[26];
+  out->count = m;
   if (m > out->capacity)
     return fail(c, DL_ERR_CAPACITY, "%lld pairs exceed the output capacity %lld", (long long)m,
                 (long long)out->capacity);
@@ -1209,6 +1321,42 @@ dl_status dl_join_eps_indexed(dl_ctx* c, dl_mat R, dl_mat S, int self_join, doub
   DL_HIP(c, hipSetDevice(c->device));
   EpsJob J{R, S, self_join != 0, prec, nullptr, nullptr, threshold_from_eps(eps), nullptr};
   return eps_indexed_core(c, J, eps, pivots, ws, ws_bytes, out, info, static_cast<hipStream_t>(stream));
+}
+
+size_t dl_join_eps_filtered_workspace(int64_t nR, int64_t nS, int32_t d, dl_prec prec, int self_join, int32_t plan,
+                                      int64_t max_candidates, int64_t max_pairs) {
+  if (nR < 0 || nS < 0 || d < 1 || d > kMaxDim || !prec_ok(prec) || max_candidates < 0 || max_pairs < 0 ||
+      (plan != 0 && plan != 1))
+    return 0;
+  if (self_join) nS = nR;
+  return layout_filter(nullptr, nR, nS, d, prec, self_join != 0, plan, max_candidates, max_pairs).bytes;
+}
+
+dl_status dl_join_eps_filtered(dl_ctx* c, dl_mat R, dl_mat S, int self_join, double eps, dl_prec prec,
+                               const int32_t* labels_R, const int32_t* labels_S, int32_t label, int32_t plan,
+                               int64_t max_candidates, int64_t max_pairs, void* ws, size_t ws_bytes, dl_pairs* out,
+                               void* stream) {
+  if (!c) return DL_ERR_INVALID;
+  c->err.clear();
+  c->required_ws = 0;
+  if (self_join) {
+    S = R;
+    labels_S = labels_R;
+  }
+  dl_status s;
+  if ((s = check_mat(c, R, "R")) != DL_OK || (s = check_mat(c, S, "S")) != DL_OK) return s;
+  if (R.d != S.d) return fail(c, DL_ERR_INVALID, "R.d %d != S.d %d", R.d, S.d);
+  if (std::isnan(eps) || eps < 0) return fail(c, DL_ERR_INVALID, "eps must be >= 0 (got %g)", eps);
+  if (!prec_ok(prec)) return fail(c, DL_ERR_INVALID, "unknown precision %d", (int)prec);
+  if (plan != 0 && plan != 1) return fail(c, DL_ERR_INVALID, "plan = %d (0: filter first, 1: match first)", plan);
+  if (max_candidates < 1 || max_pairs < 0) return fail(c, DL_ERR_INVALID, "bad capacities");
+  if ((R.n > 0 && !labels_R) || (S.n > 0 && !labels_S)) return fail(c, DL_ERR_INVALID, "null labels");
+  if (!out || out->capacity < 0) return fail(c, DL_ERR_INVALID, "bad output struct");
+  if (out->capacity > 0 && (!out->i || !out->j || !out->dist)) return fail(c, DL_ERR_INVALID, "null output array");
+  DL_HIP(c, hipSetDevice(c->device));
+  EpsJob J{R, S, self_join != 0, prec, nullptr, nullptr, threshold_from_eps(eps), nullptr};
+  return eps_filtered_core(c, J, labels_R, labels_S, label, plan, max_candidates, max_pairs, ws, ws_bytes, out,
+                           static_cast<hipStream_t>(stream));
 }
 
 size_t dl_join_topk_workspace(int64_t nR, int64_t nS, int32_t d, dl_prec prec, int self_join, int32_t k,

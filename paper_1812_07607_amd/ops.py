@@ -262,6 +262,51 @@ def join_eps_indexed(R: torch.Tensor, S: torch.Tensor | None, eps: float, prec: 
     raise RuntimeError("join_eps_indexed did not converge on workspace / capacity")
 
 
+def join_eps_filtered(R: torch.Tensor, S: torch.Tensor | None, eps: float, labels_R: torch.Tensor,
+                      labels_S: torch.Tensor | None, label: int, plan: str = "filter_first", prec: str = "bf16",
+                      max_candidates: int | None = None, max_pairs: int | None = None, capacity: int | None = None,
+                      stream=None, workspace: Workspace | None = None) -> EpsResult:
+    """eps-join of the rows whose int32 label equals `label`, with the label
+    filter before the match (plan "filter_first") or after it
+    ("match_first").  The same result either way."""
+    self_join = S is None
+    Sm = R if self_join else S
+    lR = labels_R.to(device=R.device, dtype=torch.int32).contiguous()
+    lS = lR if self_join else labels_S.to(device=R.device, dtype=torch.int32).contiguous()
+    c = context(R.device.index)
+    ws = workspace or _workspace(R.device)
+    p = _lib.PREC[prec]
+    pl = {"filter_first": 0, "match_first": 1}[plan]
+    nR, nS, d = R.shape[0], Sm.shape[0], R.shape[1]
+    if max_candidates is None:
+        max_candidates = max(1 << 20, 4 * (nR + nS))
+    if max_pairs is None:
+        max_pairs = max(1 << 20, 4 * (nR + nS))
+    cap = capacity if capacity is not None else max(1 << 16, nR + nS)
+    for _ in range(10):
+        need = c.L.dl_join_eps_filtered_workspace(nR, nS, d, p, int(self_join), pl, max_candidates, max_pairs)
+        buf = ws.get(need)
+        oi = torch.empty(cap, dtype=torch.int32, device=R.device)
+        oj = torch.empty(cap, dtype=torch.int32, device=R.device)
+        od = torch.empty(cap, dtype=torch.float32, device=R.device)
+        pr = _lib.dl_pairs(oi.data_ptr(), oj.data_ptr(), od.data_ptr(), cap, 0, 0, 0)
+        st = c.L.dl_join_eps_filtered(c.h, _mat(R), _mat(Sm), int(self_join), float(eps), p,
+                                      ctypes.c_void_p(lR.data_ptr()), ctypes.c_void_p(lS.data_ptr()), int(label), pl,
+                                      max_candidates, max_pairs, ctypes.c_void_p(buf.data_ptr()), buf.numel(),
+                                      ctypes.byref(pr), _stream_ptr(stream))
+        if st == _lib.DL_ERR_WORKSPACE:
+            max_candidates = max(2 * max_candidates, int(pr.candidates * 1.25) + 1024)
+            max_pairs = max(2 * max_pairs, int(pr.count * 1.25) + 1024)
+            continue
+        if st == _lib.DL_ERR_CAPACITY:
+            cap = int(pr.count)
+            continue
+        c.check(st)
+        m = int(pr.count)
+        return EpsResult(oi[:m], oj[:m], od[:m], m, int(pr.candidates), int(pr.ties))
+    raise RuntimeError("join_eps_filtered did not converge on workspace / capacity")
+
+
 # ---------------------------------------------------------------- top-k
 @dataclass
 class TopkResult:
@@ -372,7 +417,9 @@ class Store:
         ws = workspace or _workspace(self.base.device)
         if max_candidates is None:
             max_candidates = max(1 << 20, 4 * self.n)
-        cap = out[0].numel() if out is not None else max(1 << 16, 2 * self.n)
+        # a call with the same eps starts from the output size that sufficed
+        caps = self.__dict__.setdefault("_eps_caps", {})
+        cap = out[0].numel() if out is not None else max(1 << 16, 2 * self.n, caps.get(float(eps), 0))
         for _ in range(8):
             buf = ws.get(L.dl_join_eps_store_self_workspace(self.h, max_candidates))
             if out is not None and out[0].numel() >= cap:
@@ -393,6 +440,7 @@ class Store:
                 continue
             c.check(st)
             m = int(pr.count)
+            caps[float(eps)] = cap
             return EpsResult(oi[:m], oj[:m], od[:m], m, int(pr.candidates), int(pr.ties))
         raise RuntimeError("join_eps_self (store) did not converge")
 
