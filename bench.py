@@ -531,6 +531,8 @@ def etl_index_plan_legs():
         out["index_join"][prec] = {"plain_ms": rec0["ms_per_call"], "indexed_ms": rec1["ms_per_call"],
                                    "speedup": rec0["ms_per_call"] / rec1["ms_per_call"],
                                    "tiles_computed": info.tiles_computed, "tiles_total": info.tiles_total,
+                                   "ksteps_computed": info.ksteps_computed,
+                                   "ksteps_of_computed_tiles": info.tiles_computed * info.ksteps_per_tile,
                                    "pivots": info.pivots, "indexed_stages": rec1, "same_pairs": same(r, ref),
                                    "value_indexed": pairs / (rec1["ms_per_call"] * 1e-3) / 1e9}
         progress("index %s: %s" % (prec, json.dumps(out["index_join"][prec])))

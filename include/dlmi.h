@@ -223,9 +223,12 @@ dl_status dl_join_eps_noalloc(dl_ctx* ctx, dl_mat R, dl_mat S, int self_join,
 
 /* What the index of dl_join_eps_indexed pruned. */
 typedef struct dl_index_info {
-  int64_t tiles_total;    /* 256 x 256 tiles of the join (self-join: upper triangle) */
-  int64_t tiles_computed; /* tiles the candidate pass ran on                         */
-  int32_t pivots;         /* pivots of the row ordering; 0: no index was built        */
+  int64_t tiles_total;     /* 256 x 256 tiles of the join (self-join: upper triangle) */
+  int64_t tiles_computed;  /* tiles the candidate pass ran on                         */
+  int32_t pivots;          /* pivots of the row ordering; 0: no index was built        */
+  int32_t ksteps_per_tile; /* K-steps (128 operand bytes of each row) of a full tile   */
+  int64_t ksteps_computed; /* K-steps run over the computed tiles: steps where every
+                              row of either tile is zero are skipped                  */
 } dl_index_info;
 
 /* Scratch bytes for dl_join_eps_indexed with room for `max_candidates`
@@ -244,9 +247,15 @@ size_t dl_join_eps_indexed_workspace(int64_t nR, int64_t nS, int32_t d,
  * (centroid, radius), and a 256 x 256 tile of pairs is computed only if a
  * row of each side lies within eps + radius of the other side's ball, a test
  * the triangle inequality makes exact (no result pair is ever pruned).  On
- * clustered data most tiles are skipped.  Without a finite eps, or with a
- * relation under 512 rows, it runs as dl_join_eps.  info (host, nullable)
- * reports the tiles computed.  Synchronises `stream`. */
+ * clustered data most tiles are skipped.  Within a computed tile, the
+ * K-steps (128 bytes of each operand row: 64 bins of an fp16 histogram) in
+ * which every row of the R tile or every row of the S tile is zero are
+ * skipped too: their products are zero, so the result is unchanged (the
+ * structure of image features that section "Conclusion and Future Work"
+ * points to: the rows of one cluster share few nonzero histogram bins).
+ * Without a finite eps, or with a relation under 512 rows, it runs as
+ * dl_join_eps.  info (host, nullable) reports the tiles and K-steps
+ * computed.  Synchronises `stream`. */
 dl_status dl_join_eps_indexed(dl_ctx* ctx, dl_mat R, dl_mat S, int self_join,
                               double eps, dl_prec prec, int32_t pivots,
                               void* ws, size_t ws_bytes, dl_pairs* out,

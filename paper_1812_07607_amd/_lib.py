@@ -35,7 +35,8 @@ class dl_box(ctypes.Structure):
 
 
 class dl_index_info(ctypes.Structure):
-    _fields_ = [("tiles_total", ctypes.c_int64), ("tiles_computed", ctypes.c_int64), ("pivots", ctypes.c_int32)]
+    _fields_ = [("tiles_total", ctypes.c_int64), ("tiles_computed", ctypes.c_int64), ("pivots", ctypes.c_int32),
+                ("ksteps_per_tile", ctypes.c_int32), ("ksteps_computed", ctypes.c_int64)]
 
 
 class dl_topk_info(ctypes.Structure):

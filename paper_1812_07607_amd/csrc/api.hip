@@ -35,8 +35,8 @@ hipError_t launch_cand_mark(dl_prec, CandParams, hipStream_t, int);
 hipError_t launch_cand_nearest(dl_prec, CandParams, hipStream_t, int);
 // index.hip
 hipError_t launch_gather_rows(const float*, int64_t, int64_t, int64_t, int, float*, hipStream_t, int);
-hipError_t launch_pivot_keys(const unsigned long long*, int64_t, int64_t, int, unsigned long long*, float*,
-                             hipStream_t, int);
+int64_t pivot_sort_words(int64_t n, int64_t npiv);
+hipError_t launch_pivot_sort(const unsigned long long*, int64_t, int64_t, uint32_t*, uint32_t*, hipStream_t);
 hipError_t launch_block_balls(const float*, int64_t, const uint32_t*, int64_t, int, double, float*, double*,
                               hipStream_t);
 hipError_t launch_survive(const uint32_t*, int64_t, const uint32_t*, int64_t, int64_t, int64_t, int, uint32_t*,
@@ -45,6 +45,9 @@ hipError_t launch_group_count(const uint32_t*, int64_t, int64_t, int64_t, int64_
 hipError_t launch_group_list(const uint32_t*, int64_t, int64_t, int64_t, int64_t, const uint32_t*, uint2*,
                              unsigned long long*, hipStream_t, int);
 int cand_group_rows(int64_t qld, int64_t nTR);
+hipError_t launch_tile_kmask(const void*, int64_t, int64_t, uint64_t*, hipStream_t);
+hipError_t launch_kstep_count(const uint2*, const unsigned long long*, int64_t, int64_t, int64_t, int,
+                              const uint64_t*, const uint64_t*, unsigned long long*, hipStream_t, int);
 // plan.hip
 int64_t plan_scratch_words(int64_t);
 hipError_t launch_select_rows(const int32_t*, int64_t, int32_t, uint32_t*, uint32_t*, unsigned long long*, hipStream_t);
@@ -834,9 +837,7 @@ struct IndexLayout {
   Prep ppiv;                        // their operand copy
   RelStats* spiv;
   unsigned long long* argkey;       // nearest pivot of each row (one relation at a time)
-  unsigned long long *keys, *pk;    // ordering by pivot
-  float *vals, *pv, *od;
-  uint32_t *oi, *words;
+  uint32_t* psort;                  // scratch of the ordering by pivot
   float *centS, *centR;             // block centroids
   double *TbS, *TbR;                // (eps + r)^2 per block
   Prep pcS, pcR;                    // their operand copies
@@ -846,6 +847,8 @@ struct IndexLayout {
   int64_t m1w, m2w, sw, gm;
   uint2* tiles;
   unsigned long long* ntiles;
+  uint64_t *kmR, *kmS;              // K-step masks per tile of the ordered operand copies
+  unsigned long long* ksteps;       // K-steps the candidate pass runs
   size_t bytes;
 };
 
@@ -861,13 +864,7 @@ static IndexLayout layout_index(void* base, int64_t nR, int64_t nS, int d, dl_pr
   X.ppiv = carve_prep(b, P, d, prec);
   X.spiv = b.take<RelStats>(1);
   X.argkey = b.take<unsigned long long>(n);
-  X.keys = b.take<unsigned long long>(n);
-  X.pk = b.take<unsigned long long>(n);
-  X.vals = b.take<float>(n);
-  X.pv = b.take<float>(n);
-  X.od = b.take<float>(n);
-  X.oi = b.take<uint32_t>(n);
-  X.words = b.take<uint32_t>(row_sort_words(P));
+  X.psort = b.take<uint32_t>(pivot_sort_words(n, P));
   X.centS = b.take<float>(nTS * (int64_t)d);
   X.TbS = b.take<double>(nTS);
   X.pcS = carve_prep(b, nTS, d, prec);
@@ -901,6 +898,9 @@ static IndexLayout layout_index(void* base, int64_t nR, int64_t nS, int d, dl_pr
   X.sums = b.take<uint32_t>(scan_scratch_words(ncnt) + 1);
   X.tiles = b.take<uint2>(self ? nTR * (nTR + 1) / 2 : nTR * nTS);
   X.ntiles = b.take<unsigned long long>(1);
+  X.kmR = b.take<uint64_t>(nTR);
+  X.kmS = self ? X.kmR : b.take<uint64_t>(nTS);
+  X.ksteps = b.take<unsigned long long>(1);
   X.bytes = round_up((int64_t)b.off, 256);
   return X;
 }
@@ -939,10 +939,7 @@ static dl_status order_by_pivot(dl_ctx* c, const dl_mat& X, const IndexLayout& I
   q.nS = P;
   q.argkey = I.argkey;
   DL_HIP(c, launch_cand_nearest(prec, q, st, c->cu_count));
-  const int bj = bits_for(X.n);
-  DL_HIP(c, launch_pivot_keys(I.argkey, X.n, P, bj, I.keys, I.vals, st, c->cu_count));
-  DL_HIP(c, row_sort_pairs(I.keys, I.vals, X.n, P, bj, I.pk, I.pv, I.words, X.n, I.oi, perm, I.od, st,
-                           c->cu_count));
+  DL_HIP(c, launch_pivot_sort(I.argkey, X.n, P, perm, I.psort, st));
   return DL_OK;
 }
 
@@ -986,6 +983,8 @@ dl_status eps_indexed_core(dl_ctx* c, const EpsJob& J, double eps, int32_t pivot
     info->tiles_total = all_tiles;
     info->tiles_computed = all_tiles;
     info->pivots = 0;
+    info->ksteps_per_tile = (int32_t)(dpad_of(d, prec) * elem_bytes(prec) / kChunkBytes);
+    info->ksteps_computed = all_tiles * info->ksteps_per_tile;
   }
   if (!index_applies(R.n, S.n, eps)) return eps_core(c, J, ws, ws_bytes, out, st);
   out->count = out->candidates = out->ties = 0;
@@ -1027,8 +1026,17 @@ dl_status eps_indexed_core(dl_ctx* c, const EpsJob& J, double eps, int32_t pivot
     hipLaunchKernelGGL(input_gate_kernel, dim3(1), dim3(64), 0, st, L.sr, L.ss, &L.cnt->invalid);
     DL_HIP(c, launch_threshold(L.pr, R.n, L.ss, d, J.T, nullptr, L.thr, nullptr, L.pex, nullptr, st));
   }
+  // K-step masks: rows ordered by pivot make a tile's rows alike, and bins
+  // (elements) that are zero in every row of a tile drop out of its K-steps
+  // (at most 64 steps per row)
+  const int nsteps = (int)(L.pr.qld / kChunkBytes);
+  const bool kmask = nsteps <= 64;
   {
     StageTimer t(c, 6, st);
+    if (kmask) {
+      DL_HIP(c, launch_tile_kmask(L.pr.q, L.pr.qld, nTR, I.kmR, st));
+      if (!self) DL_HIP(c, launch_tile_kmask(L.ps.q, L.ps.qld, nTS, I.kmS, st));
+    }
     // block balls and the bound passes (both directions), then the tile list
     DL_HIP(c, launch_block_balls(S.data, S.ld, I.permS, S.n, d, eps, I.centS, I.TbS, st));
     dl_status s = bound_pass(c, I.centS, nTS, I.TbS, d, prec, I.pcS, I.scS, I.thrS, L.pr, R.n, L.sr, I.m1, I.m1w,
@@ -1045,15 +1053,12 @@ dl_status eps_indexed_core(dl_ctx* c, const EpsJob& J, double eps, int32_t pivot
     DL_HIP(c, launch_group_count(I.surv, I.sw, nTR, nTS, I.gm, I.cnt, st, c->cu_count));
     DL_HIP(c, launch_exclusive_scan(I.cnt, ncnt + 1, I.off, I.sums, st));
     DL_HIP(c, launch_group_list(I.surv, I.sw, nTR, nTS, I.gm, I.off, I.tiles, I.ntiles, st, c->cu_count));
-    DL_HIP(c, hipMemcpyAsync(c->pinned + 28, I.ntiles, 8, hipMemcpyDeviceToHost, st));
-    DL_HIP(c, hipStreamSynchronize(st));
+    DL_HIP(c, hipMemcpyAsync(c->pinned + 28, I.ntiles, 8, hipMemcpyDeviceToHost, st));  // read after the final sync
   }
   // When most tiles survive, the full grid (its order needs no per-tile
   // list reads, which for a list of many millions of entries miss every
-  // cache) beats the list; the ordered operand copies serve either.
-  const int64_t survivors = c->pinned[28];
-  if (info) info->tiles_computed = survivors;
-  const bool use_list = 2 * survivors < all_tiles;
+  // cache) beats the list; the kernel reads the list's length and picks, so
+  // the host does not wait for it.  The ordered operand copies serve either.
   {
     StageTimer t(c, 2, st);
     CandParams p{};
@@ -1073,14 +1078,23 @@ dl_status eps_indexed_core(dl_ctx* c, const EpsJob& J, double eps, int32_t pivot
     p.candp = prec == DL_FP8 ? nullptr : L.candp;
     p.ccap = cap;
     p.gate = &L.cnt->invalid;
-    if (use_list) {
-      p.tiles = I.tiles;
-      p.ntiles = I.ntiles;
-      DL_HIP(c, launch_cand_list(prec, p, st, c->cu_count));
-    } else {
-      DL_HIP(c, launch_cand_eps(prec, p, st, c->cu_count));
-      if (info) info->tiles_computed = all_tiles;
+    if (kmask) {
+      p.kmaskA = I.kmR;
+      p.kmaskB = I.kmS;
     }
+    p.tiles = I.tiles;
+    p.ntiles = I.ntiles;
+    p.list_all = all_tiles;
+    DL_HIP(c, launch_cand_list(prec, p, st, c->cu_count));
+  }
+  c->pinned[29] = -1;
+  if (kmask && info) {
+    // the K-steps run, read back with the counters below
+    hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(I.ksteps),
+                       (int64_t)2);
+    DL_HIP(c, launch_kstep_count(I.tiles, I.ntiles, all_tiles, nTR, nTS, self ? 1 : 0, I.kmR, I.kmS, I.ksteps, st,
+                                 c->cu_count));
+    DL_HIP(c, hipMemcpyAsync(c->pinned + 29, I.ksteps, 8, hipMemcpyDeviceToHost, st));
   }
   const int bj = bits_for(S.n);
   {
@@ -1105,6 +1119,12 @@ dl_status eps_indexed_core(dl_ctx* c, const EpsJob& J, double eps, int32_t pivot
   }
   DL_HIP(c, readback(c, L.cnt, L.sr, L.ss, st));
   const Counters hc = *reinterpret_cast<const Counters*>(c->pinned);
+  if (info) {
+    const int64_t survivors = c->pinned[28];
+    info->tiles_computed = 2 * survivors < all_tiles ? survivors : all_tiles;
+    info->ksteps_per_tile = nsteps;
+    info->ksteps_computed = c->pinned[29] >= 0 ? c->pinned[29] : info->tiles_computed * nsteps;
+  }
   if (dl_status bad = check_inputs(c)) return bad;
   out->candidates = (int64_t)hc.cand;
   out->ties = (int64_t)hc.ties;

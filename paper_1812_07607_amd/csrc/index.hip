@@ -28,6 +28,9 @@
 
 namespace dl {
 
+hipError_t launch_exclusive_scan(const uint32_t* in, int64_t n, uint32_t* out, uint32_t* sums, hipStream_t st);
+int64_t scan_scratch_words(int64_t n);
+
 // Rows 0, stride, 2 stride, ... (m of them) of X into out (m x d, dense).
 __global__ void gather_rows_kernel(const float* __restrict__ X, int64_t ld, int64_t stride, int64_t m, int d,
                                    float* __restrict__ out) {
@@ -38,16 +41,66 @@ __global__ void gather_rows_kernel(const float* __restrict__ X, int64_t ld, int6
   }
 }
 
-// Sort keys (pivot << bj | row) of a relation's rows, for the row-bucketed
-// ordering (which is then a stable counting sort by pivot).  argkey: per row
-// the nearest pass's key, whose low word is the complement of the pivot.
-__global__ void pivot_keys_kernel(const unsigned long long* __restrict__ argkey, int64_t n, uint32_t npiv, int bj,
-                                  unsigned long long* __restrict__ keys, float* __restrict__ vals) {
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t c = 0xffffffffu - (uint32_t)(argkey[t] & 0xffffffffull);
-    const uint32_t pv = c < npiv ? c : npiv - 1;  // a row no pivot won (NaN input) goes to the last
-    keys[t] = ((unsigned long long)pv << bj) | (unsigned long long)t;
-    vals[t] = 0.0f;
+// Ordering the rows by nearest pivot: a stable counting sort, one wave per
+// chunk of kPivChunk rows.  The pivot of row t comes from the nearest pass's
+// key, whose low word is the complement of the winning column; a row no
+// pivot won (NaN input) goes to the last pivot.
+constexpr int kPivChunk = 2048;
+
+__device__ inline uint32_t pivot_of(unsigned long long key, uint32_t npiv) {
+  const uint32_t c = 0xffffffffu - (uint32_t)(key & 0xffffffffull);
+  return c < npiv ? c : npiv - 1;
+}
+
+// Pass 1: the rows of each pivot in chunk b, at cnt[p * nb + b] (pivot
+// major, so an exclusive scan gives each (pivot, chunk) its first slot).
+// LDS: npiv words.
+__global__ __launch_bounds__(64) void pivot_count_kernel(const unsigned long long* __restrict__ argkey, int64_t n,
+                                                         uint32_t npiv, uint32_t* __restrict__ cnt) {
+  extern __shared__ uint32_t h[];
+  const int64_t nb = gridDim.x, b = blockIdx.x;
+  for (uint32_t p = threadIdx.x; p < npiv; p += 64) h[p] = 0;
+  __syncthreads();
+  const int64_t lo = b * kPivChunk, hi = min(n, lo + kPivChunk);
+  for (int64_t t = lo + threadIdx.x; t < hi; t += 64) atomicAdd(&h[pivot_of(argkey[t], npiv)], 1u);
+  __syncthreads();
+  for (uint32_t p = threadIdx.x; p < npiv; p += 64) cnt[(int64_t)p * nb + b] = h[p];
+}
+
+// Pass 2: rows in row order, 64 at a time; the lanes holding the same pivot
+// find each other with one ballot per pivot bit, take consecutive slots
+// from the pivot's cursor in lane order, and the lowest of them advances
+// the cursor.  perm[slot] = row, so perm lists the rows by (pivot, row).
+// LDS: npiv words.
+__global__ __launch_bounds__(64) void pivot_place_kernel(const unsigned long long* __restrict__ argkey, int64_t n,
+                                                         uint32_t npiv, int pbits, const uint32_t* __restrict__ off,
+                                                         uint32_t* __restrict__ perm) {
+  extern __shared__ uint32_t cur[];
+  const int64_t nb = gridDim.x, b = blockIdx.x;
+  const int lane = threadIdx.x;
+  for (uint32_t p = lane; p < npiv; p += 64) cur[p] = off[(int64_t)p * nb + b];
+  __syncthreads();
+  const int64_t lo = b * kPivChunk, hi = min(n, lo + kPivChunk);
+  const uint64_t lower = (1ull << lane) - 1;  // lanes below this one
+  for (int64_t base = lo; base < hi; base += 64) {
+    const int64_t t = base + lane;
+    const bool valid = t < hi;
+    const uint32_t p = valid ? pivot_of(argkey[t], npiv) : 0u;
+    uint64_t peers = __ballot(valid);
+    for (int k = 0; k < pbits; ++k) {
+      const bool bit = (p >> k) & 1u;
+      const uint64_t on = __ballot(bit);
+      peers &= bit ? on : ~on;
+    }
+    if (valid) {
+      const uint32_t slot = cur[p] + (uint32_t)__popcll(peers & lower);
+      perm[slot] = (uint32_t)t;
+    }
+    // every lane has read its cursor before the group's lowest lane moves it
+    __builtin_amdgcn_wave_barrier();
+    if (valid && (peers & lower) == 0) cur[p] += (uint32_t)__popcll(peers);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -61,44 +114,83 @@ __global__ __launch_bounds__(256) void block_ball_kernel(const float* __restrict
                                                          const uint32_t* __restrict__ perm, int64_t n, int d,
                                                          double eps, float* __restrict__ cent,
                                                          double* __restrict__ Tb) {
-  extern __shared__ float c_lds[];  // d floats
+  extern __shared__ double ball_lds[];  // d doubles (the column sums), then d floats (the centroid)
   __shared__ double r2_wave[4];
+  __shared__ int64_t roff[kTile];       // the block's row offsets in X
   const int64_t b = blockIdx.x;
   const int64_t r0 = b * kTile;
   const int rows = (int)min((int64_t)kTile, n - r0);
-  __shared__ int64_t roff[kTile];  // the block's row offsets in X
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int r = threadIdx.x; r < rows; r += blockDim.x) roff[r] = (int64_t)perm[r0 + r] * ld;
+  for (int k = threadIdx.x; k < d; k += blockDim.x) ball_lds[k] = 0.0;
   __syncthreads();
-  for (int k = threadIdx.x; k < d; k += blockDim.x) {
-    // eight rows' loads in flight, added in row order
-    double s = 0.0;
-    int r = 0;
-    for (; r + 8 <= rows; r += 8) {
-      float v[8];
+  // column sums: wave w takes rows w, w + 4, ...; lane l columns l, l + 64,
+  // ... in groups of kCols (kCols loads of each of two rows in flight); the
+  // waves' partial sums are added in wave order, one wave at a time
+  constexpr int kCols = 8;
+  for (int k0 = 0; k0 < d; k0 += 64 * kCols) {
+    double s[kCols];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = X[roff[r + u] + k];
+    for (int u = 0; u < kCols; ++u) s[u] = 0.0;
+    int r = wave;
+    for (; r + 4 < rows; r += 8) {
+      const float* x0 = X + roff[r];
+      const float* x1 = X + roff[r + 4];
+      float v0[kCols], v1[kCols];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) s += (double)v[u];
+      for (int u = 0; u < kCols; ++u) {
+        const int k = k0 + lane + 64 * u;
+        v0[u] = k < d ? x0[k] : 0.0f;
+        v1[u] = k < d ? x1[k] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < kCols; ++u) s[u] += (double)v0[u] + (double)v1[u];
     }
-    for (; r < rows; ++r) s += (double)X[roff[r] + k];
-    const float c = (float)(s / (double)rows);
-    c_lds[k] = c;
+    if (r < rows) {
+      const float* x0 = X + roff[r];
+#pragma unroll
+      for (int u = 0; u < kCols; ++u) {
+        const int k = k0 + lane + 64 * u;
+        s[u] += k < d ? (double)x0[k] : 0.0;
+      }
+    }
+    for (int w = 0; w < 4; ++w) {
+      if (wave == w) {
+#pragma unroll
+        for (int u = 0; u < kCols; ++u) {
+          const int k = k0 + lane + 64 * u;
+          if (k < d) ball_lds[k] += s[u];
+        }
+      }
+      __syncthreads();
+    }
+  }
+  float* c_lds = reinterpret_cast<float*>(ball_lds + d);
+  for (int k = threadIdx.x; k < d; k += blockDim.x) {
+    const float c = (float)(ball_lds[k] / (double)rows);
     cent[b * (int64_t)d + k] = c;
+    c_lds[k] = c;
   }
   __syncthreads();
-  // one wave per row: lanes over k, a float64 sum per row, the block maximum
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // one wave per row (two rows in flight): lanes over k, a float64 sum per
+  // row, the block maximum
   double r2max = 0.0;
-  for (int r = wave; r < rows; r += 4) {
-    const float* x = X + roff[r];
-    double s = 0.0;
+  for (int r = wave; r < rows; r += 8) {
+    const float* x0 = X + roff[r];
+    const float* x1 = r + 4 < rows ? X + roff[r + 4] : x0;
+    double s0 = 0.0, s1 = 0.0;
     for (int k = lane; k < d; k += 64) {
-      const double t = (double)x[k] - (double)c_lds[k];
-      s += t * t;
+      const double c = (double)c_lds[k];
+      const double t0 = (double)x0[k] - c, t1 = (double)x1[k] - c;
+      s0 += t0 * t0;
+      s1 += t1 * t1;
     }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    r2max = fmax(r2max, s);
+    for (int o = 32; o > 0; o >>= 1) {
+      s0 += __shfl_xor(s0, o, 64);
+      s1 += __shfl_xor(s1, o, 64);
+    }
+    r2max = fmax(r2max, fmax(s0, s1));
   }
   if (lane == 0) r2_wave[wave] = r2max;
   __syncthreads();
@@ -172,6 +264,94 @@ __global__ void group_list_kernel(const uint32_t* __restrict__ surv, int64_t sw,
   }
 }
 
+// K-step masks of one operand copy (rows of qld bytes, zero-padded to whole
+// tiles): bit s of mask[t] is set when some row of tile t has a nonzero byte
+// in bytes [s * kChunkBytes, (s + 1) * kChunkBytes) of its row, i.e. in the
+// candidate pass's K-step s.  A negative zero counts as nonzero, which only
+// keeps a step.  One workgroup per tile; qld / kChunkBytes <= 64.
+__global__ __launch_bounds__(256) void tile_kmask_kernel(const uint8_t* __restrict__ q, int64_t qld,
+                                                         uint64_t* __restrict__ mask) {
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  __shared__ uint32_t part[2][4];
+  const u32x4* base = reinterpret_cast<const u32x4*>(q + (int64_t)blockIdx.x * kTile * qld);
+  const uint32_t per_row = (uint32_t)(qld / 16), pieces = (uint32_t)kTile * per_row;
+  uint64_t m = 0;
+  for (uint32_t t = threadIdx.x; t < pieces; t += 256) {
+    const u32x4 v = __builtin_nontemporal_load(base + t);
+    if (v.x | v.y | v.z | v.w) m |= 1ull << ((t % per_row) / (kChunkBytes / 16));
+  }
+  uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lo |= __shfl_xor(lo, o, 64);
+    hi |= __shfl_xor(hi, o, 64);
+  }
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    part[0][wave] = lo;
+    part[1][wave] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    mask[blockIdx.x] = (uint64_t)(part[0][0] | part[0][1] | part[0][2] | part[0][3]) |
+                       ((uint64_t)(part[1][0] | part[1][1] | part[1][2] | part[1][3]) << 32);
+}
+
+// The K-steps the candidate pass runs with the masks: the sum over the tile
+// list (or over the grid, a self-join's upper triangle, when 2 * *ntiles >=
+// list_all, as the candidate pass decides) of popcount(maskA[ti] &
+// maskB[tj]), at least 1 per tile, added to *out.
+__global__ __launch_bounds__(256) void kstep_count_kernel(const uint2* __restrict__ tiles,
+                                                          const unsigned long long* __restrict__ ntiles,
+                                                          int64_t list_all, int64_t nTR, int64_t nTS, int self,
+                                                          const uint64_t* __restrict__ ma,
+                                                          const uint64_t* __restrict__ mb,
+                                                          unsigned long long* __restrict__ out) {
+  __shared__ unsigned long long part[4];
+  const int64_t nl = (int64_t)*ntiles;
+  const bool list = 2 * nl < list_all;
+  const int64_t n = list ? nl : nTR * nTS;
+  unsigned long long c = 0;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    int64_t ti, tj;
+    if (list) {
+      ti = tiles[t].x;
+      tj = tiles[t].y;
+    } else {
+      ti = t / nTS;
+      tj = t - ti * nTS;
+      if (self && tj < ti) continue;
+    }
+    const uint64_t m = ma[ti] & mb[tj];
+    c += m ? __popcll(m) : 1;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(out, part[0] + part[1] + part[2] + part[3]);
+}
+
+hipError_t launch_tile_kmask(const void* q, int64_t qld, int64_t ntiles, uint64_t* mask, hipStream_t st) {
+  if (ntiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(tile_kmask_kernel, dim3((unsigned)ntiles), dim3(256), 0, st, static_cast<const uint8_t*>(q), qld,
+                     mask);
+  return hipGetLastError();
+}
+
+// *out must be zero beforehand.
+hipError_t launch_kstep_count(const uint2* tiles, const unsigned long long* ntiles, int64_t list_all, int64_t nTR,
+                              int64_t nTS, int self, const uint64_t* ma, const uint64_t* mb, unsigned long long* out,
+                              hipStream_t st, int cu) {
+  const int64_t n = nTR * nTS;  // at least the list's length
+  int64_t g = (n + 255) / 256;
+  if (g > (int64_t)cu * 4) g = (int64_t)cu * 4;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(kstep_count_kernel, dim3((unsigned)g), dim3(256), 0, st, tiles, ntiles, list_all, nTR, nTS, self,
+                     ma, mb, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_gather_rows(const float* X, int64_t ld, int64_t stride, int64_t m, int d, float* out,
                               hipStream_t st, int cu) {
   if (m == 0) return hipSuccess;
@@ -182,13 +362,28 @@ hipError_t launch_gather_rows(const float* X, int64_t ld, int64_t stride, int64_
   return hipGetLastError();
 }
 
-hipError_t launch_pivot_keys(const unsigned long long* argkey, int64_t n, int64_t npiv, int bj,
-                             unsigned long long* keys, float* vals, hipStream_t st, int cu) {
+int64_t pivot_sort_words(int64_t n, int64_t npiv) {
+  const int64_t m = (n + kPivChunk - 1) / kPivChunk * npiv;
+  return 2 * m + scan_scratch_words(m) + 1;
+}
+
+// perm[q] = the q-th row of X in (nearest pivot, row) order.  scratch:
+// pivot_sort_words(n, npiv) words; npiv <= 4096.
+hipError_t launch_pivot_sort(const unsigned long long* argkey, int64_t n, int64_t npiv, uint32_t* perm,
+                             uint32_t* scratch, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  int64_t g = (n + 255) / 256;
-  if (g > (int64_t)cu * 8) g = (int64_t)cu * 8;
-  hipLaunchKernelGGL(pivot_keys_kernel, dim3((unsigned)g), dim3(256), 0, st, argkey, n, (uint32_t)npiv, bj, keys,
-                     vals);
+  const int64_t nb = (n + kPivChunk - 1) / kPivChunk, m = nb * npiv;
+  uint32_t* cnt = scratch;
+  uint32_t* off = scratch + m;
+  uint32_t* sums = scratch + 2 * m;
+  int pbits = 0;
+  while ((1ll << pbits) < npiv) ++pbits;
+  const size_t lds = (size_t)npiv * sizeof(uint32_t);
+  hipLaunchKernelGGL(pivot_count_kernel, dim3((unsigned)nb), dim3(64), lds, st, argkey, n, (uint32_t)npiv, cnt);
+  hipError_t e = launch_exclusive_scan(cnt, m, off, sums, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(pivot_place_kernel, dim3((unsigned)nb), dim3(64), lds, st, argkey, n, (uint32_t)npiv, pbits, off,
+                     perm);
   return hipGetLastError();
 }
 
@@ -196,8 +391,8 @@ hipError_t launch_block_balls(const float* X, int64_t ld, const uint32_t* perm, 
                               float* cent, double* Tb, hipStream_t st) {
   const int64_t nb = (n + kTile - 1) / kTile;
   if (nb == 0) return hipSuccess;
-  hipLaunchKernelGGL(block_ball_kernel, dim3((unsigned)nb), dim3(256), (size_t)d * sizeof(float), st, X, ld, perm, n,
-                     d, eps, cent, Tb);
+  hipLaunchKernelGGL(block_ball_kernel, dim3((unsigned)nb), dim3(256), (size_t)d * (sizeof(double) + sizeof(float)),
+                     st, X, ld, perm, n, d, eps, cent, Tb);
   return hipGetLastError();
 }
 

@@ -204,17 +204,24 @@ struct TileIter {
   int64_t step = 0;                              // eps: logical round
   int64_t lim = -1;                              // eps: logical tiles
   int64_t ti = 0, split = 0, t = 0, t_end = 0;   // band
+  bool list = false;                             // eps: walking the tile list
   __device__ bool next(const CandParams& p, int mode, int64_t& oti, int64_t& otj) {
     const int64_t G = gridDim.x;
     const int64_t slot = (int64_t)(blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
     if (mode != kModeBand) {
-      if (lim < 0) lim = p.tiles ? uniform64((int64_t)*p.ntiles) : p.nlogical;
+      if (lim < 0) {
+        // a long list costs a cache-missing read per tile that the grid's
+        // order computes, so when most tiles are listed the grid is walked
+        const int64_t nl = p.tiles ? uniform64((int64_t)*p.ntiles) : 0;
+        list = p.tiles && (p.list_all == 0 || 2 * nl < p.list_all);
+        lim = list ? nl : p.nlogical;
+      }
       for (;;) {
         const int64_t L = step * G + slot;
         ++step;
         if (L >= lim) return false;
         int64_t ti_, tj_;
-        if (p.tiles) {
+        if (list) {
           const uint2 t2 = p.tiles[L];
           oti = uniform64((int64_t)t2.x);
           otj = uniform64((int64_t)t2.y);
@@ -244,6 +251,16 @@ struct TileIter {
     }
   }
 };
+
+// K-steps of tile (ti, tj), bit s for step s.  With the per-tile masks a
+// step where every row of one of the two tiles is zero is dropped: each of
+// its products is zero, and adding zero leaves every accumulator as it was
+// (the inputs are finite).  A tile keeps at least one step, whose products
+// are then all zero, so its epilogue still runs on the initial values.
+__device__ inline uint64_t tile_steps(const CandParams& p, int64_t ti, int64_t tj) {
+  const uint64_t m = p.kmaskA[ti] & p.kmaskB[tj];
+  return m ? m : 1ull;
+}
 
 // ----------------------------------------------------- operand movement
 // One K-step of both operand tiles, global -> LDS.  Each wave moves blocks
@@ -963,8 +980,14 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
   TileIter lit;
   int64_t ti, tj;
   if (!lit.next(p, kMode, ti, tj)) return;
+  // K-step masks (eps mode only): the loader issues a tile's set steps in
+  // order, and the compute side runs as many steps as the loader issued
+  const bool masked = kQ && p.kmaskA != nullptr;
   int64_t lti = ti, ltj = tj;  // tile of the loader's next step
   int64_t iti = ti, itj = tj;  // tile of the step issued last
+  uint64_t lrem = masked ? tile_steps(p, ti, tj) : 0;  // the loader tile's steps not yet issued
+  int lsteps = masked ? __builtin_popcountll(lrem) : nsteps;
+  int isteps = lsteps;  // steps of the tile of the step issued last
   int lstep = 0, ltile = 0, issued = 0;
   bool lmore = true;
   auto issue = [&]() {
@@ -974,14 +997,21 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
                                                       side_sb[kFp8 ? sb : 0]});
     }
     const int st = issued % Q::kStages;
-    issue_loads<kPrec, kMode>(p, lti, ltj, lstep, lds_ab[st][0], lds_ab[st][1]);
+    const int k = masked ? (int)__builtin_ctzll(lrem) : lstep;
+    issue_loads<kPrec, kMode>(p, lti, ltj, k, lds_ab[st][0], lds_ab[st][1]);
     iti = lti;
     itj = ltj;
+    isteps = lsteps;
     ++issued;
-    if (++lstep == nsteps) {
+    if (masked) lrem &= lrem - 1;
+    if (++lstep == lsteps) {
       lstep = 0;
       ++ltile;
       lmore = lit.next(p, kMode, lti, ltj);
+      if (masked && lmore) {
+        lrem = tile_steps(p, lti, ltj);
+        lsteps = __builtin_popcountll(lrem);
+      }
     }
   };
 
@@ -1018,6 +1048,7 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
   if constexpr (kEps) {
     // eps mode: one tile per pass; each K-step's last products are issued
     // after the next barrier (mma_step, kTailIn)
+    int tsteps = lsteps;  // K-steps of the current tile
     for (;;) {  // one tile per pass
       // ---- the tile's first K-step
       wait_and_sync(dirty ? 0 : (issued - step - 1) * kPerStep);
@@ -1044,7 +1075,7 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
       }
       ++step;
       // ---- its other K-steps
-      for (int c = 1; c < nsteps; ++c) {
+      for (int c = 1; c < tsteps; ++c) {
         wait_and_sync(dirty ? 0 : (issued - step - 1) * kPerStep);
         dirty = false;
         more = lmore;
@@ -1067,6 +1098,7 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
       if (!more) break;
       ti = iti;  // the step just issued opens the next tile
       tj = itj;
+      tsteps = isteps;
       ++ctile;
     }
   } else {
@@ -1166,19 +1198,15 @@ static void div_magic(uint32_t d, uint32_t& m, uint32_t& s1, uint32_t& s2) {
 
 // eps mode over a device tile list (p.tiles, *p.ntiles entries): persistent
 // workgroups, one per CU, walk the list; mark = the bound pass (every tile).
-hipError_t launch_cand_list(dl_prec prec, CandParams p, hipStream_t st, int cu_count) {
-  p.nTR = (p.nR + kTile - 1) / kTile;
-  p.nTS = (p.nS + kTile - 1) / kTile;
-  if (p.nTR == 0 || p.nTS == 0 || !p.tiles) return hipSuccess;
-  p.GM = 1;
-  p.ngroups = p.nTR;
-  p.nlogical = 0;
-  p.small32 = 0;
-  const int64_t G = (cu_count + 7) / 8 * 8;
-  return launch_mode<kModeEps>(prec, p, dim3((unsigned)G), st);
-}
-
 static hipError_t launch_eps_like(dl_prec prec, CandParams p, hipStream_t st, int cu_count, int mode);
+
+// The eps pass over the tile list p.tiles (length *p.ntiles, on the device),
+// or over the full grid when p.list_all is set and 2 * *p.ntiles >= it; the
+// grid's set-up is made either way, the kernel picks.
+hipError_t launch_cand_list(dl_prec prec, CandParams p, hipStream_t st, int cu_count) {
+  if (!p.tiles) return hipSuccess;
+  return launch_eps_like(prec, p, st, cu_count, kModeEps);
+}
 
 hipError_t launch_cand_mark(dl_prec prec, CandParams p, hipStream_t st, int cu_count) {
   p.tiles = nullptr;

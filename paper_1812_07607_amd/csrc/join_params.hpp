@@ -54,11 +54,18 @@ struct CandParams {
   // device-side count; null = every tile
   const uint2* tiles;
   const unsigned long long* ntiles;
+  int64_t list_all;    // nonzero: walk the list only if 2 * *ntiles < list_all, else the full grid
   // mark mode: bit (tile tj, row i) at mark[tj * mark_words + i / 32]
   uint32_t* mark;
   int64_t mark_words;
   // nearest mode: per row, the maximum of (order key of P~ << 32 | ~column)
   unsigned long long* argkey;
+  // eps mode (nullable, at most 64 K-steps): per tile of each operand, bit s
+  // set when some row of the tile has a nonzero byte in K-step s.  A step
+  // that is zero in every row of either tile adds only zero products and is
+  // skipped.
+  const uint64_t* kmaskA;
+  const uint64_t* kmaskB;
 };
 
 // eps-join recheck (recheck.hip).

@@ -221,6 +221,8 @@ class IndexInfo:
     tiles_total: int     # 256 x 256 tiles of the join (self-join: upper triangle)
     tiles_computed: int  # tiles the candidate pass ran on
     pivots: int          # 0: no index was built (the plain join ran)
+    ksteps_per_tile: int = 0  # K-steps (128 operand bytes per row) of a full tile
+    ksteps_computed: int = 0  # K-steps run: steps zero in every row of either tile are skipped
 
 
 def join_eps_indexed(R: torch.Tensor, S: torch.Tensor | None, eps: float, prec: str = "bf16", pivots: int = 0,
@@ -238,6 +240,9 @@ def join_eps_indexed(R: torch.Tensor, S: torch.Tensor | None, eps: float, prec: 
     if max_candidates is None:
         max_candidates = max(1 << 20, 4 * (nR + nS))
     cap = capacity if capacity is not None else max(1 << 16, nR + nS)
+    key = ("indexed", nR, nS, d, p, self_join, float(eps), int(pivots))
+    if capacity is None:
+        cap = max(cap, c.eps_caps.get(key, 0))
     info = _lib.dl_index_info()
     for _ in range(8):
         need = c.L.dl_join_eps_indexed_workspace(nR, nS, d, p, int(self_join), max_candidates, pivots)
@@ -257,8 +262,11 @@ def join_eps_indexed(R: torch.Tensor, S: torch.Tensor | None, eps: float, prec: 
             continue
         c.check(st)
         m = int(pr.count)
+        if capacity is None:
+            c.eps_caps[key] = cap
         return (EpsResult(oi[:m], oj[:m], od[:m], m, int(pr.candidates), int(pr.ties)),
-                IndexInfo(int(info.tiles_total), int(info.tiles_computed), int(info.pivots)))
+                IndexInfo(int(info.tiles_total), int(info.tiles_computed), int(info.pivots),
+                          int(info.ksteps_per_tile), int(info.ksteps_computed)))
     raise RuntimeError("join_eps_indexed did not converge on workspace / capacity")
 
 
@@ -283,6 +291,9 @@ def join_eps_filtered(R: torch.Tensor, S: torch.Tensor | None, eps: float, label
     if max_pairs is None:
         max_pairs = max(1 << 20, 4 * (nR + nS))
     cap = capacity if capacity is not None else max(1 << 16, nR + nS)
+    key = ("filtered", nR, nS, d, p, self_join, float(eps), int(label), pl)
+    if capacity is None:
+        cap = max(cap, c.eps_caps.get(key, 0))
     for _ in range(10):
         need = c.L.dl_join_eps_filtered_workspace(nR, nS, d, p, int(self_join), pl, max_candidates, max_pairs)
         buf = ws.get(need)
@@ -303,6 +314,8 @@ def join_eps_filtered(R: torch.Tensor, S: torch.Tensor | None, eps: float, label
             continue
         c.check(st)
         m = int(pr.count)
+        if capacity is None:
+            c.eps_caps[key] = cap
         return EpsResult(oi[:m], oj[:m], od[:m], m, int(pr.candidates), int(pr.ties))
     raise RuntimeError("join_eps_filtered did not converge on workspace / capacity")
 

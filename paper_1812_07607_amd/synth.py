@@ -171,6 +171,29 @@ def gaussian_mixture_unit(n, d, n_centres, sigma=0.05, seed=303, stream=0):
     return out
 
 
+def block_sparse_rows(n, d=512, groups=8, sigma=0.1, faint=0.1, faint_norm=0.05, seed=0, stream=0):
+    """Rows nonzero only inside one of `groups` equal blocks of coordinates
+    (like colour histograms whose mass sits in a few bins): row x of group g
+    is (mu_g + sigma z) restricted to block g, normalised to unit length, mu_g
+    a unit vector inside block g drawn from the seed alone; a fraction
+    `faint` of the rows is then scaled to length `faint_norm`, so rows of
+    different blocks can still lie close together.  float32."""
+    rc = _rng(seed, 0)
+    w = d // groups
+    mu = rc.standard_normal((groups, w))
+    mu /= np.linalg.norm(mu, axis=1, keepdims=True)
+    r = _rng(seed, 40 + stream)
+    g = r.integers(0, groups, size=n)
+    x = mu[g] + sigma * r.standard_normal((n, w))
+    x /= np.linalg.norm(x, axis=1, keepdims=True)
+    x[r.random(n) < faint] *= faint_norm
+    out = np.zeros((n, d), np.float32)
+    for k in range(groups):
+        rows = np.nonzero(g == k)[0]
+        out[rows, k * w:(k + 1) * w] = x[rows]
+    return out
+
+
 def uniform_rows(n, d, lo=-1.0, hi=1.0, seed=0, stream=0):
     """Independent uniform float32 rows (no structure)."""
     return _rng(seed, 20 + stream).uniform(lo, hi, size=(n, d)).astype(np.float32)

@@ -50,6 +50,46 @@ def test_mixture_join_indexed(orc, prec):
         assert info.tiles_computed <= info.tiles_total == 12 * 20
 
 
+@pytest.mark.parametrize("prec", PRECS)
+def test_block_sparse_rows_skip_ksteps(orc, prec):
+    """Rows nonzero in one of 8 blocks of 64 coordinates, 10% of them faint
+    (length 0.05): K-steps that are zero in every row of a tile are skipped
+    and the pairs are still the oracle's.  eps = 0.12 holds every faint
+    pair, whatever their blocks (products all zero); eps = 1.5 holds every
+    pair of rows of different blocks (d^2 = 2 from the norms alone), so
+    every tile survives, the full grid runs with the masks, and tiles of two
+    different blocks run a single all-zero step."""
+    R = synth.block_sparse_rows(1200, seed=71)
+    S = synth.block_sparse_rows(1100, seed=71, stream=1)
+    pairs = synth.sample_pairs(1200, 1100, 20000, False, seed=72)
+    for eps in (0.12, eps_quantile(orc, R, S, pairs, 0.01), 1.5):
+        ref = orc.eps_join(R, S, eps)
+        got, info = ops.join_eps_indexed(dev(R), dev(S), eps, prec, pivots=16)
+        assert_eps_equal(got, ref, 512, "block-sparse eps=%g/%s" % (eps, prec))
+        assert info.ksteps_per_tile == {"fp32": 16, "bf16": 8, "fp16": 8, "fp8": 4}[prec]
+        assert info.ksteps_computed < info.tiles_computed * info.ksteps_per_tile, info
+    X = synth.block_sparse_rows(1500, seed=73)
+    for eps in (0.12, 1.5):
+        ref = orc.eps_join(X, None, eps)
+        got, info = ops.join_eps_indexed(dev(X), None, eps, prec, pivots=16)
+        assert_eps_equal(got, ref, 512, "block-sparse self eps=%g/%s" % (eps, prec))
+        assert info.ksteps_computed < info.tiles_computed * info.ksteps_per_tile, info
+
+
+def test_histogram_ksteps_skipped(orc):
+    """On palette histograms ordered by pivot, a tile's rows mostly share a
+    colour, and some of the 8 K-steps (64 bins, one red level, each in fp16)
+    of a computed tile are zero on one side (noise spreads a patch over
+    several red levels, so most steps stay)."""
+    cfg = synth.config2(0.08)
+    H = orc.hist_rgb8(cfg["patches"], 8)
+    eps = eps_quantile(orc, H, H, cfg["pairs"], cfg["q"])
+    got, info = ops.join_eps_indexed(dev(H), None, eps, "fp16")
+    assert_eps_equal(got, orc.eps_join(H, None, eps), 512, "histogram ksteps")
+    assert info.ksteps_per_tile == 8
+    assert info.ksteps_computed < info.tiles_computed * 8, info
+
+
 @pytest.mark.parametrize("shape", [(513, 1000, 1), (700, 2049, 129), (1500, 600, 300)])
 def test_ragged_shapes_indexed(orc, shape):
     nR, nS, d = shape
