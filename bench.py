@@ -751,6 +751,12 @@ def main():
     roof = {"kernel": "cand_kernel<%s, eps>" % args.prec, "bound": "mfma", "achieved": achieved, "peak": peak,
             "unit": "TFLOP/s", "frac": achieved / peak, "traffic": measured_traffic(args.prec, workload),
             "flops_per_launch": flops, "avg_launch_ms": c_avg}
+    # the achievable rates of this device (register-operand matrix-core loop,
+    # 1 GiB copy), measured once after the timed steps: the second denominator
+    progress("measured peaks")
+    peaks = ops.measure_peaks()
+    roof["measured_peak"] = peaks[args.prec]
+    roof["frac_of_measured_peak"] = achieved / peaks[args.prec]
     res = {
         "metric": METRIC, "value": value, "unit": "G distance-pairs/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
@@ -764,6 +770,10 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3)},
         "stages_ms_per_step": {k: v[0] / max(args.steps, 1) for k, v in stages.items() if v[1]},
         "roofline": roof,
+        "measured_peaks": {"mfma_tflops": {k: peaks[k] for k in ("fp32", "bf16", "fp16", "fp8")},
+                           "hbm_copy_GBps": peaks["hbm_copy_GBps"],
+                           "how": "dl_measure_peaks: 8 independent MFMA chains per wave, 32 waves per CU, register "
+                                  "operands; a 1 GiB device copy (bytes read + written)"},
     }
     if not args.no_extras:
         if args.prec != "fp32":

@@ -466,6 +466,24 @@ dl_status dl_server_reset_stats(dl_server* srv);
 /* Cancels queued requests, waits for running batches, stops the workers. */
 void dl_server_destroy(dl_server* srv);
 
+/* ------------------------------------------------------------ measurement */
+
+/* Achievable rates of this device, measured: the denominators of roofline
+ * fractions beside the published peaks.  Not a step of the method; the
+ * benchmark calls it once. */
+typedef struct dl_peaks {
+  double mfma_fp32_tflops; /* dense matrix-core rate of each operand format on */
+  double mfma_bf16_tflops; /* register operands: v_mfma_f32_16x16x4f32,         */
+  double mfma_fp16_tflops; /* v_mfma_f32_16x16x32_{bf16,f16} and the E4M3       */
+  double mfma_fp8_tflops;  /* v_mfma_scale_f32_16x16x128_f8f6f4, 8 chains/wave  */
+  double hbm_copy_gbps;    /* a 1 GiB device copy: bytes read + written per s   */
+} dl_peaks;
+
+/* Runs the rate kernels on the context's device (default stream; it
+ * allocates and frees 2 GiB of device memory and synchronises).  About
+ * 0.1 s. */
+dl_status dl_measure_peaks(dl_ctx* ctx, dl_peaks* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -39,6 +39,12 @@ class dl_index_info(ctypes.Structure):
                 ("ksteps_per_tile", ctypes.c_int32), ("ksteps_computed", ctypes.c_int64)]
 
 
+class dl_peaks(ctypes.Structure):
+    _fields_ = [("mfma_fp32_tflops", ctypes.c_double), ("mfma_bf16_tflops", ctypes.c_double),
+                ("mfma_fp16_tflops", ctypes.c_double), ("mfma_fp8_tflops", ctypes.c_double),
+                ("hbm_copy_gbps", ctypes.c_double)]
+
+
 class dl_topk_info(ctypes.Structure):
     _fields_ = [("band_entries", ctypes.c_int64), ("ties", ctypes.c_int64)]
 
@@ -119,6 +125,7 @@ SIGNATURES = {
     "dl_server_stats": (ctypes.c_int, [P, ctypes.POINTER(dl_server_info)]),
     "dl_server_reset_stats": (ctypes.c_int, [P]),
     "dl_server_destroy": (None, [P]),
+    "dl_measure_peaks": (ctypes.c_int, [P, ctypes.POINTER(dl_peaks)]),
 }
 
 _lib = None

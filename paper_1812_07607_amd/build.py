@@ -30,7 +30,7 @@ FLAGS = [
     "-I" + INCLUDE, "-I" + CSRC,
 ]
 SOURCES = ["api.hip", "featurize.hip", "prep.hip", "join_mfma.hip", "recheck.hip", "sort.hip", "serve.hip",
-           "index.hip", "plan.hip"]
+           "index.hip", "plan.hip", "peak.hip"]
 
 
 def _compile(src: str) -> str:

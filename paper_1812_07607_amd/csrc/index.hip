@@ -114,83 +114,44 @@ __global__ __launch_bounds__(256) void block_ball_kernel(const float* __restrict
                                                          const uint32_t* __restrict__ perm, int64_t n, int d,
                                                          double eps, float* __restrict__ cent,
                                                          double* __restrict__ Tb) {
-  extern __shared__ double ball_lds[];  // d doubles (the column sums), then d floats (the centroid)
+  extern __shared__ float c_lds[];  // d floats
   __shared__ double r2_wave[4];
-  __shared__ int64_t roff[kTile];       // the block's row offsets in X
   const int64_t b = blockIdx.x;
   const int64_t r0 = b * kTile;
   const int rows = (int)min((int64_t)kTile, n - r0);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __shared__ int64_t roff[kTile];  // the block's row offsets in X
   for (int r = threadIdx.x; r < rows; r += blockDim.x) roff[r] = (int64_t)perm[r0 + r] * ld;
-  for (int k = threadIdx.x; k < d; k += blockDim.x) ball_lds[k] = 0.0;
   __syncthreads();
-  // column sums: wave w takes rows w, w + 4, ...; lane l columns l, l + 64,
-  // ... in groups of kCols (kCols loads of each of two rows in flight); the
-  // waves' partial sums are added in wave order, one wave at a time
-  constexpr int kCols = 8;
-  for (int k0 = 0; k0 < d; k0 += 64 * kCols) {
-    double s[kCols];
-#pragma unroll
-    for (int u = 0; u < kCols; ++u) s[u] = 0.0;
-    int r = wave;
-    for (; r + 4 < rows; r += 8) {
-      const float* x0 = X + roff[r];
-      const float* x1 = X + roff[r + 4];
-      float v0[kCols], v1[kCols];
-#pragma unroll
-      for (int u = 0; u < kCols; ++u) {
-        const int k = k0 + lane + 64 * u;
-        v0[u] = k < d ? x0[k] : 0.0f;
-        v1[u] = k < d ? x1[k] : 0.0f;
-      }
-#pragma unroll
-      for (int u = 0; u < kCols; ++u) s[u] += (double)v0[u] + (double)v1[u];
-    }
-    if (r < rows) {
-      const float* x0 = X + roff[r];
-#pragma unroll
-      for (int u = 0; u < kCols; ++u) {
-        const int k = k0 + lane + 64 * u;
-        s[u] += k < d ? (double)x0[k] : 0.0;
-      }
-    }
-    for (int w = 0; w < 4; ++w) {
-      if (wave == w) {
-#pragma unroll
-        for (int u = 0; u < kCols; ++u) {
-          const int k = k0 + lane + 64 * u;
-          if (k < d) ball_lds[k] += s[u];
-        }
-      }
-      __syncthreads();
-    }
-  }
-  float* c_lds = reinterpret_cast<float*>(ball_lds + d);
   for (int k = threadIdx.x; k < d; k += blockDim.x) {
-    const float c = (float)(ball_lds[k] / (double)rows);
-    cent[b * (int64_t)d + k] = c;
+    // eight rows' loads in flight, added in row order
+    double s = 0.0;
+    int r = 0;
+    for (; r + 8 <= rows; r += 8) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = X[roff[r + u] + k];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += (double)v[u];
+    }
+    for (; r < rows; ++r) s += (double)X[roff[r] + k];
+    const float c = (float)(s / (double)rows);
     c_lds[k] = c;
+    cent[b * (int64_t)d + k] = c;
   }
   __syncthreads();
-  // one wave per row (two rows in flight): lanes over k, a float64 sum per
-  // row, the block maximum
+  // one wave per row: lanes over k, a float64 sum per row, the block maximum
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double r2max = 0.0;
-  for (int r = wave; r < rows; r += 8) {
-    const float* x0 = X + roff[r];
-    const float* x1 = r + 4 < rows ? X + roff[r + 4] : x0;
-    double s0 = 0.0, s1 = 0.0;
+  for (int r = wave; r < rows; r += 4) {
+    const float* x = X + roff[r];
+    double s = 0.0;
     for (int k = lane; k < d; k += 64) {
-      const double c = (double)c_lds[k];
-      const double t0 = (double)x0[k] - c, t1 = (double)x1[k] - c;
-      s0 += t0 * t0;
-      s1 += t1 * t1;
+      const double t = (double)x[k] - (double)c_lds[k];
+      s += t * t;
     }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      s0 += __shfl_xor(s0, o, 64);
-      s1 += __shfl_xor(s1, o, 64);
-    }
-    r2max = fmax(r2max, fmax(s0, s1));
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    r2max = fmax(r2max, s);
   }
   if (lane == 0) r2_wave[wave] = r2max;
   __syncthreads();
@@ -276,7 +237,17 @@ __global__ __launch_bounds__(256) void tile_kmask_kernel(const uint8_t* __restri
   const u32x4* base = reinterpret_cast<const u32x4*>(q + (int64_t)blockIdx.x * kTile * qld);
   const uint32_t per_row = (uint32_t)(qld / 16), pieces = (uint32_t)kTile * per_row;
   uint64_t m = 0;
-  for (uint32_t t = threadIdx.x; t < pieces; t += 256) {
+  constexpr int kUnroll = 8;  // loads in flight per thread
+  uint32_t t = threadIdx.x;
+  for (; t + (kUnroll - 1) * 256 < pieces; t += kUnroll * 256) {
+    u32x4 v[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) v[u] = __builtin_nontemporal_load(base + t + u * 256);
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+      if (v[u].x | v[u].y | v[u].z | v[u].w) m |= 1ull << (((t + u * 256) % per_row) / (kChunkBytes / 16));
+  }
+  for (; t < pieces; t += 256) {
     const u32x4 v = __builtin_nontemporal_load(base + t);
     if (v.x | v.y | v.z | v.w) m |= 1ull << ((t % per_row) / (kChunkBytes / 16));
   }
@@ -391,8 +362,8 @@ hipError_t launch_block_balls(const float* X, int64_t ld, const uint32_t* perm, 
                               float* cent, double* Tb, hipStream_t st) {
   const int64_t nb = (n + kTile - 1) / kTile;
   if (nb == 0) return hipSuccess;
-  hipLaunchKernelGGL(block_ball_kernel, dim3((unsigned)nb), dim3(256), (size_t)d * (sizeof(double) + sizeof(float)),
-                     st, X, ld, perm, n, d, eps, cent, Tb);
+  hipLaunchKernelGGL(block_ball_kernel, dim3((unsigned)nb), dim3(256), (size_t)d * sizeof(float), st, X, ld, perm, n,
+                     d, eps, cent, Tb);
   return hipGetLastError();
 }
 

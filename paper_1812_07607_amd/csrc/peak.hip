@@ -1,0 +1,180 @@
+// peak.hip -- achievable rates of this device, the second denominator of the
+// roofline fractions beside the published peaks: the matrix-core rate of each
+// operand format on register operands (no memory traffic; the same MFMA
+// instructions as the candidate pass), and the HBM rate of a streaming copy.
+#include "dl_internal.hpp"
+
+namespace dl {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kChains = 8;        // independent accumulators per wave
+constexpr int kPeakThreads = 256;
+constexpr int kPeakBlocksPerCU = 8;  // 32 waves per CU
+
+// flop of one MFMA instruction of each format
+constexpr double mfma_flop(int prec) {
+  return prec == DL_FP32 ? 2.0 * 16 * 16 * 4 : prec == DL_FP8 ? 2.0 * 16 * 16 * 128 : 2.0 * 16 * 16 * 32;
+}
+
+// kChains independent chains of `iters` MFMAs per wave; operands are small
+// values derived from `seed`, so nothing folds, nothing overflows and no
+// value is subnormal.  One float per wave is stored.
+template <int kPrec>
+__global__ __launch_bounds__(kPeakThreads) void mfma_peak_kernel(int iters, float seed, float* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const float x = seed * (float)(1 + (lane & 7));  // in [2^-8, 2^-5]
+  f32x4 acc[kChains];
+#pragma unroll
+  for (int c = 0; c < kChains; ++c) acc[c] = f32x4{x * c, x * c, x * c, x * c};  // distinct chains: none merges
+  if constexpr (kPrec == DL_BF16) {
+    bf16x8 a, b;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      a[e] = (__bf16)x;
+      b[e] = (__bf16)(x * 0.5f);
+    }
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+      for (int c = 0; c < kChains; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[c], 0, 0, 0);
+    }
+  } else if constexpr (kPrec == DL_FP16) {
+    f16x8 a, b;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      a[e] = (_Float16)x;
+      b[e] = (_Float16)(x * 0.5f);
+    }
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+      for (int c = 0; c < kChains; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, acc[c], 0, 0, 0);
+    }
+  } else if constexpr (kPrec == DL_FP8) {
+    // E4M3 0x20 = 2^-3 in every byte; unit scales (E8M0 127)
+    i32x8 a, b;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      a[e] = 0x20202020;
+      b[e] = 0x20202020;
+    }
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+      for (int c = 0; c < kChains; ++c)
+        acc[c] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, acc[c], 0, 0, 0, 127, 0, 127);
+    }
+  } else {
+    const float a = x, b = x * 0.5f;
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+      for (int c = 0; c < kChains; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[c], 0, 0, 0);
+    }
+  }
+  float s = 0.0f;
+#pragma unroll
+  for (int c = 0; c < kChains; ++c) s += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
+  if (lane == 0) out[(blockIdx.x * kPeakThreads + threadIdx.x) >> 6] = s;
+}
+
+// Streaming copy, 16 bytes per lane per load, four loads in flight.
+__global__ __launch_bounds__(256) void copy_peak_kernel(const u32x4* __restrict__ src, u32x4* __restrict__ dst,
+                                                        int64_t n16) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; t + 3 * stride < n16; t += 4 * stride) {
+    const u32x4 v0 = __builtin_nontemporal_load(src + t);
+    const u32x4 v1 = __builtin_nontemporal_load(src + t + stride);
+    const u32x4 v2 = __builtin_nontemporal_load(src + t + 2 * stride);
+    const u32x4 v3 = __builtin_nontemporal_load(src + t + 3 * stride);
+    __builtin_nontemporal_store(v0, dst + t);
+    __builtin_nontemporal_store(v1, dst + t + stride);
+    __builtin_nontemporal_store(v2, dst + t + 2 * stride);
+    __builtin_nontemporal_store(v3, dst + t + 3 * stride);
+  }
+  for (; t < n16; t += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + t), dst + t);
+}
+
+// Milliseconds of one launch of `launch` (after one untimed launch).
+template <class F>
+hipError_t time_launch(F launch, float* ms) {
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  if (e == hipSuccess) {
+    launch();
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipEventRecord(a, nullptr);
+  if (e == hipSuccess) {
+    launch();
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipEventRecord(b, nullptr);
+  if (e == hipSuccess) e = hipEventSynchronize(b);
+  if (e == hipSuccess) e = hipEventElapsedTime(ms, a, b);
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  return e;
+}
+
+template <int kPrec>
+hipError_t mfma_rate(int cu, float* wave_out, double* tflops) {
+  // about 10 ms per launch at the published rate
+  const int iters = kPrec == DL_FP32 ? 12000 : kPrec == DL_FP8 ? 12000 : 24000;
+  const int blocks = cu * kPeakBlocksPerCU;
+  float ms = 0.0f;
+  hipError_t e = time_launch(
+      [&]() {
+        hipLaunchKernelGGL(mfma_peak_kernel<kPrec>, dim3(blocks), dim3(kPeakThreads), 0, nullptr, iters, 0x1p-8f,
+                           wave_out);
+      },
+      &ms);
+  if (e != hipSuccess) return e;
+  const double flop = (double)blocks * (kPeakThreads / 64) * kChains * (double)iters * mfma_flop(kPrec);
+  *tflops = ms > 0.0f ? flop / (ms * 1e-3) / 1e12 : 0.0;
+  return hipSuccess;
+}
+
+}  // namespace
+}  // namespace dl
+
+dl_status dl_measure_peaks(dl_ctx* c, dl_peaks* out) {
+  using namespace dl;
+  if (!c || !out) return DL_ERR_INVALID;
+  c->err.clear();
+  hipError_t e = hipSetDevice(c->device);
+  const int64_t copy_bytes = (int64_t)1 << 30;
+  float* wave_out = nullptr;
+  uint8_t* buf = nullptr;
+  if (e == hipSuccess) e = hipMalloc(&wave_out, (size_t)c->cu_count * kPeakBlocksPerCU * (kPeakThreads / 64) * 4);
+  if (e == hipSuccess) e = hipMalloc(&buf, (size_t)(2 * copy_bytes));
+  if (e == hipSuccess) e = hipMemset(buf, 0, (size_t)copy_bytes);
+  if (e == hipSuccess) e = mfma_rate<DL_FP32>(c->cu_count, wave_out, &out->mfma_fp32_tflops);
+  if (e == hipSuccess) e = mfma_rate<DL_BF16>(c->cu_count, wave_out, &out->mfma_bf16_tflops);
+  if (e == hipSuccess) e = mfma_rate<DL_FP16>(c->cu_count, wave_out, &out->mfma_fp16_tflops);
+  if (e == hipSuccess) e = mfma_rate<DL_FP8>(c->cu_count, wave_out, &out->mfma_fp8_tflops);
+  if (e == hipSuccess) {
+    float ms = 0.0f;
+    const int64_t n16 = copy_bytes / 16;
+    const u32x4* src = reinterpret_cast<const u32x4*>(buf);
+    u32x4* dst = reinterpret_cast<u32x4*>(buf + copy_bytes);
+    e = time_launch(
+        [&]() {
+          hipLaunchKernelGGL(copy_peak_kernel, dim3((unsigned)(c->cu_count * 16)), dim3(256), 0, nullptr, src, dst,
+                             n16);
+        },
+        &ms);
+    out->hbm_copy_gbps = ms > 0.0f ? 2.0 * (double)copy_bytes / (ms * 1e-3) / 1e9 : 0.0;
+  }
+  if (buf) (void)hipFree(buf);
+  if (wave_out) (void)hipFree(wave_out);
+  if (e != hipSuccess) {
+    c->err = std::string("dl_measure_peaks: ") + hipGetErrorString(e);
+    return DL_ERR_DEVICE;
+  }
+  return DL_OK;
+}

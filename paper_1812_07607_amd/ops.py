@@ -320,6 +320,17 @@ def join_eps_filtered(R: torch.Tensor, S: torch.Tensor | None, eps: float, label
     raise RuntimeError("join_eps_filtered did not converge on workspace / capacity")
 
 
+# ---------------------------------------------------------------- measurement
+def measure_peaks(device: int | None = None) -> dict:
+    """Achievable matrix-core rates (TFLOP/s per operand format) and HBM copy
+    rate (GB/s) of the device, measured by the library's rate kernels."""
+    c = context(device)
+    pk = _lib.dl_peaks()
+    c.check(c.L.dl_measure_peaks(c.h, ctypes.byref(pk)))
+    return {"fp32": pk.mfma_fp32_tflops, "bf16": pk.mfma_bf16_tflops, "fp16": pk.mfma_fp16_tflops,
+            "fp8": pk.mfma_fp8_tflops, "hbm_copy_GBps": pk.hbm_copy_gbps}
+
+
 # ---------------------------------------------------------------- top-k
 @dataclass
 class TopkResult:
