@@ -477,6 +477,9 @@ typedef struct dl_peaks {
   double mfma_fp16_tflops; /* v_mfma_f32_16x16x32_{bf16,f16} and the E4M3       */
   double mfma_fp8_tflops;  /* v_mfma_scale_f32_16x16x128_f8f6f4, 8 chains/wave  */
   double hbm_copy_gbps;    /* a 1 GiB device copy: bytes read + written per s   */
+  double mfma_bf16_2w_tflops;        /* 16x16x32 bf16 at two waves per SIMD (the  */
+  double mfma_bf16_32x32_2w_tflops;  /* candidate pass's occupancy); 32x32x16 bf16 */
+  double hbm_read_gbps;              /* a 1 GiB streaming read: bytes per s        */
 } dl_peaks;
 
 /* Runs the rate kernels on the context's device (default stream; it

@@ -14,13 +14,18 @@ typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kChains = 8;        // independent accumulators per wave
+constexpr int kBf16Wide = 16;     // the 32 x 32 x 16 bf16 instruction (not an operand format)
 constexpr int kPeakThreads = 256;
 constexpr int kPeakBlocksPerCU = 8;  // 32 waves per CU
 
-// flop of one MFMA instruction of each format
+// flop of one MFMA instruction, and the instructions per wave and iteration
 constexpr double mfma_flop(int prec) {
-  return prec == DL_FP32 ? 2.0 * 16 * 16 * 4 : prec == DL_FP8 ? 2.0 * 16 * 16 * 128 : 2.0 * 16 * 16 * 32;
+  return prec == DL_FP32 ? 2.0 * 16 * 16 * 4
+         : prec == DL_FP8 ? 2.0 * 16 * 16 * 128
+         : prec == kBf16Wide ? 2.0 * 32 * 32 * 16
+                             : 2.0 * 16 * 16 * 32;
 }
+constexpr int mfma_per_iter(int prec) { return prec == kBf16Wide ? kChains / 2 : kChains; }
 
 // kChains independent chains of `iters` MFMAs per wave; operands are small
 // values derived from `seed`, so nothing folds, nothing overflows and no
@@ -67,6 +72,26 @@ __global__ __launch_bounds__(kPeakThreads) void mfma_peak_kernel(int iters, floa
       for (int c = 0; c < kChains; ++c)
         acc[c] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, acc[c], 0, 0, 0, 127, 0, 127);
     }
+  } else if constexpr (kPrec == kBf16Wide) {
+    // v_mfma_f32_32x32x16_bf16: 32 x 32 blocks, four chains of 16 floats
+    typedef float f32x16 __attribute__((ext_vector_type(16)));
+    bf16x8 a, b;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      a[e] = (__bf16)x;
+      b[e] = (__bf16)(x * 0.5f);
+    }
+    f32x16 w[kChains / 2];
+#pragma unroll
+    for (int c = 0; c < kChains / 2; ++c)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) w[c][e] = x * (c + e);
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+      for (int c = 0; c < kChains / 2; ++c) w[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, w[c], 0, 0, 0);
+    }
+#pragma unroll
+    for (int c = 0; c < kChains / 2; ++c) acc[c] = f32x4{w[c][0], w[c][5], w[c][10], w[c][15]};
   } else {
     const float a = x, b = x * 0.5f;
     for (int it = 0; it < iters; ++it) {
@@ -98,6 +123,24 @@ __global__ __launch_bounds__(256) void copy_peak_kernel(const u32x4* __restrict_
   for (; t < n16; t += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + t), dst + t);
 }
 
+// Streaming read (a checksum that is almost never stored), eight 16-byte
+// loads in flight per lane.
+__global__ __launch_bounds__(256) void read_peak_kernel(const u32x4* __restrict__ src, int64_t n16,
+                                                        unsigned* __restrict__ out) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned acc = 0;
+  for (; t + 7 * stride < n16; t += 8 * stride) {
+    u32x4 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = __builtin_nontemporal_load(src + t + u * stride);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
+  }
+  for (; t < n16; t += stride) acc ^= src[t].x;
+  if (acc == 0x9e3779b9u) out[0] = acc;
+}
+
 // Milliseconds of one launch of `launch` (after one untimed launch).
 template <class F>
 hipError_t time_launch(F launch, float* ms) {
@@ -121,11 +164,14 @@ hipError_t time_launch(F launch, float* ms) {
   return e;
 }
 
+// blocks_per_cu workgroups of four waves per CU: 8 (eight waves per SIMD)
+// for the device's rate, 2 for the candidate pass's occupancy (one
+// workgroup of eight waves per CU: two per SIMD)
 template <int kPrec>
-hipError_t mfma_rate(int cu, float* wave_out, double* tflops) {
-  // about 10 ms per launch at the published rate
+hipError_t mfma_rate(int cu, float* wave_out, double* tflops, int blocks_per_cu = kPeakBlocksPerCU) {
+  // about 10 ms per launch at the published rate (fewer waves: less)
   const int iters = kPrec == DL_FP32 ? 12000 : kPrec == DL_FP8 ? 12000 : 24000;
-  const int blocks = cu * kPeakBlocksPerCU;
+  const int blocks = cu * blocks_per_cu;
   float ms = 0.0f;
   hipError_t e = time_launch(
       [&]() {
@@ -134,7 +180,7 @@ hipError_t mfma_rate(int cu, float* wave_out, double* tflops) {
       },
       &ms);
   if (e != hipSuccess) return e;
-  const double flop = (double)blocks * (kPeakThreads / 64) * kChains * (double)iters * mfma_flop(kPrec);
+  const double flop = (double)blocks * (kPeakThreads / 64) * mfma_per_iter(kPrec) * (double)iters * mfma_flop(kPrec);
   *tflops = ms > 0.0f ? flop / (ms * 1e-3) / 1e12 : 0.0;
   return hipSuccess;
 }
@@ -157,6 +203,8 @@ dl_status dl_measure_peaks(dl_ctx* c, dl_peaks* out) {
   if (e == hipSuccess) e = mfma_rate<DL_BF16>(c->cu_count, wave_out, &out->mfma_bf16_tflops);
   if (e == hipSuccess) e = mfma_rate<DL_FP16>(c->cu_count, wave_out, &out->mfma_fp16_tflops);
   if (e == hipSuccess) e = mfma_rate<DL_FP8>(c->cu_count, wave_out, &out->mfma_fp8_tflops);
+  if (e == hipSuccess) e = mfma_rate<DL_BF16>(c->cu_count, wave_out, &out->mfma_bf16_2w_tflops, 2);
+  if (e == hipSuccess) e = mfma_rate<kBf16Wide>(c->cu_count, wave_out, &out->mfma_bf16_32x32_2w_tflops, 2);
   if (e == hipSuccess) {
     float ms = 0.0f;
     const int64_t n16 = copy_bytes / 16;
@@ -164,11 +212,19 @@ dl_status dl_measure_peaks(dl_ctx* c, dl_peaks* out) {
     u32x4* dst = reinterpret_cast<u32x4*>(buf + copy_bytes);
     e = time_launch(
         [&]() {
-          hipLaunchKernelGGL(copy_peak_kernel, dim3((unsigned)(c->cu_count * 16)), dim3(256), 0, nullptr, src, dst,
+          hipLaunchKernelGGL(copy_peak_kernel, dim3((unsigned)(c->cu_count * 32)), dim3(256), 0, nullptr, src, dst,
                              n16);
         },
         &ms);
     out->hbm_copy_gbps = ms > 0.0f ? 2.0 * (double)copy_bytes / (ms * 1e-3) / 1e9 : 0.0;
+    if (e == hipSuccess)
+      e = time_launch(
+          [&]() {
+            hipLaunchKernelGGL(read_peak_kernel, dim3((unsigned)(c->cu_count * 64)), dim3(256), 0, nullptr, src, n16,
+                               reinterpret_cast<unsigned*>(wave_out));
+          },
+          &ms);
+    out->hbm_read_gbps = ms > 0.0f ? (double)copy_bytes / (ms * 1e-3) / 1e9 : 0.0;
   }
   if (buf) (void)hipFree(buf);
   if (wave_out) (void)hipFree(wave_out);

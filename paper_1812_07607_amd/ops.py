@@ -328,7 +328,9 @@ def measure_peaks(device: int | None = None) -> dict:
     pk = _lib.dl_peaks()
     c.check(c.L.dl_measure_peaks(c.h, ctypes.byref(pk)))
     return {"fp32": pk.mfma_fp32_tflops, "bf16": pk.mfma_bf16_tflops, "fp16": pk.mfma_fp16_tflops,
-            "fp8": pk.mfma_fp8_tflops, "hbm_copy_GBps": pk.hbm_copy_gbps}
+            "fp8": pk.mfma_fp8_tflops, "hbm_copy_GBps": pk.hbm_copy_gbps,
+            "bf16_16x16x32_2_waves_per_simd": pk.mfma_bf16_2w_tflops,
+            "bf16_32x32x16_2_waves_per_simd": pk.mfma_bf16_32x32_2w_tflops, "hbm_read_GBps": pk.hbm_read_gbps}
 
 
 # ---------------------------------------------------------------- top-k
