@@ -939,8 +939,12 @@ __device__ inline void wait_and_sync(int n) {
   asm volatile("" ::: "memory");
 }
 
-template <int kPrec, int kMode>
+// kMasked (eps mode): the K-step masks p.kmaskA / p.kmaskB are set; a
+// separate instantiation, so that the unmasked pass carries none of their
+// bookkeeping.
+template <int kPrec, int kMode, bool kMasked = false>
 __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
+  static_assert(!kMasked || kMode == kModeEps, "K-step masks in eps mode only");
   using Q = Pipe<kPrec>;
   static_assert(Q::kStages == 2 || Q::kStages == 4, "ring depth");
   // operand transfers per issuing wave per step (the count a wait leaves in
@@ -982,7 +986,7 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
   if (!lit.next(p, kMode, ti, tj)) return;
   // K-step masks (eps mode only): the loader issues a tile's set steps in
   // order, and the compute side runs as many steps as the loader issued
-  const bool masked = kQ && p.kmaskA != nullptr;
+  constexpr bool masked = kMasked;
   int64_t lti = ti, ltj = tj;  // tile of the loader's next step
   int64_t iti = ti, itj = tj;  // tile of the step issued last
   uint64_t lrem = masked ? tile_steps(p, ti, tj) : 0;  // the loader tile's steps not yet issued
@@ -1075,7 +1079,7 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
       }
       ++step;
       // ---- its other K-steps
-      for (int c = 1; c < tsteps; ++c) {
+      for (int c = 1; c < (masked ? tsteps : nsteps); ++c) {
         wait_and_sync(dirty ? 0 : (issued - step - 1) * kPerStep);
         dirty = false;
         more = lmore;
@@ -1165,6 +1169,17 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
 
 template <int kMode>
 static hipError_t launch_mode(dl_prec prec, const CandParams& p, dim3 grid, hipStream_t st) {
+  if constexpr (kMode == kModeEps) {
+    if (p.kmaskA) {
+      switch (prec) {
+        case DL_FP32: hipLaunchKernelGGL((cand_kernel<DL_FP32, kModeEps, true>), grid, dim3(kThreads), 0, st, p); break;
+        case DL_BF16: hipLaunchKernelGGL((cand_kernel<DL_BF16, kModeEps, true>), grid, dim3(kThreads), 0, st, p); break;
+        case DL_FP16: hipLaunchKernelGGL((cand_kernel<DL_FP16, kModeEps, true>), grid, dim3(kThreads), 0, st, p); break;
+        case DL_FP8: hipLaunchKernelGGL((cand_kernel<DL_FP8, kModeEps, true>), grid, dim3(kThreads), 0, st, p); break;
+      }
+      return hipGetLastError();
+    }
+  }
   switch (prec) {
     case DL_FP32: hipLaunchKernelGGL((cand_kernel<DL_FP32, kMode>), grid, dim3(kThreads), 0, st, p); break;
     case DL_BF16: hipLaunchKernelGGL((cand_kernel<DL_BF16, kMode>), grid, dim3(kThreads), 0, st, p); break;
