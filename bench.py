@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--crossover", action="store_true",
                     help="instead of the headline step, sweep the histogram self-join size and time the CPU oracle "
                          "against the GPU join (device-resident and with the host transfers) (one JSON line)")
+    ap.add_argument("--etl-only", action="store_true",
+                    help="only the fused-store, index-pruned join, plan and crop legs (one JSON line)")
     ap.add_argument("--serving-only", action="store_true",
                     help="instead of the headline step, run the serving leg alone (profiling runs of the loop)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -695,6 +697,9 @@ def main():
         return
     if args.serving_only:
         print(json.dumps({"serving": serving(args)}))
+        return
+    if args.etl_only:
+        print(json.dumps({"etl_index_plans": etl_index_plan_legs()}))
         return
     if args.crossover:
         cpu_baseline_crossover()
