@@ -37,8 +37,7 @@ hipError_t launch_cand_nearest(dl_prec, CandParams, hipStream_t, int);
 hipError_t launch_gather_rows(const float*, int64_t, int64_t, int64_t, int, float*, hipStream_t, int);
 int64_t pivot_sort_words(int64_t n, int64_t npiv);
 hipError_t launch_pivot_sort(const unsigned long long*, int64_t, int64_t, uint32_t*, uint32_t*, hipStream_t);
-hipError_t launch_block_balls(const float*, int64_t, const uint32_t*, int64_t, int, double, float*, double*,
-                              hipStream_t);
+hipError_t launch_block_balls_q(const Prep&, int64_t, int, dl_prec, double, float*, double*, hipStream_t);
 hipError_t launch_survive(const uint32_t*, int64_t, const uint32_t*, int64_t, int64_t, int64_t, int, uint32_t*,
                           int64_t, hipStream_t);
 hipError_t launch_group_count(const uint32_t*, int64_t, int64_t, int64_t, int64_t, uint32_t*, hipStream_t, int);
@@ -1038,11 +1037,13 @@ dl_status eps_indexed_core(dl_ctx* c, const EpsJob& J, double eps, int32_t pivot
       if (!self) DL_HIP(c, launch_tile_kmask(L.ps.q, L.ps.qld, nTS, I.kmS, st));
     }
     // block balls and the bound passes (both directions), then the tile list
-    DL_HIP(c, launch_block_balls(S.data, S.ld, I.permS, S.n, d, eps, I.centS, I.TbS, st));
+    // balls from the ordered operand copies (contiguous blocks; the prep's
+    // rho bounds what the copy leaves out of each row)
+    DL_HIP(c, launch_block_balls_q(L.ps, S.n, d, prec, eps, I.centS, I.TbS, st));
     dl_status s = bound_pass(c, I.centS, nTS, I.TbS, d, prec, I.pcS, I.scS, I.thrS, L.pr, R.n, L.sr, I.m1, I.m1w,
                              &L.cnt->invalid, st);
     if (s == DL_OK && !self) {
-      DL_HIP(c, launch_block_balls(R.data, R.ld, I.permR, R.n, d, eps, I.centR, I.TbR, st));
+      DL_HIP(c, launch_block_balls_q(L.pr, R.n, d, prec, eps, I.centR, I.TbR, st));
       s = bound_pass(c, I.centR, nTR, I.TbR, d, prec, I.pcR, I.scR, I.thrR, L.ps, S.n, L.ss, I.m2, I.m2w,
                      &L.cnt->invalid, st);
     }

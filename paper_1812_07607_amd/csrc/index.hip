@@ -104,61 +104,85 @@ __global__ __launch_bounds__(64) void pivot_place_kernel(const unsigned long lon
   }
 }
 
-// One workgroup per block of kTile consecutive ordered rows (row q of the
-// order is row perm[q] of X): the block's centroid in float32 (the float64
-// mean, rounded) and the threshold Tb = (eps + r)^2 for its ball, with r an
-// upper bound of max |x - c| over the block's rows.  The squared distances
-// are summed in float64 (relative error below d 2^-53) and r and Tb are
-// rounded up by 2^-30 relative, far more than that error.
-__global__ __launch_bounds__(256) void block_ball_kernel(const float* __restrict__ X, int64_t ld,
-                                                         const uint32_t* __restrict__ perm, int64_t n, int d,
-                                                         double eps, float* __restrict__ cent,
-                                                         double* __restrict__ Tb) {
-  extern __shared__ float c_lds[];  // d floats
-  __shared__ double r2_wave[4];
+// Block balls from the ordered operand copy, whose 256 rows of a block are
+// contiguous (qld bytes each): the centroid c is the float64 mean of the
+// operand values x~ rounded to float32, and r bounds |x - c| from above for
+// each row x of the block through |x - c| <= |x~ - c| + |x - x~|, the second
+// term being the prep's rounded-up rho of the row; the sums are float64
+// (relative error below dpad 2^-53) and r and Tb are rounded up by 2^-30
+// relative.  Reads the 2 to 8 times smaller operand
+// copy sequentially instead of float32 rows scattered by the permutation.
+template <int kPrec>
+__device__ inline float op_elem(const uint8_t* row, int k, float scale) {
+  if constexpr (kPrec == DL_FP32) return reinterpret_cast<const float*>(row)[k];
+  else if constexpr (kPrec == DL_BF16) return dec_bf16(reinterpret_cast<const uint16_t*>(row)[k]);
+  else if constexpr (kPrec == DL_FP16) return dec_f16(reinterpret_cast<const uint16_t*>(row)[k]);
+  else return dec_e4m3(row[k]) * scale;
+}
+
+template <int kPrec>
+__global__ __launch_bounds__(256) void block_ball_q_kernel(const uint8_t* __restrict__ q, int64_t qld,
+                                                           const int* __restrict__ sexp,
+                                                           const float* __restrict__ rho, int64_t n, int d,
+                                                           double eps, float* __restrict__ cent,
+                                                           double* __restrict__ Tb) {
+  constexpr int kElem = kPrec == DL_FP32 ? 4 : kPrec == DL_FP8 ? 1 : 2;  // bytes per value
+  constexpr int kPer = 16 / kElem;                                       // values per 16-byte piece
+  extern __shared__ float c_lds[];  // qld / kElem floats: the centroid, zero past d
+  __shared__ double r_wave[4];
+  __shared__ float scale_lds[kTile];
   const int64_t b = blockIdx.x;
   const int64_t r0 = b * kTile;
   const int rows = (int)min((int64_t)kTile, n - r0);
-  __shared__ int64_t roff[kTile];  // the block's row offsets in X
-  for (int r = threadIdx.x; r < rows; r += blockDim.x) roff[r] = (int64_t)perm[r0 + r] * ld;
+  const int dpad = (int)(qld / kElem);
+  const uint8_t* base = q + r0 * qld;
+  for (int r = threadIdx.x; r < rows; r += blockDim.x)
+    scale_lds[r] = kPrec == DL_FP8 ? ldexpf(1.0f, sexp[r0 + r]) : 1.0f;
   __syncthreads();
-  for (int k = threadIdx.x; k < d; k += blockDim.x) {
-    // eight rows' loads in flight, added in row order
+  // the mean: one value column per thread, eight rows' loads in flight
+  for (int k = threadIdx.x; k < dpad; k += blockDim.x) {
     double s = 0.0;
     int r = 0;
     for (; r + 8 <= rows; r += 8) {
       float v[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = X[roff[r + u] + k];
+      for (int u = 0; u < 8; ++u) v[u] = op_elem<kPrec>(base + (int64_t)(r + u) * qld, k, scale_lds[r + u]);
 #pragma unroll
       for (int u = 0; u < 8; ++u) s += (double)v[u];
     }
-    for (; r < rows; ++r) s += (double)X[roff[r] + k];
-    const float c = (float)(s / (double)rows);
+    for (; r < rows; ++r) s += (double)op_elem<kPrec>(base + (int64_t)r * qld, k, scale_lds[r]);
+    const float c = k < d ? (float)(s / (double)rows) : 0.0f;
+    if (k < d) cent[b * (int64_t)d + k] = c;
     c_lds[k] = c;
-    cent[b * (int64_t)d + k] = c;
   }
   __syncthreads();
-  // one wave per row: lanes over k, a float64 sum per row, the block maximum
+  // |x~ - c| + rho per row: one wave per row, 16-byte pieces across the lanes
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double r2max = 0.0;
+  const int pieces = (int)(qld / 16);
+  double rmax = 0.0;
   for (int r = wave; r < rows; r += 4) {
-    const float* x = X + roff[r];
+    const uint8_t* row = base + (int64_t)r * qld;
+    const float sc = scale_lds[r];
     double s = 0.0;
-    for (int k = lane; k < d; k += 64) {
-      const double t = (double)x[k] - (double)c_lds[k];
-      s += t * t;
+    for (int pc = lane; pc < pieces; pc += 64) {
+      const uint4 w = *reinterpret_cast<const uint4*>(row + (int64_t)pc * 16);
+      const uint8_t* wb = reinterpret_cast<const uint8_t*>(&w);
+#pragma unroll
+      for (int e = 0; e < kPer; ++e) {
+        const double t = (double)op_elem<kPrec>(wb, e, sc) - (double)c_lds[pc * kPer + e];
+        s += t * t;
+      }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    r2max = fmax(r2max, s);
+    rmax = fmax(rmax, sqrt(s) + (double)rho[r0 + r]);
   }
-  if (lane == 0) r2_wave[wave] = r2max;
+  if (lane == 0) r_wave[wave] = rmax;
   __syncthreads();
   if (threadIdx.x == 0) {
-    const double m = fmax(fmax(r2_wave[0], r2_wave[1]), fmax(r2_wave[2], r2_wave[3]));
-    const double r = sqrt(m) * (1.0 + 0x1p-30) + 0x1p-100;
-    const double e = eps + r;
+    const double m = fmax(fmax(r_wave[0], r_wave[1]), fmax(r_wave[2], r_wave[3]));
+    const double rr = m * (1.0 + 0x1p-30) + 0x1p-100;
+    const double e = eps + rr;
     Tb[b] = e * e * (1.0 + 0x1p-30);
   }
 }
@@ -358,12 +382,32 @@ hipError_t launch_pivot_sort(const unsigned long long* argkey, int64_t n, int64_
   return hipGetLastError();
 }
 
-hipError_t launch_block_balls(const float* X, int64_t ld, const uint32_t* perm, int64_t n, int d, double eps,
-                              float* cent, double* Tb, hipStream_t st) {
+// Balls of the blocks of an ordered operand copy P (n real rows).
+hipError_t launch_block_balls_q(const Prep& P, int64_t n, int d, dl_prec prec, double eps, float* cent, double* Tb,
+                                hipStream_t st) {
   const int64_t nb = (n + kTile - 1) / kTile;
   if (nb == 0) return hipSuccess;
-  hipLaunchKernelGGL(block_ball_kernel, dim3((unsigned)nb), dim3(256), (size_t)d * sizeof(float), st, X, ld, perm, n,
-                     d, eps, cent, Tb);
+  const int elem = prec == DL_FP32 ? 4 : prec == DL_FP8 ? 1 : 2;
+  const size_t lds = (size_t)(P.qld / elem) * sizeof(float);
+  const uint8_t* q = static_cast<const uint8_t*>(P.q);
+  switch (prec) {
+    case DL_FP32:
+      hipLaunchKernelGGL(block_ball_q_kernel<DL_FP32>, dim3((unsigned)nb), dim3(256), lds, st, q, P.qld, P.sexp, P.rho,
+                         n, d, eps, cent, Tb);
+      break;
+    case DL_BF16:
+      hipLaunchKernelGGL(block_ball_q_kernel<DL_BF16>, dim3((unsigned)nb), dim3(256), lds, st, q, P.qld, P.sexp, P.rho,
+                         n, d, eps, cent, Tb);
+      break;
+    case DL_FP16:
+      hipLaunchKernelGGL(block_ball_q_kernel<DL_FP16>, dim3((unsigned)nb), dim3(256), lds, st, q, P.qld, P.sexp, P.rho,
+                         n, d, eps, cent, Tb);
+      break;
+    case DL_FP8:
+      hipLaunchKernelGGL(block_ball_q_kernel<DL_FP8>, dim3((unsigned)nb), dim3(256), lds, st, q, P.qld, P.sexp, P.rho,
+                         n, d, eps, cent, Tb);
+      break;
+  }
   return hipGetLastError();
 }
 
