@@ -143,3 +143,22 @@ def test_full_histogram_workload_equals_plain_join():
     assert got.count == plain.count > 0
     assert torch.equal(got.i, plain.i) and torch.equal(got.j, plain.j) and torch.equal(got.dist, plain.dist)
     assert info.tiles_computed < info.tiles_total // 4, info
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_index_degenerate_inputs(orc, prec):
+    """All rows identical (every ball has radius 0, every tile survives, every
+    pair is at distance 0), exactly two tiles per relation, and more pivots
+    asked for than S has rows."""
+    X = np.tile(synth.gaussian_mixture_unit(1, 40, 1, seed=91), (700, 1))
+    got, info = ops.join_eps_indexed(dev(X), None, 0.0, prec)
+    assert_eps_equal(got, orc.eps_join(X, None, 0.0), 40, "identical rows/%s" % prec)
+    assert got.count == 700 * 699 // 2 and info.tiles_computed == info.tiles_total
+    R = synth.gaussian_mixture_unit(512, 24, 5, sigma=0.02, seed=92)
+    S = synth.gaussian_mixture_unit(512, 24, 5, sigma=0.02, seed=92, stream=1)
+    pairs = synth.sample_pairs(512, 512, 10000, False, seed=93)
+    eps = eps_quantile(orc, R, S, pairs, 0.01)
+    for piv in (0, 5000):
+        got, info = ops.join_eps_indexed(dev(R), dev(S), eps, prec, pivots=piv)
+        assert_eps_equal(got, orc.eps_join(R, S, eps), 24, "two tiles pivots=%d/%s" % (piv, prec))
+        assert info.tiles_total == 4 and 0 < info.pivots <= 512

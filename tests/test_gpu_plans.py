@@ -54,3 +54,33 @@ def test_two_relations_both_plans(orc):
         for got, plan in zip(res, ("filter_first", "match_first")):
             assert_eps_equal(got, ref, 64, "%s label %d" % (plan, label))
         assert torch.equal(res[0].i, res[1].i) and torch.equal(res[0].j, res[1].j)
+
+
+def test_plans_degenerate_labels(orc):
+    """Every row labelled (both plans are the plain join), one labelled row
+    (a self-join has no pair; a two-relation join one row against the
+    labelled S rows), and a self-join whose labelled rows are all identical."""
+    X = synth.gaussian_mixture_unit(1800, 32, 6, sigma=0.03, seed=81)
+    pairs = synth.sample_pairs(1800, 1800, 20000, True, seed=82)
+    eps = float(np.sqrt(synth.order_statistic(orc.pair_d2(X, X, *pairs), 0.01)))
+    every = np.full(1800, 5, np.int32)
+    plain = ops.join_eps(dev(X), None, eps, "bf16")
+    for plan in ("filter_first", "match_first"):
+        got = ops.join_eps_filtered(dev(X), None, eps, dev(every), None, 5, plan, "bf16")
+        assert got.count == plain.count and torch.equal(got.i, plain.i) and torch.equal(got.j, plain.j), plan
+    one = np.zeros(1800, np.int32)
+    one[977] = 1
+    for plan in ("filter_first", "match_first"):
+        got = ops.join_eps_filtered(dev(X), None, eps, dev(one), None, 1, plan, "fp16")
+        assert got.count == 0, plan
+        got = ops.join_eps_filtered(dev(X), dev(X), eps, dev(one), dev(every - 4), 1, plan, "fp16")
+        ref = restricted_oracle(orc, X, X, one, every - 4, 1, eps, False)
+        assert_eps_equal(got, ref, 32, "one row/%s" % plan)
+    Y = X.copy()
+    lab = (np.arange(1800) % 3 == 0).astype(np.int32)
+    Y[lab == 1] = Y[0]
+    for plan in ("filter_first", "match_first"):
+        got = ops.join_eps_filtered(dev(Y), None, 0.0, dev(lab), None, 1, plan, "bf16")
+        ref = restricted_oracle(orc, Y, None, lab, None, 1, 0.0, True)
+        assert_eps_equal(got, ref, 32, "identical rows/%s" % plan)
+        assert got.count == 600 * 599 // 2
