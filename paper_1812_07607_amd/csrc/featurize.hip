@@ -22,9 +22,12 @@ namespace dl {
 constexpr int kHistWaves = 4;  // patches (waves) per workgroup
 
 // This wave's LDS operations are complete and every lane has reached this
-// point (the histogram is private to the wave).
+// point (the histogram is private to the wave).  Only the LDS counter is
+// waited for (s_waitcnt lgkmcnt(0); vmcnt and expcnt at their no-wait
+// values): the wave's global stores of the previous patch need not land
+// before it clears and counts the next one.
 __device__ inline void wave_lds_fence() {
-  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_s_waitcnt(0xC07F);
   __builtin_amdgcn_wave_barrier();
 }
 
