@@ -84,12 +84,55 @@ __device__ inline int count_patch(const PixelSource& src, int64_t p, uint32_t* _
     }
     const int cw = bx.x1 - bx.x0, area = cw * (bx.y1 - bx.y0);
     const uint8_t* base = src.pix + (((int64_t)bx.frame * src.h + bx.y0) * src.w + bx.x0) * 3;
-    for (int q = lane; q < area; q += 64) {
-      const int y = q / cw, x = q - y * cw;
-      const uint8_t* px = base + ((int64_t)y * src.w + x) * 3;
-      const uint32_t bin = ((((uint32_t)px[0] >> shift) * bins) + ((uint32_t)px[1] >> shift)) * bins +
-                           ((uint32_t)px[2] >> shift);
-      atomicAdd(&hist[bin], 1u);
+    // row of pixel q by a float reciprocal, then one correction step each
+    // way (q < 2^24, so the estimate is off by at most one)
+    const float rcw = 1.0f / (float)cw;
+    auto at = [&](int q) {
+      int y = (int)((float)q * rcw);
+      int x = q - y * cw;
+      if (x < 0) {
+        --y;
+        x += cw;
+      } else if (x >= cw) {
+        ++y;
+        x -= cw;
+      }
+      return base + ((int64_t)y * src.w + x) * 3;
+    };
+    auto bin_of = [&](uint32_t r, uint32_t g, uint32_t b) {
+      return (((r >> shift) * bins) + (g >> shift)) * bins + (b >> shift);
+    };
+    // eight (then four) pixels' loads in flight per lane, then their counts (a box's
+    // rows are short strided runs, so the loads' latency, not their bytes,
+    // bounds a wave)
+    int q = lane;
+    for (; q + 7 * 64 < area; q += 8 * 64) {
+      uint32_t c[8][3];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const uint8_t* px = at(q + 64 * u);
+        c[u][0] = px[0];
+        c[u][1] = px[1];
+        c[u][2] = px[2];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) atomicAdd(&hist[bin_of(c[u][0], c[u][1], c[u][2])], 1u);
+    }
+    for (; q + 3 * 64 < area; q += 4 * 64) {
+      uint32_t c[4][3];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint8_t* px = at(q + 64 * u);
+        c[u][0] = px[0];
+        c[u][1] = px[1];
+        c[u][2] = px[2];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) atomicAdd(&hist[bin_of(c[u][0], c[u][1], c[u][2])], 1u);
+    }
+    for (; q < area; q += 64) {
+      const uint8_t* px = at(q);
+      atomicAdd(&hist[bin_of(px[0], px[1], px[2])], 1u);
     }
     return area;
   } else {
