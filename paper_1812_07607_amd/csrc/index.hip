@@ -62,7 +62,15 @@ __global__ __launch_bounds__(64) void pivot_count_kernel(const unsigned long lon
   for (uint32_t p = threadIdx.x; p < npiv; p += 64) h[p] = 0;
   __syncthreads();
   const int64_t lo = b * kPivChunk, hi = min(n, lo + kPivChunk);
-  for (int64_t t = lo + threadIdx.x; t < hi; t += 64) atomicAdd(&h[pivot_of(argkey[t], npiv)], 1u);
+  uint32_t piv[kPivChunk / 64];  // all the chunk's loads in flight, then the counts
+#pragma unroll
+  for (int u = 0; u < kPivChunk / 64; ++u) {
+    const int64_t t = lo + 64 * u + threadIdx.x;
+    piv[u] = t < hi ? pivot_of(argkey[t], npiv) : npiv;
+  }
+#pragma unroll
+  for (int u = 0; u < kPivChunk / 64; ++u)
+    if (piv[u] < npiv) atomicAdd(&h[piv[u]], 1u);
   __syncthreads();
   for (uint32_t p = threadIdx.x; p < npiv; p += 64) cnt[(int64_t)p * nb + b] = h[p];
 }
@@ -82,10 +90,20 @@ __global__ __launch_bounds__(64) void pivot_place_kernel(const unsigned long lon
   __syncthreads();
   const int64_t lo = b * kPivChunk, hi = min(n, lo + kPivChunk);
   const uint64_t lower = (1ull << lane) - 1;  // lanes below this one
-  for (int64_t base = lo; base < hi; base += 64) {
+  // the chunk's pivots first (all its loads in flight), then the placement
+  uint32_t piv[kPivChunk / 64];
+#pragma unroll
+  for (int u = 0; u < kPivChunk / 64; ++u) {
+    const int64_t t = lo + 64 * u + lane;
+    piv[u] = t < hi ? pivot_of(argkey[t], npiv) : 0u;
+  }
+#pragma unroll
+  for (int u = 0; u < kPivChunk / 64; ++u) {
+    const int64_t base = lo + 64 * u;
+    if (base >= hi) break;
     const int64_t t = base + lane;
     const bool valid = t < hi;
-    const uint32_t p = valid ? pivot_of(argkey[t], npiv) : 0u;
+    const uint32_t p = piv[u];
     uint64_t peers = __ballot(valid);
     for (int k = 0; k < pbits; ++k) {
       const bool bit = (p >> k) & 1u;
@@ -156,26 +174,40 @@ __global__ __launch_bounds__(256) void block_ball_q_kernel(const uint8_t* __rest
     c_lds[k] = c;
   }
   __syncthreads();
-  // |x~ - c| + rho per row: one wave per row, 16-byte pieces across the lanes
+  // |x~ - c| + rho per row: a wave takes four rows at a time (four loads in
+  // flight per lane), 16-byte pieces across the lanes; rows past the block
+  // repeat its last row
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int pieces = (int)(qld / 16);
+  constexpr int kRows = 4;
   double rmax = 0.0;
-  for (int r = wave; r < rows; r += 4) {
-    const uint8_t* row = base + (int64_t)r * qld;
-    const float sc = scale_lds[r];
-    double s = 0.0;
-    for (int pc = lane; pc < pieces; pc += 64) {
-      const uint4 w = *reinterpret_cast<const uint4*>(row + (int64_t)pc * 16);
-      const uint8_t* wb = reinterpret_cast<const uint8_t*>(&w);
+  for (int r = wave; r < rows; r += 4 * kRows) {
+    int rq[kRows];
 #pragma unroll
-      for (int e = 0; e < kPer; ++e) {
-        const double t = (double)op_elem<kPrec>(wb, e, sc) - (double)c_lds[pc * kPer + e];
-        s += t * t;
+    for (int u = 0; u < kRows; ++u) rq[u] = min(r + 4 * u, rows - 1);
+    double s[kRows] = {0.0, 0.0, 0.0, 0.0};
+    for (int pc = lane; pc < pieces; pc += 64) {
+      uint4 w[kRows];
+#pragma unroll
+      for (int u = 0; u < kRows; ++u) w[u] = *reinterpret_cast<const uint4*>(base + (int64_t)rq[u] * qld + (int64_t)pc * 16);
+#pragma unroll
+      for (int u = 0; u < kRows; ++u) {
+        const uint8_t* wb = reinterpret_cast<const uint8_t*>(&w[u]);
+        const float sc = scale_lds[rq[u]];
+#pragma unroll
+        for (int e = 0; e < kPer; ++e) {
+          const double t = (double)op_elem<kPrec>(wb, e, sc) - (double)c_lds[pc * kPer + e];
+          s[u] += t * t;
+        }
       }
     }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    rmax = fmax(rmax, sqrt(s) + (double)rho[r0 + r]);
+    for (int u = 0; u < kRows; ++u) {
+      double t = s[u];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+      rmax = fmax(rmax, sqrt(t) + (double)rho[r0 + rq[u]]);
+    }
   }
   if (lane == 0) r_wave[wave] = rmax;
   __syncthreads();
