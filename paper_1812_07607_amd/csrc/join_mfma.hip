@@ -500,15 +500,16 @@ __device__ inline void flush_eps(const CandParams& p, const uint2* q, const uint
 }
 
 // Eps epilogue.  A fast test (each row's maximum over the wave's four
-// column blocks against the row threshold) lets most waves skip the tile.
-// Otherwise each (row block, row) slot with a hit forms its four hit masks
-// and stages its (i, j) in the wave's LDS queue (ballot prefix, no
-// atomics); the queue persists across tiles and goes to global memory only
-// when full and at the end.  Bounds (rows and columns left in the tile) and
-// the self-join's j > i (only on a diagonal tile) are checked in 32-bit
-// tile coordinates, and only on tiles that need them.  With kP each
-// record's P~ is staged too (qp).  Returns whether this wave wrote to global
-// memory.
+// column blocks against the row threshold) lets most waves skip the tile,
+// and records which of the eight row blocks hold a hit.  Only those blocks
+// are visited after it: each of their (row block, row) slots with a hit
+// forms its four hit masks and stages its (i, j) in the wave's LDS queue
+// (ballot prefix, no atomics); the queue persists across tiles and goes to
+// global memory only when full and at the end.  Bounds (rows and columns
+// left in the tile) and the self-join's j > i (only on a diagonal tile) are
+// checked in 32-bit tile coordinates, and only on tiles that need them.
+// With kP each record's P~ is staged too (qp).  Returns whether this wave
+// wrote to global memory.
 template <bool kP>
 __device__ inline bool epilogue_eps(const CandParams& p, int64_t ti, int64_t tj, const f32x4 (&acc)[8][4],
                                     const float* thr_tile, uint2* q, uint32_t* qp, int& nq) {
@@ -517,16 +518,18 @@ __device__ inline bool epilogue_eps(const CandParams& p, int64_t ti, int64_t tj,
   const int lrow0 = wm * kWaveM + 4 * (lane >> 4);
   const int lcol0 = wn * kWaveN + (lane & 15);
   float4 th[8];
-  uint64_t any = 0;
+  uint32_t hit_mb = 0;  // bit mb: row block mb holds a hit (wave-uniform)
 #pragma unroll
   for (int mb = 0; mb < 8; ++mb) {
     th[mb] = *reinterpret_cast<const float4*>(thr_tile + lrow0 + mb * 16);
     float m[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) m[r] = max4_nan(acc[mb][0][r], acc[mb][1][r], acc[mb][2][r], acc[mb][3][r]);
-    any |= mask_uge(m[0], th[mb].x) | mask_uge(m[1], th[mb].y) | mask_uge(m[2], th[mb].z) | mask_uge(m[3], th[mb].w);
+    const uint64_t h =
+        mask_uge(m[0], th[mb].x) | mask_uge(m[1], th[mb].y) | mask_uge(m[2], th[mb].z) | mask_uge(m[3], th[mb].w);
+    hit_mb |= (h != 0 ? 1u : 0u) << mb;
   }
-  if (!any) return false;
+  if (!hit_mb) return false;
   const int rrem = (int)min(p.nR - ti * kTile, (int64_t)kTile);
   const int crem = (int)min(p.nS - tj * kTile, (int64_t)kTile);
   const bool diag = p.self_join && ti == tj;
@@ -536,6 +539,7 @@ __device__ inline bool epilogue_eps(const CandParams& p, int64_t ti, int64_t tj,
   bool wrote = false;
 #pragma unroll
   for (int mb = 0; mb < 8; ++mb) {
+    if (!(hit_mb & (1u << mb))) continue;
     const float tv[4] = {th[mb].x, th[mb].y, th[mb].z, th[mb].w};
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
