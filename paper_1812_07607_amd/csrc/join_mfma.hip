@@ -393,7 +393,27 @@ __device__ inline void mma_tail(f32x4 (&acc)[8][4], const Frags& fr) {
   }
 }
 
-template <int kPrec, bool kFirst, bool kTailIn>
+// The first sub-step's first fragments of a 16-bit K-step (A0, B0..B3,
+// A1..A3), in the order of first use: the first instruction waits for two
+// reads.  mma_step issues them itself unless kReadsDone (the eps pass issues
+// them, then runs the previous tile's epilogue while they land).
+template <int kPrec>
+__device__ inline void mma_first_reads(const uint8_t* la, const uint8_t* lb, int ra0, int rb0, Frags& fr) {
+  constexpr int kCB = Pipe<kPrec>::kCB;
+  const int lane = threadIdx.x & 63;
+  const int r16 = lane & 15, grp = lane >> 4;
+  fr.a[0] = *reinterpret_cast<const uint4*>(la + lds_off<kCB>(ra0 + r16, grp));
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) fr.b0[nb] = *reinterpret_cast<const uint4*>(lb + lds_off<kCB>(rb0 + nb * 16 + r16, grp));
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int mb = 1; mb < kTailFrom; ++mb)
+    fr.a[mb] = *reinterpret_cast<const uint4*>(la + lds_off<kCB>(ra0 + mb * 16 + r16, grp));
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int kPrec, bool kFirst, bool kTailIn, bool kReadsDone = false>
 __device__ inline void mma_step(f32x4 (&acc)[8][4], const uint8_t* la, const uint8_t* lb, int ra0, int rb0,
                                 const int (&sa)[8], const int (&sb)[4], const f32x4 (&init)[4], Frags& fr) {
   constexpr int kCB = Pipe<kPrec>::kCB;
@@ -412,15 +432,7 @@ __device__ inline void mma_step(f32x4 (&acc)[8][4], const uint8_t* la, const uin
     uint4(&a)[8] = fr.a;
     uint4(&b0)[4] = fr.b0;
     uint4(&b1)[4] = fr.b1;
-    // in the order of first use: the first instruction waits for two reads
-    a[0] = ldA(0, grp);
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int nb = 0; nb < 4; ++nb) b0[nb] = ldB(nb, grp);
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int mb = 1; mb < kTailFrom; ++mb) a[mb] = ldA(mb, grp);
-    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (!kReadsDone) mma_first_reads<kPrec>(la, lb, ra0, rb0, fr);
     if constexpr (kTailIn) {
       mma_tail<kPrec>(acc, fr);  // the previous K-step's pending products
       __builtin_amdgcn_sched_barrier(0);
@@ -1055,8 +1067,17 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
   // may overwrite it.
   if constexpr (kEps) {
     // eps mode: one tile per pass; each K-step's last products are issued
-    // after the next barrier (mma_step, kTailIn)
+    // after the next barrier (mma_step, kTailIn).  A tile's candidate
+    // epilogue runs after the barrier that opens the next tile, between that
+    // step's first fragment reads and its first matrix instruction: a wave
+    // that stages hits then works while the other wave of its SIMD issues
+    // matrix instructions, instead of holding every wave at the barrier.
+    // (Not for E4M3, whose step has no registers to spare for it.)
+    constexpr bool kDefer = kQ && !kFp8;
     int tsteps = lsteps;  // K-steps of the current tile
+    bool pend = false;    // eps: a finished tile (pti, ptj) awaits its epilogue
+    int64_t pti = 0, ptj = 0;
+    int psbuf = 0;
     for (;;) {  // one tile per pass
       // ---- the tile's first K-step
       wait_and_sync(dirty ? 0 : (issued - step - 1) * kPerStep);
@@ -1079,7 +1100,20 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
         }
         if (lmore) issue();
         const int st = step % Q::kStages;
-        mma_step<kPrec, true, false>(acc, lds_ab[st][0], lds_ab[st][1], wm * kWaveM, wn * kWaveN, sa, sb, init, fr);
+        if constexpr (kDefer) {
+          mma_first_reads<kPrec>(lds_ab[st][0], lds_ab[st][1], wm * kWaveM, wn * kWaveN, fr);
+          // side_thr[psbuf] is intact: the loader is one step ahead, so it
+          // fills at most the next tile's side buffer
+          if (pend)
+            dirty |= epilogue_eps<kStageP>(p, pti, ptj, acc, side_thr[psbuf], lds_eq[wave],
+                                           lds_eqp[kStageP ? wave : 0], eq);
+          __builtin_amdgcn_sched_barrier(0);
+          mma_step<kPrec, true, false, true>(acc, lds_ab[st][0], lds_ab[st][1], wm * kWaveM, wn * kWaveN, sa, sb,
+                                             init, fr);
+        } else {
+          mma_step<kPrec, true, false>(acc, lds_ab[st][0], lds_ab[st][1], wm * kWaveM, wn * kWaveN, sa, sb, init,
+                                       fr);
+        }
       }
       ++step;
       // ---- its other K-steps
@@ -1100,6 +1134,11 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
       } else if constexpr (kMode == kModeNearest) {
         epilogue_nearest(p, ti, tj, acc);
         dirty = true;
+      } else if constexpr (kDefer) {
+        pend = true;  // after the next tile's first barrier, or below
+        pti = ti;
+        ptj = tj;
+        psbuf = sbuf;
       } else {
         dirty |= epilogue_eps<kStageP>(p, ti, tj, acc, side_thr[sbuf], lds_eq[wave], lds_eqp[kStageP ? wave : 0], eq);
       }
@@ -1108,6 +1147,11 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
       tj = itj;
       tsteps = isteps;
       ++ctile;
+    }
+    if constexpr (kDefer) {
+      if (pend)
+        dirty |= epilogue_eps<kStageP>(p, pti, ptj, acc, side_thr[psbuf], lds_eq[wave], lds_eqp[kStageP ? wave : 0],
+                                       eq);
     }
   } else {
     // band mode (more live state beside the accumulators): each K-step's
