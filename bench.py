@@ -778,10 +778,12 @@ def main():
         "measured_peaks": {"mfma_tflops": {k: peaks[k] for k in ("fp32", "bf16", "fp16", "fp8")},
                            "mfma_bf16_tflops_at_2_waves_per_simd": {
                                "16x16x32": peaks["bf16_16x16x32_2_waves_per_simd"],
-                               "32x32x16": peaks["bf16_32x32x16_2_waves_per_simd"]},
+                               "32x32x16": peaks["bf16_32x32x16_2_waves_per_simd"],
+                               "16x16x32_lds_fed_candidate_loop": peaks["bf16_lds_fed_candidate_loop"]},
                            "hbm_copy_GBps": peaks["hbm_copy_GBps"], "hbm_read_GBps": peaks["hbm_read_GBps"],
                            "how": "dl_measure_peaks: 8 independent MFMA chains per wave, 32 waves per CU, register "
-                                  "operands (and 8 waves per CU, the candidate pass's occupancy); a 1 GiB device "
+                                  "operands (and 8 waves per CU, the candidate pass's occupancy, with register "
+                                  "operands or with the pass's LDS fragment reads and a barrier per K-step); a 1 GiB device "
                                   "copy (bytes read + written) and a 1 GiB streaming read"},
     }
     if not args.no_extras:

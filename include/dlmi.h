@@ -480,6 +480,9 @@ typedef struct dl_peaks {
   double mfma_bf16_2w_tflops;        /* 16x16x32 bf16 at two waves per SIMD (the  */
   double mfma_bf16_32x32_2w_tflops;  /* candidate pass's occupancy); 32x32x16 bf16 */
   double hbm_read_gbps;              /* a 1 GiB streaming read: bytes per s        */
+  double mfma_bf16_lds_tflops;       /* 16x16x32 bf16 fed from LDS in the candidate */
+                                     /* pass's fragment pattern, two waves per SIMD,*/
+                                     /* a barrier per K-step: that loop's ceiling   */
 } dl_peaks;
 
 /* Runs the rate kernels on the context's device (default stream; it

@@ -43,7 +43,8 @@ class dl_peaks(ctypes.Structure):
     _fields_ = [("mfma_fp32_tflops", ctypes.c_double), ("mfma_bf16_tflops", ctypes.c_double),
                 ("mfma_fp16_tflops", ctypes.c_double), ("mfma_fp8_tflops", ctypes.c_double),
                 ("hbm_copy_gbps", ctypes.c_double), ("mfma_bf16_2w_tflops", ctypes.c_double),
-                ("mfma_bf16_32x32_2w_tflops", ctypes.c_double), ("hbm_read_gbps", ctypes.c_double)]
+                ("mfma_bf16_32x32_2w_tflops", ctypes.c_double), ("hbm_read_gbps", ctypes.c_double),
+                ("mfma_bf16_lds_tflops", ctypes.c_double)]
 
 
 class dl_topk_info(ctypes.Structure):

@@ -1,7 +1,9 @@
 // peak.hip -- achievable rates of this device, the second denominator of the
 // roofline fractions beside the published peaks: the matrix-core rate of each
 // operand format on register operands (no memory traffic; the same MFMA
-// instructions as the candidate pass), and the HBM rate of a streaming copy.
+// instructions as the candidate pass), the bf16 rate with operands read from
+// LDS in the candidate pass's own pattern, and the HBM rate of a streaming
+// copy.
 #include "dl_internal.hpp"
 
 namespace dl {
@@ -105,6 +107,60 @@ __global__ __launch_bounds__(kPeakThreads) void mfma_peak_kernel(int iters, floa
   if (lane == 0) out[(blockIdx.x * kPeakThreads + threadIdx.x) >> 6] = s;
 }
 
+// The candidate pass's inner loop without its memory traffic and epilogue:
+// 512 threads (two waves per SIMD), a 128 KiB LDS ring of two stages of
+// 256 rows x 128 bytes per operand with the pass's piece swizzle, each wave
+// 128 x 64 outputs as 8 x 4 blocks of v_mfma_f32_16x16x32_bf16; per K-step
+// a workgroup barrier, 24 fragment reads and 64 matrix instructions per
+// wave, alternating stages.  Its rate is the ceiling of that loop: LDS
+// bandwidth and latency, barriers and matrix issue, nothing else.
+constexpr int kLdsThreads = 512;
+__device__ inline int lds_piece(int r, int c) { return r * 128 + ((c ^ ((r >> 1) & 7)) << 4); }
+
+__global__ __launch_bounds__(kLdsThreads, 1) void lds_mfma_kernel(int steps, float* __restrict__ out) {
+  __shared__ __attribute__((aligned(1024))) uint8_t ring[2][2][256 * 128];
+  // every bf16 of the ring 2^-7 (0x3c00): products 2^-14, no overflow over
+  // the loop and no subnormal
+  u32x4* w = reinterpret_cast<u32x4*>(&ring[0][0][0]);
+  for (int i = threadIdx.x; i < (int)(sizeof(ring) / 16); i += kLdsThreads)
+    w[i] = u32x4{0x3c003c00u, 0x3c003c00u, 0x3c003c00u, 0x3c003c00u};
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ra0 = (wave >> 2) * 128, rb0 = (wave & 3) * 64;
+  const int r16 = lane & 15, grp = lane >> 4;
+  f32x4 acc[8][4];
+#pragma unroll
+  for (int mb = 0; mb < 8; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int s = 0; s < steps; ++s) {
+    const uint8_t* la = ring[s & 1][0];
+    const uint8_t* lb = ring[s & 1][1];
+    __syncthreads();
+#pragma unroll
+    for (int sub = 0; sub < 2; ++sub) {
+      bf16x8 a[8], b[4];
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb)
+        b[nb] = *reinterpret_cast<const bf16x8*>(lb + lds_piece(rb0 + nb * 16 + r16, grp + 4 * sub));
+#pragma unroll
+      for (int mb = 0; mb < 8; ++mb)
+        a[mb] = *reinterpret_cast<const bf16x8*>(la + lds_piece(ra0 + mb * 16 + r16, grp + 4 * sub));
+#pragma unroll
+      for (int mb = 0; mb < 8; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb)
+          acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mb], b[nb], acc[mb][nb], 0, 0, 0);
+    }
+  }
+  float t = 0.0f;
+#pragma unroll
+  for (int mb = 0; mb < 8; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) t += acc[mb][nb][0] + acc[mb][nb][3];
+  if (lane == 0) out[(blockIdx.x * kLdsThreads + threadIdx.x) >> 6] = t;
+}
+
 // Streaming copy, 16 bytes per lane per load, four loads in flight.
 __global__ __launch_bounds__(256) void copy_peak_kernel(const u32x4* __restrict__ src, u32x4* __restrict__ dst,
                                                         int64_t n16) {
@@ -205,6 +261,19 @@ dl_status dl_measure_peaks(dl_ctx* c, dl_peaks* out) {
   if (e == hipSuccess) e = mfma_rate<DL_FP8>(c->cu_count, wave_out, &out->mfma_fp8_tflops);
   if (e == hipSuccess) e = mfma_rate<DL_BF16>(c->cu_count, wave_out, &out->mfma_bf16_2w_tflops, 2);
   if (e == hipSuccess) e = mfma_rate<kBf16Wide>(c->cu_count, wave_out, &out->mfma_bf16_32x32_2w_tflops, 2);
+  if (e == hipSuccess) {
+    // one workgroup per CU; 20,000 K-steps, about 2.5 ms at 2 PFLOP/s
+    const int steps = 20000;
+    float ms = 0.0f;
+    e = time_launch(
+        [&]() {
+          hipLaunchKernelGGL(lds_mfma_kernel, dim3((unsigned)c->cu_count), dim3(kLdsThreads), 0, nullptr, steps,
+                             wave_out);
+        },
+        &ms);
+    const double flop = (double)c->cu_count * 2.0 * 256 * 256 * 64 * (double)steps;
+    out->mfma_bf16_lds_tflops = ms > 0.0f ? flop / (ms * 1e-3) / 1e12 : 0.0;
+  }
   if (e == hipSuccess) {
     float ms = 0.0f;
     const int64_t n16 = copy_bytes / 16;

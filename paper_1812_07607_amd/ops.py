@@ -322,15 +322,18 @@ def join_eps_filtered(R: torch.Tensor, S: torch.Tensor | None, eps: float, label
 
 # ---------------------------------------------------------------- measurement
 def measure_peaks(device: int | None = None) -> dict:
-    """Achievable matrix-core rates (TFLOP/s per operand format) and HBM copy
-    rate (GB/s) of the device, measured by the library's rate kernels."""
+    """Achievable matrix-core rates (TFLOP/s per operand format, and bf16 at
+    the candidate pass's occupancy, with register or LDS operands) and HBM
+    copy and read rates (GB/s) of the device, measured by the library's rate
+    kernels."""
     c = context(device)
     pk = _lib.dl_peaks()
     c.check(c.L.dl_measure_peaks(c.h, ctypes.byref(pk)))
     return {"fp32": pk.mfma_fp32_tflops, "bf16": pk.mfma_bf16_tflops, "fp16": pk.mfma_fp16_tflops,
             "fp8": pk.mfma_fp8_tflops, "hbm_copy_GBps": pk.hbm_copy_gbps,
             "bf16_16x16x32_2_waves_per_simd": pk.mfma_bf16_2w_tflops,
-            "bf16_32x32x16_2_waves_per_simd": pk.mfma_bf16_32x32_2w_tflops, "hbm_read_GBps": pk.hbm_read_gbps}
+            "bf16_32x32x16_2_waves_per_simd": pk.mfma_bf16_32x32_2w_tflops, "hbm_read_GBps": pk.hbm_read_gbps,
+            "bf16_lds_fed_candidate_loop": pk.mfma_bf16_lds_tflops}
 
 
 # ---------------------------------------------------------------- top-k

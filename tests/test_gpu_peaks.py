@@ -16,3 +16,5 @@ def test_measured_peaks_are_plausible():
     for fmt, peak in PUBLISHED.items():
         assert 0.2 * peak < pk[fmt] <= 1.05 * peak, (fmt, pk)
     assert 0.2 * HBM_GBPS < pk["hbm_copy_GBps"] <= 1.05 * HBM_GBPS, pk
+    # the LDS-fed loop at two waves per SIMD cannot beat the published rate
+    assert 0.2 * PUBLISHED["bf16"] < pk["bf16_lds_fed_candidate_loop"] <= 1.05 * PUBLISHED["bf16"], pk
