@@ -781,12 +781,13 @@ __device__ inline void flush_band(const CandParams& p, int64_t ti, int64_t tj, i
   }
 }
 
-// Band epilogue.  Each of the wave's 128 outputs per lane is compared with
-// its row's band threshold; the 64-lane hit mask of each (row block, row,
-// column block) is a single ballot, and only a nonzero mask stages its hits
-// in the wave's LDS queue (ballot prefix, no atomics, no waits).  The queue
-// is flushed when the next (row block, row) slot might not fit and at the
-// end.  A full tile
+// Band epilogue.  A first test (each row's maximum over the wave's four
+// column blocks against its band threshold) finds the row blocks that hold
+// an entry; in those, each output is compared with its row's band
+// threshold, the 64-lane hit mask of each (row block, row, column block) is
+// a single ballot, and only a nonzero mask stages its hits in the wave's LDS
+// queue (ballot prefix, no atomics, no waits).  The queue is flushed when
+// the next (row block, row) slot might not fit and at the end.  A full tile
 // (the common case) carries no bounds or diagonal code; a partial or
 // self-diagonal tile checks rows and columns left in the tile in 32-bit tile
 // coordinates.  Returns whether this wave wrote to global memory.
@@ -812,8 +813,23 @@ __device__ inline bool epilogue_band(const CandParams& p, int64_t ti, int64_t tj
     crem = (int)min(p.nS - tj * kTile, (int64_t)kTile);
     diag = p.exclude_self && ti == tj;
   }
+  // which row blocks hold an entry: each row's maximum over the wave's four
+  // column blocks against its band threshold (NaN passes; bounds are
+  // applied below)
+  uint32_t hit_mb = 0;
 #pragma unroll
   for (int mb = 0; mb < 8; ++mb) {
+    const float4 th = *reinterpret_cast<const float4*>(L.thr + lrow0 + mb * 16);
+    const uint64_t h = mask_uge(max4_nan(acc[mb][0][0], acc[mb][1][0], acc[mb][2][0], acc[mb][3][0]), th.x) |
+                       mask_uge(max4_nan(acc[mb][0][1], acc[mb][1][1], acc[mb][2][1], acc[mb][3][1]), th.y) |
+                       mask_uge(max4_nan(acc[mb][0][2], acc[mb][1][2], acc[mb][2][2], acc[mb][3][2]), th.z) |
+                       mask_uge(max4_nan(acc[mb][0][3], acc[mb][1][3], acc[mb][2][3], acc[mb][3][3]), th.w);
+    hit_mb |= (h != 0 ? 1u : 0u) << mb;
+  }
+  if (!hit_mb) return false;
+#pragma unroll
+  for (int mb = 0; mb < 8; ++mb) {
+    if (!(hit_mb & (1u << mb))) continue;
     const float4 th = *reinterpret_cast<const float4*>(L.thr + lrow0 + mb * 16);
     const float tv[4] = {th.x, th.y, th.z, th.w};
 #pragma unroll
