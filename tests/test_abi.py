@@ -87,3 +87,34 @@ def test_product_path_does_not_touch_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "dl_oracle" not in text and "liboracle" not in text, f
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every public struct of the header has the size and field offsets of
+    its ctypes declaration in the binding (a C program compiled against the
+    header prints them)."""
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    from paper_1812_07607_amd import _lib
+    structs = [getattr(_lib, n) for n in dir(_lib)
+               if n.startswith("dl_") and isinstance(getattr(_lib, n), type)
+               and issubclass(getattr(_lib, n), ctypes.Structure)]
+    assert len(structs) >= 10
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "dlmi.h"', "int main(void) {"]
+    for s in structs:
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (s.__name__, s.__name__))
+        for f in s._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (s.__name__, f[0], s.__name__, f[0]))
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-std=c99", "-Wall", "-Werror", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)],
+                   check=True)
+    got = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                               check=True).stdout.splitlines())
+    for s in structs:
+        assert int(got[s.__name__ + " size"]) == ctypes.sizeof(s), s.__name__
+        for f in s._fields_:
+            assert int(got["%s.%s" % (s.__name__, f[0])]) == getattr(s, f[0]).offset, (s.__name__, f[0])
