@@ -538,6 +538,17 @@ def etl_index_plan_legs():
                                    "pivots": info.pivots, "indexed_stages": rec1, "same_pairs": same(r, ref),
                                    "value_indexed": pairs / (rec1["ms_per_call"] * 1e-3) / 1e9}
         progress("index %s: %s" % (prec, json.dumps(out["index_join"][prec])))
+    # the index-pruned top-10 self-join (each patch's 10 nearest other patches)
+    ref, rec0 = timed_calls(ctx, lambda: ops.join_topk(hist, None, 10, exclude_self=True, prec="fp16"), 3)
+    (r, info), rec1 = timed_calls(ctx, lambda: ops.join_topk_indexed(hist, None, 10, exclude_self=True,
+                                                                     prec="fp16"), 3)
+    out["index_top10"] = {"plain_ms": rec0["ms_per_call"], "indexed_ms": rec1["ms_per_call"],
+                          "speedup": rec0["ms_per_call"] / rec1["ms_per_call"],
+                          "tiles_computed": info.tiles_computed, "tiles_total": info.tiles_total,
+                          "pivots": info.pivots, "plain_stages": rec0, "indexed_stages": rec1,
+                          "same_rows": bool(torch.equal(r.j, ref.j) and torch.equal(r.dist, ref.dist))}
+    progress("index top-10: %s" % json.dumps(out["index_top10"]))
+    del ref, r
     # filter before / after the match (the palette colour as the label)
     labels = torch.from_numpy(cfg["colour"].astype(np.int32)).cuda()
     res = {}

@@ -326,6 +326,38 @@ dl_status dl_join_topk(dl_ctx* ctx, dl_mat R, dl_mat S, int self_join,
                        uint32_t* out_j, float* out_dist, dl_topk_info* info,
                        void* stream);
 
+/* Scratch bytes for dl_join_topk_indexed (the index, a sample top-k and the
+ * pruned join's own; at least dl_join_topk_workspace's). */
+size_t dl_join_topk_indexed_workspace(int64_t nR, int64_t nS, int32_t d, dl_prec prec,
+                                      int self_join, int exclude_self, int32_t k,
+                                      int32_t band_cap, int32_t pivots);
+
+/* The top-k join with an index built inside the call (section "Query
+ * Processing": an index built on the fly inside the join; section "Derived
+ * Data": ball bounds for Euclidean queries): the result of dl_join_topk,
+ * exactly, while tiles of pairs that cannot hold a row's k nearest are
+ * skipped.  Each row's k-th distance is bounded by an exact top-k against
+ * every 16th row of S (k + 1 with exclude_self).  Rows are ordered by
+ * nearest pivot as in dl_join_eps_indexed (pivots, 0 = default).  Every 256
+ * ordered rows of R form a ball whose radius is the largest bound of its
+ * rows.  A bound pass on the matrix cores keeps the S tiles with a row
+ * within that ball's reach, and the band pass runs on the kept tiles only.
+ * The band and the exact selection are dl_join_topk's.  Falls back to
+ * dl_join_topk when either relation spans fewer than two 256-row tiles or
+ * the sample top-k does not fit the workspace.
+ *   out_j, out_dist, info  as dl_join_topk;
+ *   xinfo     host, nullable: tiles_total = row tiles x column tiles,
+ *             tiles_computed = those kept, pivots (0 when no index was
+ *             built); K-step fields 0.
+ * Errors as dl_join_topk ("band buffer": retry with a larger band_cap and
+ * dl_join_topk_indexed_workspace of it).  Synchronises `stream`. */
+dl_status dl_join_topk_indexed(dl_ctx* ctx, dl_mat R, dl_mat S, int self_join,
+                               int32_t k, int exclude_self, dl_prec prec,
+                               int32_t band_cap, int32_t pivots, void* ws,
+                               size_t ws_bytes, uint32_t* out_j, float* out_dist,
+                               dl_topk_info* info, dl_index_info* xinfo,
+                               void* stream);
+
 
 /* ---------------------------------------------------------------- store */
 

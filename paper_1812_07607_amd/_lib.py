@@ -107,6 +107,10 @@ SIGNATURES = {
     "dl_join_topk_workspace": (sz, [i64, i64, i32, ctypes.c_int, ctypes.c_int, i32, i32]),
     "dl_join_topk": (ctypes.c_int, [P, dl_mat, dl_mat, ctypes.c_int, i32, ctypes.c_int, ctypes.c_int, i32, P, sz,
                                     P, P, ctypes.POINTER(dl_topk_info), P]),
+    "dl_join_topk_indexed_workspace": (sz, [i64, i64, i32, ctypes.c_int, ctypes.c_int, ctypes.c_int, i32, i32, i32]),
+    "dl_join_topk_indexed": (ctypes.c_int, [P, dl_mat, dl_mat, ctypes.c_int, i32, ctypes.c_int, ctypes.c_int, i32,
+                                            i32, P, sz, P, P, ctypes.POINTER(dl_topk_info),
+                                            ctypes.POINTER(dl_index_info), P]),
     "dl_store_bytes": (sz, [i64, i32, ctypes.c_int]),
     "dl_store_create": (ctypes.c_int, [P, dl_mat, ctypes.c_int, P, sz, ctypes.POINTER(P), P]),
     "dl_store_destroy": (None, [P]),

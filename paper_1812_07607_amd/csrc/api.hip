@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <vector>
 #include <new>
 
 #include "core.hpp"
@@ -37,7 +38,11 @@ hipError_t launch_cand_nearest(dl_prec, CandParams, hipStream_t, int);
 hipError_t launch_gather_rows(const float*, int64_t, int64_t, int64_t, int, float*, hipStream_t, int);
 int64_t pivot_sort_words(int64_t n, int64_t npiv);
 hipError_t launch_pivot_sort(const unsigned long long*, int64_t, int64_t, uint32_t*, uint32_t*, hipStream_t);
-hipError_t launch_block_balls_q(const Prep&, int64_t, int, dl_prec, double, float*, double*, hipStream_t);
+hipError_t launch_block_balls_q(const Prep&, int64_t, int, dl_prec, double, float*, double*, hipStream_t,
+                                const float* eps_row = nullptr);
+hipError_t launch_take_bound(const float*, int, const uint32_t*, int64_t, float*, hipStream_t, int);
+hipError_t launch_scatter_rows(const uint32_t*, const float*, int, const uint32_t*, int64_t, uint32_t*, float*,
+                               hipStream_t, int);
 hipError_t launch_survive(const uint32_t*, int64_t, const uint32_t*, int64_t, int64_t, int64_t, int, uint32_t*,
                           int64_t, hipStream_t);
 hipError_t launch_group_count(const uint32_t*, int64_t, int64_t, int64_t, int64_t, uint32_t*, hipStream_t, int);
@@ -680,7 +685,7 @@ dl_status topk_core(dl_ctx* c, const TopkJob& J, void* ws, size_t ws_bytes, uint
   const int P = topk_splits(R.n, S.n, c->cu_count, &tps);
   const int band_cap = band_cap_of(J.band_cap, k, tps);
   const size_t main_bytes = layout_topk(nullptr, R.n, S.n, R.d, prec, self, P, band_cap, sx).bytes;
-  const bool pilot = pilot_of(prec, self, S.n, k);
+  const bool pilot = !J.seed && pilot_of(prec, self, S.n, k);
   const size_t need = pilot ? main_bytes + 2 * pilot_out_bytes(R.n, k) +
                                   topk_workspace(R.n, pilot_rows(S.n), R.d, DL_BF16, false, false, k, 0, c->cu_count)
                             : main_bytes;
@@ -711,22 +716,33 @@ dl_status topk_core(dl_ctx* c, const TopkJob& J, void* ws, size_t ws_bytes, uint
     L.ps = *J.ps_ext;
     L.ss = J.ss_ext;
   }
+  const bool rx = J.pr_ext != nullptr;
+  if (rx) {
+    L.pr = *J.pr_ext;
+    L.sr = J.sr_ext;
+    if (self) {
+      L.ps = L.pr;
+      L.ss = L.sr;
+    }
+  }
   hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(L.cnt),
                      (int64_t)(sizeof(Counters) / 4));
   hipLaunchKernelGGL(zero_words_kernel, dim3(64), dim3(256), 0, st, reinterpret_cast<uint32_t*>(L.rstate), R.n);
   hipLaunchKernelGGL(zero_words_kernel, dim3(64), dim3(256), 0, st, reinterpret_cast<uint32_t*>(L.wide), R.n);
-  if (S.n == 0) {
-    // nothing to match: every row is padding
+  if (S.n == 0 || J.surv) {
+    // nothing to match (every row is padding), or work items whose tiles
+    // the index rules out all (they store no count)
     hipLaunchKernelGGL(zero_words_kernel, dim3(256), dim3(256), 0, st, reinterpret_cast<uint32_t*>(L.bcount),
                        R.n * (int64_t)P);
   }
   {
     StageTimer t(c, 1, st);
-    DL_HIP(c, launch_prep(R.data, R.n, R.d, R.ld, prec, L.pr, L.sr, st, c->cu_count));
+    if (!rx) DL_HIP(c, launch_prep(R.data, R.n, R.d, R.ld, prec, L.pr, L.sr, st, c->cu_count));
     if (!self && !sx) DL_HIP(c, launch_prep(S.data, S.n, S.d, S.ld, prec, L.ps, L.ss, st, c->cu_count));
     hipLaunchKernelGGL(input_gate_kernel, dim3(1), dim3(64), 0, st, L.sr, L.ss, &L.cnt->invalid);
     DL_HIP(c, launch_threshold(L.pr, R.n, L.ss, R.d, 0.0, nullptr, nullptr, L.marg, nullptr, L.gkey, st));
     if (pilot_dist) DL_HIP(c, launch_band_seed(L.pr, R.n, pilot_dist, k, L.marg, L.gkey, st));
+    if (J.seed) DL_HIP(c, launch_band_seed(L.pr, R.n, J.seed, 1, L.marg, L.gkey, st));
   }
   if (S.n > 0) {
     StageTimer t(c, 2, st);
@@ -750,7 +766,10 @@ dl_status topk_core(dl_ctx* c, const TopkJob& J, void* ws, size_t ws_bytes, uint
     p.retight = retight_of(k, p.limit);
     p.marg = L.marg;
     p.gkey = L.gkey;
-    p.flood = pilot_dist ? 0 : 1;
+    p.flood = (pilot_dist || J.seed) ? 0 : 1;  // (flood_band stores unmapped j: never with jmap)
+    p.surv = J.surv;
+    p.sw = J.sw;
+    p.jmap = J.jmap;
     p.band = L.band;
     p.bcount = L.bcount;
     p.overflow = &L.cnt->overflow;
@@ -1151,6 +1170,186 @@ dl_status eps_indexed_core(dl_ctx* c, const EpsJob& J, double eps, int32_t pivot
   return DL_OK;
 }
 
+// ------------------------------------------------------------ indexed top-k join
+// The top-k join pruned by the same index: each row's k-th distance is
+// bounded by an exact top-k against every 16th row of S; a row tile's ball
+// with the largest bound of its rows as radius marks, in the bound pass, the
+// S tiles that may hold a neighbour of one of its rows; the band pass runs
+// over the ordered operand copies and skips every other tile.  Its entries
+// carry S's own row indices, so the exact selection (which reads the rows of
+// S and breaks ties by index) is the plain join's; the rows of the result
+// are scattered back to R's order.
+
+struct TopkIndexLayout {
+  Prep pr, ps;           // operand copies in pivot order (ps: not for a self-join)
+  RelStats *sr, *ss;
+  float* Rp;             // R's float32 rows in pivot order (the selection's R)
+  float* sdist;          // the sample top-k: k1 distances per row of R
+  uint32_t* sj;
+  float* bound;          // per ordered row: its k-th distance bound
+  uint32_t* oj;          // the result in pivot order
+  float* od;
+  size_t bytes;
+};
+
+static constexpr int kSampleStride = 16;
+
+static TopkIndexLayout layout_topk_index(void* base, int64_t nR, int64_t nS, int d, dl_prec prec, bool self, int k,
+                                         int k1) {
+  TopkIndexLayout X{};
+  Bump b(base);
+  X.sr = b.take<RelStats>(1);
+  X.pr = carve_prep(b, nR, d, prec);
+  if (self) {
+    X.ss = X.sr;
+    X.ps = X.pr;
+  } else {
+    X.ss = b.take<RelStats>(1);
+    X.ps = carve_prep(b, nS, d, prec);
+  }
+  X.Rp = b.take<float>(nR * (int64_t)d);
+  X.sdist = b.take<float>(nR * (int64_t)k1);
+  X.sj = b.take<uint32_t>(nR * (int64_t)k1);
+  X.bound = b.take<float>(nR);
+  X.oj = b.take<uint32_t>(nR * (int64_t)k);
+  X.od = b.take<float>(nR * (int64_t)k);
+  X.bytes = round_up((int64_t)b.off, 256);
+  return X;
+}
+
+// the index's parts of the workspace: [index | top-k index | sample top-k | main top-k]
+struct TopkIndexSizes {
+  size_t index, tk, sample, main, total;
+};
+// The sampled pass runs in the join's own candidate format, except that E4M3
+// candidates sample in bf16: E4M3's margin is wide next to the spread of
+// unrelated rows (see the E4M3 pilot), and so is bf16's on histogram rows,
+// where a bf16 sample would keep tens of near-tie contenders per row.
+static dl_prec sample_prec(dl_prec prec) { return prec == DL_FP8 ? DL_BF16 : prec; }
+
+static TopkIndexSizes topk_index_sizes(int64_t nR, int64_t nS, int d, dl_prec prec, bool self, bool excl, int k,
+                                       int band_cap, int64_t P, int cu) {
+  TopkIndexSizes z{};
+  const int k1 = k + (excl ? 1 : 0);
+  z.index = layout_index(nullptr, nR, nS, d, prec, self, P, cu).bytes;
+  z.tk = layout_topk_index(nullptr, nR, nS, d, prec, self, k, k1).bytes;
+  z.sample = topk_workspace(nR, (nS + kSampleStride - 1) / kSampleStride, d, sample_prec(prec), false, false, k1, 0,
+                            cu);
+  z.main = topk_workspace(nR, nS, d, prec, self, !self, k, band_cap, cu);
+  z.total = z.index + z.tk + z.sample + z.main;
+  return z;
+}
+
+static bool topk_index_applies(int64_t nR, int64_t nS, int k, bool excl) {
+  return index_applies(nR, nS, 1.0) && k + (excl ? 1 : 0) <= 256;
+}
+
+size_t topk_indexed_workspace(int64_t nR, int64_t nS, int d, dl_prec prec, bool self, bool excl, int k, int band_cap,
+                              int32_t pivots, int cu) {
+  const size_t plain = topk_workspace(nR, nS, d, prec, self, false, k, band_cap, cu);
+  if (!topk_index_applies(nR, nS, k, excl)) return plain;
+  const int64_t P = index_pivots(nS, pivots);
+  int64_t tps = 1;
+  const int bc = band_cap_of(band_cap, k, (topk_splits(nR, nS, cu, &tps), tps));
+  const size_t z = topk_index_sizes(nR, nS, d, prec, self, excl, k, bc, P, cu).total;
+  return z > plain ? z : plain;
+}
+
+dl_status topk_indexed_core(dl_ctx* c, const TopkJob& J, int32_t pivots, void* ws, size_t ws_bytes, uint32_t* out_j,
+                            float* out_dist, dl_topk_info* info, dl_index_info* xinfo, hipStream_t st) {
+  const dl_mat &R = J.R, &S = J.S;
+  const bool self = J.self, excl = self && J.excl;
+  const dl_prec prec = J.prec;
+  const int d = R.d, k = J.k, k1 = k + (excl ? 1 : 0);
+  const int64_t nTR = (R.n + kTile - 1) / kTile, nTS = (S.n + kTile - 1) / kTile;
+  if (xinfo) {
+    xinfo->tiles_total = nTR * nTS;
+    xinfo->tiles_computed = nTR * nTS;
+    xinfo->pivots = 0;
+    xinfo->ksteps_per_tile = 0;
+    xinfo->ksteps_computed = 0;
+  }
+  if (!topk_index_applies(R.n, S.n, k, excl)) return topk_core(c, J, ws, ws_bytes, out_j, out_dist, info, st);
+  if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(c, DL_ERR_INVALID, "workspace is not 256-byte aligned");
+  const int64_t P = index_pivots(S.n, pivots);
+  int64_t tps = 1;
+  topk_splits(R.n, S.n, c->cu_count, &tps);
+  const int band_cap = band_cap_of(J.band_cap, k, tps);
+  const TopkIndexSizes z = topk_index_sizes(R.n, S.n, d, prec, self, excl, k, band_cap, P, c->cu_count);
+  if (!ws || ws_bytes < z.total) {
+    c->required_ws = z.total;
+    return fail(c, DL_ERR_WORKSPACE, "workspace of %zu bytes below the %zu needed", ws_bytes, z.total);
+  }
+  uint8_t* w = static_cast<uint8_t*>(ws);
+  IndexLayout I = layout_index(w, R.n, S.n, d, prec, self, P, c->cu_count);
+  TopkIndexLayout X = layout_topk_index(w + z.index, R.n, S.n, d, prec, self, k, k1);
+  uint8_t* sws = w + z.index + z.tk;
+  uint8_t* mws = sws + z.sample;
+  if (xinfo) xinfo->pivots = (int32_t)P;
+
+  // each row's k-th distance bound: an exact top-k1 against every 16th row
+  // of S (k1 = k + 1 when the row itself is excluded, which the sample may
+  // hold); should it fail, the plain join runs instead
+  {
+    dl_mat Ss = S;
+    Ss.n = (S.n + kSampleStride - 1) / kSampleStride;
+    Ss.ld = S.ld * kSampleStride;
+    const TopkJob Js{R, Ss, false, false, sample_prec(prec), nullptr, nullptr, k1, 0};
+    const dl_status ss = topk_core(c, Js, sws, z.sample, X.sj, X.sdist, nullptr, st);
+    if (ss == DL_ERR_WORKSPACE) {
+      c->err.clear();
+      c->required_ws = 0;
+      return topk_core(c, J, ws, ws_bytes, out_j, out_dist, info, st);
+    }
+    if (ss != DL_OK) return ss;
+  }
+  {
+    StageTimer t(c, 6, st);
+    // pivots and the nearest-pivot order of each relation (the row-order
+    // operand copy goes where the ordered one will be)
+    DL_HIP(c, launch_gather_rows(S.data, S.ld, S.n / P, P, d, I.piv, st, c->cu_count));
+    DL_HIP(c, launch_prep(I.piv, P, d, d, prec, I.ppiv, I.spiv, st, c->cu_count));
+    dl_status s = order_by_pivot(c, R, I, P, prec, X.pr, X.sr, I.permR, st);
+    if (s == DL_OK && !self) s = order_by_pivot(c, S, I, P, prec, X.ps, X.ss, I.permS, st);
+    if (s != DL_OK) return s;
+    DL_HIP(c, launch_prep(R.data, R.n, d, R.ld, prec, X.pr, X.sr, st, c->cu_count, I.permR));
+    if (!self) DL_HIP(c, launch_prep(S.data, S.n, d, S.ld, prec, X.ps, X.ss, st, c->cu_count, I.permS));
+    DL_HIP(c, launch_gather(R.data, R.ld, d, I.permR, R.n, X.Rp, st, c->cu_count));
+    DL_HIP(c, launch_take_bound(X.sdist, k1, I.permR, R.n, X.bound, st, c->cu_count));
+    // R's row-tile balls with the bound as radius, the bound pass against
+    // the ordered S rows (bit (S tile, R tile) of m2), every (ti, tj) kept
+    // that m2 marks
+    DL_HIP(c, launch_block_balls_q(X.pr, R.n, d, prec, 0.0, I.centR, I.TbR, st, X.bound));
+    s = bound_pass(c, I.centR, nTR, I.TbR, d, prec, I.pcR, I.scR, I.thrR, X.ps, S.n, X.ss, I.m2, I.m2w, nullptr, st);
+    if (s != DL_OK) return s;
+    DL_HIP(c, launch_survive(nullptr, 0, I.m2, I.m2w, nTR, nTS, 0, I.surv, I.sw, st));
+  }
+  // the band pass over the surviving tiles, the exact selection, the rows
+  // back in R's order
+  const dl_mat Rp{X.Rp, R.n, d, d};
+  const TopkJob Jm{Rp, self ? R : S, self, excl, prec, self ? nullptr : &X.ps, self ? nullptr : X.ss, k, band_cap,
+                   &X.pr, X.sr, I.surv, I.sw, self ? I.permR : I.permS, X.bound};
+  const dl_status ms = topk_core(c, Jm, mws, z.main, X.oj, X.od, info, st);
+  if (ms == DL_ERR_WORKSPACE && c->required_ws) {
+    // a larger band: the whole call's workspace at the capacity asked for
+    c->required_ws = z.index + z.tk + z.sample + c->required_ws;
+    return ms;
+  }
+  if (ms != DL_OK) return ms;
+  DL_HIP(c, launch_scatter_rows(X.oj, X.od, k, I.permR, R.n, out_j, out_dist, st, c->cu_count));
+  if (xinfo) {
+    std::vector<uint32_t> h((size_t)(nTR * I.sw));
+    DL_HIP(c, hipMemcpyAsync(h.data(), I.surv, h.size() * 4, hipMemcpyDeviceToHost, st));
+    DL_HIP(c, hipStreamSynchronize(st));
+    int64_t n = 0;
+    for (uint32_t v : h) n += __builtin_popcount(v);
+    xinfo->tiles_computed = n;
+  } else {
+    DL_HIP(c, hipStreamSynchronize(st));
+  }
+  return DL_OK;
+}
+
 // ------------------------------------------------------------ filtered eps-join
 // A label filter before or after the match (plan.hip).
 struct FilterLayout {
@@ -1406,6 +1605,36 @@ dl_status dl_join_topk(dl_ctx* c, dl_mat R, dl_mat S, int self_join, int32_t k, 
   DL_HIP(c, hipSetDevice(c->device));
   TopkJob J{R, S, self_join != 0, exclude_self != 0, prec, nullptr, nullptr, k, band_cap};
   return topk_core(c, J, ws, ws_bytes, out_j, out_dist, info, static_cast<hipStream_t>(stream));
+}
+
+size_t dl_join_topk_indexed_workspace(int64_t nR, int64_t nS, int32_t d, dl_prec prec, int self_join,
+                                      int exclude_self, int32_t k, int32_t band_cap, int32_t pivots) {
+  if (nR < 0 || nS < 0 || d < 1 || d > kMaxDim || !prec_ok(prec) || k < 1 || pivots < 0) return 0;
+  if (self_join) nS = nR;
+  int cu = 256, dev;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) cu = prop.multiProcessorCount;
+  return topk_indexed_workspace(nR, nS, d, prec, self_join != 0, self_join && exclude_self, k, band_cap, pivots, cu);
+}
+
+dl_status dl_join_topk_indexed(dl_ctx* c, dl_mat R, dl_mat S, int self_join, int32_t k, int exclude_self,
+                               dl_prec prec, int32_t band_cap, int32_t pivots, void* ws, size_t ws_bytes,
+                               uint32_t* out_j, float* out_dist, dl_topk_info* info, dl_index_info* xinfo,
+                               void* stream) {
+  if (!c) return DL_ERR_INVALID;
+  c->err.clear();
+  c->required_ws = 0;
+  if (self_join) S = R;
+  dl_status s;
+  if ((s = check_mat(c, R, "R")) != DL_OK || (s = check_mat(c, S, "S")) != DL_OK) return s;
+  if (R.d != S.d) return fail(c, DL_ERR_INVALID, "R.d %d != S.d %d", R.d, S.d);
+  if (k < 1 || k > 256) return fail(c, DL_ERR_INVALID, "k = %d outside [1, 256]", k);
+  if (!prec_ok(prec)) return fail(c, DL_ERR_INVALID, "unknown precision %d", (int)prec);
+  if (pivots < 0) return fail(c, DL_ERR_INVALID, "pivots = %d < 0", pivots);
+  if (R.n > 0 && (!out_j || !out_dist)) return fail(c, DL_ERR_INVALID, "null output array");
+  DL_HIP(c, hipSetDevice(c->device));
+  TopkJob J{R, S, self_join != 0, exclude_self != 0, prec, nullptr, nullptr, k, band_cap};
+  return topk_indexed_core(c, J, pivots, ws, ws_bytes, out_j, out_dist, info, xinfo, static_cast<hipStream_t>(stream));
 }
 
 // ------------------------------------------------------------ ABI: store

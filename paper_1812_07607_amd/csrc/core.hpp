@@ -40,6 +40,17 @@ struct TopkJob {
   RelStats* ss_ext;
   int k;
   int band_cap;
+  // the index-pruned top-k join (all nullable): R's operand copy and
+  // statistics built by the caller; the band pass skips the tiles whose bit
+  // in surv (sw words per row tile) is clear and stores jmap[j] for column
+  // j of the ordered S (the selection then reads S, the relation in its
+  // own order); seed: one distance bound per R row that seeds its band
+  const Prep* pr_ext;
+  RelStats* sr_ext;
+  const uint32_t* surv;
+  int64_t sw;
+  const uint32_t* jmap;
+  const float* seed;
 };
 
 size_t eps_workspace(int64_t nR, int64_t nS, int d, dl_prec prec, bool self, bool s_ext, int64_t cap,

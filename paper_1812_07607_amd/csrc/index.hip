@@ -142,12 +142,13 @@ template <int kPrec>
 __global__ __launch_bounds__(256) void block_ball_q_kernel(const uint8_t* __restrict__ q, int64_t qld,
                                                            const int* __restrict__ sexp,
                                                            const float* __restrict__ rho, int64_t n, int d,
-                                                           double eps, float* __restrict__ cent,
-                                                           double* __restrict__ Tb) {
+                                                           double eps, const float* __restrict__ eps_row,
+                                                           float* __restrict__ cent, double* __restrict__ Tb) {
   constexpr int kElem = kPrec == DL_FP32 ? 4 : kPrec == DL_FP8 ? 1 : 2;  // bytes per value
   constexpr int kPer = 16 / kElem;                                       // values per 16-byte piece
   extern __shared__ float c_lds[];  // qld / kElem floats: the centroid, zero past d
   __shared__ double r_wave[4];
+  __shared__ float e_wave[4];
   __shared__ float scale_lds[kTile];
   const int64_t b = blockIdx.x;
   const int64_t r0 = b * kTile;
@@ -209,13 +210,22 @@ __global__ __launch_bounds__(256) void block_ball_q_kernel(const uint8_t* __rest
       rmax = fmax(rmax, sqrt(t) + (double)rho[r0 + rq[u]]);
     }
   }
-  if (lane == 0) r_wave[wave] = rmax;
+  // per-row eps (eps_row, the top-k bound of each row): the block's largest
+  float emax = 0.0f;
+  if (eps_row)
+    for (int r = threadIdx.x; r < rows; r += blockDim.x) emax = fmaxf(emax, eps_row[r0 + r]);
+  for (int o = 32; o > 0; o >>= 1) emax = fmaxf(emax, __shfl_xor(emax, o, 64));
+  if (lane == 0) {
+    r_wave[wave] = rmax;
+    e_wave[wave] = emax;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     const double m = fmax(fmax(r_wave[0], r_wave[1]), fmax(r_wave[2], r_wave[3]));
     const double rr = m * (1.0 + 0x1p-30) + 0x1p-100;
-    const double e = eps + rr;
-    Tb[b] = e * e * (1.0 + 0x1p-30);
+    const double eb = eps_row ? (double)fmaxf(fmaxf(e_wave[0], e_wave[1]), fmaxf(e_wave[2], e_wave[3])) : eps;
+    const double e = eb + rr;
+    Tb[b] = e * e * (1.0 + 0x1p-30);  // +inf when a row has no bound
   }
 }
 
@@ -231,7 +241,7 @@ __global__ __launch_bounds__(256) void survive_kernel(const uint32_t* __restrict
   const int64_t ti = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   if (ti >= nTR) return;
   for (int64_t w = lane; w < sw; w += 64) {
-    uint32_t word = m1[ti * m1w + w];
+    uint32_t word = m1 ? m1[ti * m1w + w] : 0xffffffffu;  // no m1: that direction marks every tile
     uint32_t keep = 0;
     for (int bit = 0; bit < 32; ++bit) {
       const int64_t tj = w * 32 + bit;
@@ -416,7 +426,7 @@ hipError_t launch_pivot_sort(const unsigned long long* argkey, int64_t n, int64_
 
 // Balls of the blocks of an ordered operand copy P (n real rows).
 hipError_t launch_block_balls_q(const Prep& P, int64_t n, int d, dl_prec prec, double eps, float* cent, double* Tb,
-                                hipStream_t st) {
+                                hipStream_t st, const float* eps_row) {
   const int64_t nb = (n + kTile - 1) / kTile;
   if (nb == 0) return hipSuccess;
   const int elem = prec == DL_FP32 ? 4 : prec == DL_FP8 ? 1 : 2;
@@ -425,21 +435,62 @@ hipError_t launch_block_balls_q(const Prep& P, int64_t n, int d, dl_prec prec, d
   switch (prec) {
     case DL_FP32:
       hipLaunchKernelGGL(block_ball_q_kernel<DL_FP32>, dim3((unsigned)nb), dim3(256), lds, st, q, P.qld, P.sexp, P.rho,
-                         n, d, eps, cent, Tb);
+                         n, d, eps, eps_row, cent, Tb);
       break;
     case DL_BF16:
       hipLaunchKernelGGL(block_ball_q_kernel<DL_BF16>, dim3((unsigned)nb), dim3(256), lds, st, q, P.qld, P.sexp, P.rho,
-                         n, d, eps, cent, Tb);
+                         n, d, eps, eps_row, cent, Tb);
       break;
     case DL_FP16:
       hipLaunchKernelGGL(block_ball_q_kernel<DL_FP16>, dim3((unsigned)nb), dim3(256), lds, st, q, P.qld, P.sexp, P.rho,
-                         n, d, eps, cent, Tb);
+                         n, d, eps, eps_row, cent, Tb);
       break;
     case DL_FP8:
       hipLaunchKernelGGL(block_ball_q_kernel<DL_FP8>, dim3((unsigned)nb), dim3(256), lds, st, q, P.qld, P.sexp, P.rho,
-                         n, d, eps, cent, Tb);
+                         n, d, eps, eps_row, cent, Tb);
       break;
   }
+  return hipGetLastError();
+}
+
+// The top-k join's per-row bound in the index's row order: bound[q] =
+// dist[perm[q] * k + k - 1], the k-th distance of row perm[q] against a
+// sample of S (+inf when the sample held fewer than k rows).
+__global__ void take_bound_kernel(const float* __restrict__ dist, int k, const uint32_t* __restrict__ perm, int64_t n,
+                                  float* __restrict__ bound) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+    bound[q] = dist[(int64_t)perm[q] * k + k - 1];
+}
+
+// Rows of k results from the index's row order back to R's: row q goes to
+// row perm[q].
+__global__ void scatter_rows_kernel(const uint32_t* __restrict__ j_in, const float* __restrict__ d_in, int k,
+                                    const uint32_t* __restrict__ perm, int64_t n, uint32_t* __restrict__ j_out,
+                                    float* __restrict__ d_out) {
+  const int64_t total = n * k;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t q = t / k, c = t - q * k;
+    const int64_t o = (int64_t)perm[q] * k + c;
+    j_out[o] = j_in[t];
+    d_out[o] = d_in[t];
+  }
+}
+
+hipError_t launch_take_bound(const float* dist, int k, const uint32_t* perm, int64_t n, float* bound, hipStream_t st,
+                             int cu) {
+  if (n == 0) return hipSuccess;
+  int64_t g = (n + 255) / 256;
+  if (g > (int64_t)cu * 8) g = (int64_t)cu * 8;
+  hipLaunchKernelGGL(take_bound_kernel, dim3((unsigned)g), dim3(256), 0, st, dist, k, perm, n, bound);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_rows(const uint32_t* j_in, const float* d_in, int k, const uint32_t* perm, int64_t n,
+                               uint32_t* j_out, float* d_out, hipStream_t st, int cu) {
+  if (n == 0) return hipSuccess;
+  int64_t g = (n * k + 255) / 256;
+  if (g > (int64_t)cu * 8) g = (int64_t)cu * 8;
+  hipLaunchKernelGGL(scatter_rows_kernel, dim3((unsigned)g), dim3(256), 0, st, j_in, d_in, k, perm, n, j_out, d_out);
   return hipGetLastError();
 }
 

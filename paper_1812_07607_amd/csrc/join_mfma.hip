@@ -243,6 +243,9 @@ struct TileIter {
         t_end = min(t + p.tps, p.nTS);
         if (t >= t_end) t_end = -1;  // no S tiles for this workgroup
       }
+      // tiles the index cannot rule out only (a row tile's survivor bits)
+      if (p.surv)
+        while (t < t_end && !((p.surv[ti * p.sw + (t >> 5)] >> (t & 31)) & 1u)) ++t;
       if (t_end < 0 || t >= t_end) return false;
       oti = uniform64(ti);
       otj = uniform64(t);
@@ -774,8 +777,8 @@ __device__ inline void flush_band(const CandParams& p, int64_t ti, int64_t tj, i
       if (pos == p.limit) L.urgent = 1;
       if (pos < p.cap) {
         const int64_t i = ti * kTile + lr;
-        p.band[(i * p.P + split) * (int64_t)p.cap + pos] =
-            make_uint2(h.x, (uint32_t)(tj * kTile) + (h.y & 255u));
+        const uint32_t j = (uint32_t)(tj * kTile) + (h.y & 255u);
+        p.band[(i * p.P + split) * (int64_t)p.cap + pos] = make_uint2(h.x, p.jmap ? p.jmap[j] : j);
       }
     }
   }

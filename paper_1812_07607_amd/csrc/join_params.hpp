@@ -49,6 +49,13 @@ struct CandParams {
   uint2* band;         // (P~ bits, j): [(row * P + split) * cap + slot]
   int* bcount;         // [row * P + split]
   int* overflow;       // set when a band exceeds cap - 256
+  // band mode over the tiles of an index (nullable): bit tj of row tile
+  // ti's words surv[ti * sw ..] set when (ti, tj) may hold a row's top-k
+  // neighbour (other tiles are skipped); jmap[j] = the index in S that band
+  // entries carry for column j of the ordered S
+  const uint32_t* surv;
+  int64_t sw;
+  const uint32_t* jmap;
   const int* gate;     // nonzero: invalid input, the kernel does nothing
   // eps mode over a tile list (index-pruned join): (ti, tj) entries and the
   // device-side count; null = every tile

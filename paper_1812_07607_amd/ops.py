@@ -381,6 +381,41 @@ def join_topk(R: torch.Tensor, S: torch.Tensor | None, k: int, exclude_self: boo
 
 
 
+def join_topk_indexed(R: torch.Tensor, S: torch.Tensor | None, k: int, exclude_self: bool = False,
+                      prec: str = "bf16", pivots: int = 0, band_cap: int = 0, stream=None,
+                      workspace: Workspace | None = None):
+    """top-k join with an index built on the fly (each row's k-th distance
+    bounded from a sample of S, row-tile balls of that radius, tiles that
+    cannot hold a neighbour skipped).  Same result as join_topk; returns
+    (TopkResult, IndexInfo)."""
+    self_join = S is None
+    Sm = R if self_join else S
+    c = context(R.device.index)
+    ws = workspace or _workspace(R.device)
+    p = _lib.PREC[prec]
+    nR, nS, d = R.shape[0], Sm.shape[0], R.shape[1]
+    oj = torch.empty((nR, k), dtype=torch.int32, device=R.device)
+    od = torch.empty((nR, k), dtype=torch.float32, device=R.device)
+    info = _lib.dl_topk_info()
+    xinfo = _lib.dl_index_info()
+    for _ in range(6):
+        need = c.L.dl_join_topk_indexed_workspace(nR, nS, d, p, int(self_join), int(exclude_self), k, band_cap,
+                                                  pivots)
+        buf = ws.get(need)
+        st = c.L.dl_join_topk_indexed(c.h, _mat(R), _mat(Sm), int(self_join), k, int(exclude_self), p, band_cap,
+                                      pivots, ctypes.c_void_p(buf.data_ptr()), buf.numel(),
+                                      ctypes.c_void_p(oj.data_ptr()), ctypes.c_void_p(od.data_ptr()),
+                                      ctypes.byref(info), ctypes.byref(xinfo), _stream_ptr(stream))
+        if c.band_full(st):
+            band_cap = max(2 * (band_cap or 1024), 1024)
+            continue
+        c.check(st)
+        return (TopkResult(oj, od, int(info.band_entries), int(info.ties)),
+                IndexInfo(int(xinfo.tiles_total), int(xinfo.tiles_computed), int(xinfo.pivots),
+                          int(xinfo.ksteps_per_tile), int(xinfo.ksteps_computed)))
+    raise RuntimeError("join_topk_indexed did not converge on band capacity")
+
+
 # ---------------------------------------------------------------- store
 class Store:
     """A resident relation: float32 rows (kept alive here) plus their operand
