@@ -545,6 +545,8 @@ def etl_index_plan_legs():
     out["index_top10"] = {"plain_ms": rec0["ms_per_call"], "indexed_ms": rec1["ms_per_call"],
                           "speedup": rec0["ms_per_call"] / rec1["ms_per_call"],
                           "tiles_computed": info.tiles_computed, "tiles_total": info.tiles_total,
+                          "ksteps_computed": info.ksteps_computed,
+                          "ksteps_of_computed_tiles": info.tiles_computed * info.ksteps_per_tile,
                           "pivots": info.pivots, "plain_stages": rec0, "indexed_stages": rec1,
                           "same_rows": bool(torch.equal(r.j, ref.j) and torch.equal(r.dist, ref.dist))}
     progress("index top-10: %s" % json.dumps(out["index_top10"]))

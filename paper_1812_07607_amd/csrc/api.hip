@@ -770,6 +770,8 @@ dl_status topk_core(dl_ctx* c, const TopkJob& J, void* ws, size_t ws_bytes, uint
     p.surv = J.surv;
     p.sw = J.sw;
     p.jmap = J.jmap;
+    p.kmaskA = J.kmA;
+    p.kmaskB = J.kmB;
     p.band = L.band;
     p.bcount = L.bcount;
     p.overflow = &L.cnt->overflow;
@@ -1286,6 +1288,8 @@ dl_status topk_indexed_core(dl_ctx* c, const TopkJob& J, int32_t pivots, void* w
   uint8_t* sws = w + z.index + z.tk;
   uint8_t* mws = sws + z.sample;
   if (xinfo) xinfo->pivots = (int32_t)P;
+  const int nsteps = (int)(X.pr.qld / kChunkBytes);
+  const bool kmask = nsteps <= 64;
 
   // each row's k-th distance bound: an exact top-k1 against every 16th row
   // of S (k1 = k + 1 when the row itself is excluded, which the sample may
@@ -1316,6 +1320,12 @@ dl_status topk_indexed_core(dl_ctx* c, const TopkJob& J, int32_t pivots, void* w
     if (!self) DL_HIP(c, launch_prep(S.data, S.n, d, S.ld, prec, X.ps, X.ss, st, c->cu_count, I.permS));
     DL_HIP(c, launch_gather(R.data, R.ld, d, I.permR, R.n, X.Rp, st, c->cu_count));
     DL_HIP(c, launch_take_bound(X.sdist, k1, I.permR, R.n, X.bound, st, c->cu_count));
+    // K-step masks of the ordered operand tiles, as in the index-pruned
+    // eps-join (a tile's rows are alike, so many bins are zero in all of them)
+    if (kmask) {
+      DL_HIP(c, launch_tile_kmask(X.pr.q, X.pr.qld, nTR, I.kmR, st));
+      if (!self) DL_HIP(c, launch_tile_kmask(X.ps.q, X.ps.qld, nTS, I.kmS, st));
+    }
     // R's row-tile balls with the bound as radius, the bound pass against
     // the ordered S rows (bit (S tile, R tile) of m2), every (ti, tj) kept
     // that m2 marks
@@ -1328,7 +1338,8 @@ dl_status topk_indexed_core(dl_ctx* c, const TopkJob& J, int32_t pivots, void* w
   // back in R's order
   const dl_mat Rp{X.Rp, R.n, d, d};
   const TopkJob Jm{Rp, self ? R : S, self, excl, prec, self ? nullptr : &X.ps, self ? nullptr : X.ss, k, band_cap,
-                   &X.pr, X.sr, I.surv, I.sw, self ? I.permR : I.permS, X.bound};
+                   &X.pr, X.sr, I.surv, I.sw, self ? I.permR : I.permS, X.bound,
+                   kmask ? I.kmR : nullptr, kmask ? (self ? I.kmR : I.kmS) : nullptr};
   const dl_status ms = topk_core(c, Jm, mws, z.main, X.oj, X.od, info, st);
   if (ms == DL_ERR_WORKSPACE && c->required_ws) {
     // a larger band: the whole call's workspace at the capacity asked for
@@ -1339,11 +1350,28 @@ dl_status topk_indexed_core(dl_ctx* c, const TopkJob& J, int32_t pivots, void* w
   DL_HIP(c, launch_scatter_rows(X.oj, X.od, k, I.permR, R.n, out_j, out_dist, st, c->cu_count));
   if (xinfo) {
     std::vector<uint32_t> h((size_t)(nTR * I.sw));
+    std::vector<uint64_t> mR(kmask ? nTR : 0), mS(kmask ? nTS : 0);
     DL_HIP(c, hipMemcpyAsync(h.data(), I.surv, h.size() * 4, hipMemcpyDeviceToHost, st));
+    if (kmask) {
+      DL_HIP(c, hipMemcpyAsync(mR.data(), I.kmR, nTR * 8, hipMemcpyDeviceToHost, st));
+      DL_HIP(c, hipMemcpyAsync(mS.data(), self ? I.kmR : I.kmS, nTS * 8, hipMemcpyDeviceToHost, st));
+    }
     DL_HIP(c, hipStreamSynchronize(st));
-    int64_t n = 0;
-    for (uint32_t v : h) n += __builtin_popcount(v);
+    int64_t n = 0, ks = 0;
+    for (int64_t ti = 0; ti < nTR; ++ti)
+      for (int64_t tj = 0; tj < nTS; ++tj)
+        if ((h[ti * I.sw + (tj >> 5)] >> (tj & 31)) & 1u) {
+          ++n;
+          if (kmask) {
+            const uint64_t m = mR[ti] & mS[tj];
+            ks += m ? __builtin_popcountll(m) : 1;  // a tile runs one step at least
+          }
+        }
     xinfo->tiles_computed = n;
+    if (kmask) {
+      xinfo->ksteps_per_tile = nsteps;
+      xinfo->ksteps_computed = ks;
+    }
   } else {
     DL_HIP(c, hipStreamSynchronize(st));
   }

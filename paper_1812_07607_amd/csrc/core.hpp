@@ -51,6 +51,9 @@ struct TopkJob {
   int64_t sw;
   const uint32_t* jmap;
   const float* seed;
+  // K-step masks of R's and S's operand tiles (nullable; both or neither)
+  const uint64_t* kmA;
+  const uint64_t* kmB;
 };
 
 size_t eps_workspace(int64_t nR, int64_t nS, int d, dl_prec prec, bool self, bool s_ext, int64_t cap,

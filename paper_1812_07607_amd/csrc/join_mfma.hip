@@ -974,12 +974,12 @@ __device__ inline void wait_and_sync(int n) {
   asm volatile("" ::: "memory");
 }
 
-// kMasked (eps mode): the K-step masks p.kmaskA / p.kmaskB are set; a
-// separate instantiation, so that the unmasked pass carries none of their
-// bookkeeping.
+// kMasked (eps and band modes): the K-step masks p.kmaskA / p.kmaskB are
+// set; a separate instantiation, so that the unmasked pass carries none of
+// their bookkeeping.
 template <int kPrec, int kMode, bool kMasked = false>
 __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
-  static_assert(!kMasked || kMode == kModeEps, "K-step masks in eps mode only");
+  static_assert(!kMasked || kMode == kModeEps || kMode == kModeBand, "K-step masks in eps and band modes only");
   using Q = Pipe<kPrec>;
   static_assert(Q::kStages == 2 || Q::kStages == 4, "ring depth");
   // operand transfers per issuing wave per step (the count a wait leaves in
@@ -1019,7 +1019,7 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
   TileIter lit;
   int64_t ti, tj;
   if (!lit.next(p, kMode, ti, tj)) return;
-  // K-step masks (eps mode only): the loader issues a tile's set steps in
+  // K-step masks (eps and band modes): the loader issues a tile's set steps in
   // order, and the compute side runs as many steps as the loader issued
   constexpr bool masked = kMasked;
   int64_t lti = ti, ltj = tj;  // tile of the loader's next step
@@ -1176,6 +1176,7 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
     // band mode (more live state beside the accumulators): each K-step's
     // products are all issued before the next barrier
     int chunk = 0;
+    int tsteps = lsteps;  // K-steps of the current tile
     for (;;) {
       wait_and_sync(dirty ? 0 : (issued - step - 1) * kPerStep);
       dirty = false;
@@ -1204,7 +1205,7 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
       const int st = step % Q::kStages;
       mma_step<kPrec, false, false>(acc, lds_ab[st][0], lds_ab[st][1], wm * kWaveM, wn * kWaveN, sa, sb, acc[0], fr);
       mma_tail<kPrec>(acc, fr);
-      if (chunk == nsteps - 1) {
+      if (chunk == (masked ? tsteps : nsteps) - 1) {
         if (full && ctile == 0 && p.flood) {
           // the first tile: no round has run, every threshold is -inf
           flood_band(p, ti, tj, split, acc, band);
@@ -1213,11 +1214,12 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
         else dirty |= epilogue_band<false>(p, ti, tj, split, acc, band);
       }
       ++step;
-      if (++chunk == nsteps) {
+      if (++chunk == (masked ? tsteps : nsteps)) {
         if (!more) break;
         chunk = 0;
         ti = iti;  // the step just issued opens the next tile
         tj = itj;
+        tsteps = isteps;
         ++ctile;
       }
     }
@@ -1236,13 +1238,13 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
 
 template <int kMode>
 static hipError_t launch_mode(dl_prec prec, const CandParams& p, dim3 grid, hipStream_t st) {
-  if constexpr (kMode == kModeEps) {
+  if constexpr (kMode == kModeEps || kMode == kModeBand) {
     if (p.kmaskA) {
       switch (prec) {
-        case DL_FP32: hipLaunchKernelGGL((cand_kernel<DL_FP32, kModeEps, true>), grid, dim3(kThreads), 0, st, p); break;
-        case DL_BF16: hipLaunchKernelGGL((cand_kernel<DL_BF16, kModeEps, true>), grid, dim3(kThreads), 0, st, p); break;
-        case DL_FP16: hipLaunchKernelGGL((cand_kernel<DL_FP16, kModeEps, true>), grid, dim3(kThreads), 0, st, p); break;
-        case DL_FP8: hipLaunchKernelGGL((cand_kernel<DL_FP8, kModeEps, true>), grid, dim3(kThreads), 0, st, p); break;
+        case DL_FP32: hipLaunchKernelGGL((cand_kernel<DL_FP32, kMode, true>), grid, dim3(kThreads), 0, st, p); break;
+        case DL_BF16: hipLaunchKernelGGL((cand_kernel<DL_BF16, kMode, true>), grid, dim3(kThreads), 0, st, p); break;
+        case DL_FP16: hipLaunchKernelGGL((cand_kernel<DL_FP16, kMode, true>), grid, dim3(kThreads), 0, st, p); break;
+        case DL_FP8: hipLaunchKernelGGL((cand_kernel<DL_FP8, kMode, true>), grid, dim3(kThreads), 0, st, p); break;
       }
       return hipGetLastError();
     }

@@ -43,7 +43,7 @@ def test_self_join_topk_indexed(orc, prec):
 def test_histogram_topk_indexed_equals_plain(orc):
     """8,000 palette-patch histograms (fp16 candidates, the exact format on
     them): the pruned and the plain top-5 self-joins are identical and equal
-    to the oracle's."""
+    to the oracle's; tiles and K-steps are skipped."""
     cfg = synth.config2(0.08)
     H = orc.hist_rgb8(cfg["patches"], 8)
     ref_j, _, ref_dist = orc.topk(H, None, 5, exclude_self=True)
@@ -52,6 +52,8 @@ def test_histogram_topk_indexed_equals_plain(orc):
     assert_topk_equal(got, ref_j, ref_dist, 512, "histograms")
     assert torch.equal(got.j, plain.j) and torch.equal(got.dist, plain.dist)
     assert info.tiles_computed < 0.7 * info.tiles_total, info
+    # bins empty in every row of a pivot-ordered tile drop out of its K-steps
+    assert 0 < info.ksteps_computed < info.tiles_computed * info.ksteps_per_tile, info
 
 
 @pytest.mark.parametrize("prec", ["bf16", "fp32"])
