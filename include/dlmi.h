@@ -341,14 +341,17 @@ size_t dl_join_topk_indexed_workspace(int64_t nR, int64_t nS, int32_t d, dl_prec
  * nearest pivot as in dl_join_eps_indexed (pivots, 0 = default).  Every 256
  * ordered rows of R form a ball whose radius is the largest bound of its
  * rows.  A bound pass on the matrix cores keeps the S tiles with a row
- * within that ball's reach, and the band pass runs on the kept tiles only.
- * The band and the exact selection are dl_join_topk's.  Falls back to
+ * within that ball's reach, and the band pass runs on the kept tiles only,
+ * skipping K-steps as dl_join_eps_indexed does.  The sample runs in prec
+ * (bf16 when prec is DL_FP8).  The band and the exact selection are
+ * dl_join_topk's.  Falls back to
  * dl_join_topk when either relation spans fewer than two 256-row tiles or
  * the sample top-k does not fit the workspace.
  *   out_j, out_dist, info  as dl_join_topk;
  *   xinfo     host, nullable: tiles_total = row tiles x column tiles,
  *             tiles_computed = those kept, pivots (0 when no index was
- *             built); K-step fields 0.
+ *             built), ksteps_per_tile and ksteps_computed over the kept
+ *             tiles (0 when rows span more than 64 K-steps: no masks).
  * Errors as dl_join_topk ("band buffer": retry with a larger band_cap and
  * dl_join_topk_indexed_workspace of it).  Synchronises `stream`. */
 dl_status dl_join_topk_indexed(dl_ctx* ctx, dl_mat R, dl_mat S, int self_join,
