@@ -1093,7 +1093,7 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
     // matrix instructions, instead of holding every wave at the barrier.
     // (Not for E4M3, whose step has no registers to spare for it.)
     constexpr bool kDefer = kQ && !kFp8;
-    int tsteps = lsteps;  // K-steps of the current tile
+    int tsteps = isteps;  // K-steps of the current tile (the prologue issued its first step)
     bool pend = false;    // eps: a finished tile (pti, ptj) awaits its epilogue
     int64_t pti = 0, ptj = 0;
     int psbuf = 0;
@@ -1176,7 +1176,7 @@ __global__ __launch_bounds__(kThreads, 1) void cand_kernel(CandParams p) {
     // band mode (more live state beside the accumulators): each K-step's
     // products are all issued before the next barrier
     int chunk = 0;
-    int tsteps = lsteps;  // K-steps of the current tile
+    int tsteps = isteps;  // K-steps of the current tile (the prologue issued its first step)
     for (;;) {
       wait_and_sync(dirty ? 0 : (issued - step - 1) * kPerStep);
       dirty = false;

@@ -96,3 +96,27 @@ def test_random_topk_indexed_sweep(orc, prec):
             seed, n, m, d, k, self_join, excl, prec))
         pruned += info.tiles_computed < info.tiles_total
     assert pruned >= 4, pruned
+
+
+def test_histogram_100k_topk_indexed_equals_plain(orc):
+    """100,000 palette-patch histograms, the top-10 self-join without the row
+    itself: the pruned join (with K-step masks; among its work items some
+    whose first tile has a single K-step) equals the plain join row for row,
+    and 64 seeded rows equal the oracle's."""
+    cfg = synth.config2(1.0)
+    hist = ops.featurize_rgb8(torch.from_numpy(cfg["patches"]).cuda(), 8)
+    ref = ops.join_topk(hist, None, 10, exclude_self=True, prec="fp16")
+    got, info = ops.join_topk_indexed(hist, None, 10, exclude_self=True, prec="fp16")
+    bad = torch.nonzero((got.j != ref.j).any(1) | (got.dist != ref.dist).any(1)).flatten()
+    assert bad.numel() == 0, "%d rows differ from the plain join, first %d" % (bad.numel(), int(bad[0]))
+    assert info.tiles_computed < info.tiles_total // 2, info
+    assert info.ksteps_computed < info.tiles_computed * info.ksteps_per_tile, info
+    H = hist.cpu().numpy()
+    rows = synth.sample_rows(H.shape[0], 64, seed=191)
+    oj, _, od = orc.topk(H[rows], H, 11)
+    keep = oj != np.asarray(rows)[:, None]  # the row itself, wherever it falls
+    ref_j = np.stack([oj[r][keep[r]][:10] for r in range(len(rows))])
+    ref_d = np.stack([od[r][keep[r]][:10] for r in range(len(rows))])
+    sub = type(got)(got.j[torch.from_numpy(np.asarray(rows)).cuda()], got.dist[torch.from_numpy(np.asarray(rows)).cuda()],
+                    0, 0)
+    assert_topk_equal(sub, ref_j, ref_d, 512, "100k histograms, seeded rows")
