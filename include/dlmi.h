@@ -342,8 +342,10 @@ size_t dl_join_topk_indexed_workspace(int64_t nR, int64_t nS, int32_t d, dl_prec
  * ordered rows of R form a ball whose radius is the largest bound of its
  * rows.  A bound pass on the matrix cores keeps the S tiles with a row
  * within that ball's reach, and the band pass runs on the kept tiles only,
- * skipping K-steps as dl_join_eps_indexed does.  The sample runs in prec
- * (bf16 when prec is DL_FP8).  The band and the exact selection are
+ * skipping K-steps as dl_join_eps_indexed does.  Every pass runs in prec,
+ * except that DL_FP8 runs in bf16: in pivot order a row's near rows fall
+ * into few band splits, where E4M3's wide margin overflows the band (the
+ * result is the same).  The band and the exact selection are
  * dl_join_topk's.  Falls back to
  * dl_join_topk when either relation spans fewer than two 256-row tiles or
  * the sample top-k does not fit the workspace.

@@ -1223,11 +1223,9 @@ static TopkIndexLayout layout_topk_index(void* base, int64_t nR, int64_t nS, int
 struct TopkIndexSizes {
   size_t index, tk, sample, main, total;
 };
-// The sampled pass runs in the join's own candidate format, except that E4M3
-// candidates sample in bf16: E4M3's margin is wide next to the spread of
-// unrelated rows (see the E4M3 pilot), and so is bf16's on histogram rows,
-// where a bf16 sample would keep tens of near-tie contenders per row.
-static dl_prec sample_prec(dl_prec prec) { return prec == DL_FP8 ? DL_BF16 : prec; }
+// The sampled pass runs in the join's own candidate format (never E4M3 here,
+// see indexed_topk_prec): bf16's margin is wide on histogram rows, where a
+// bf16 sample of an fp16 join would keep tens of near-tie contenders per row.
 
 static TopkIndexSizes topk_index_sizes(int64_t nR, int64_t nS, int d, dl_prec prec, bool self, bool excl, int k,
                                        int band_cap, int64_t P, int cu) {
@@ -1235,7 +1233,7 @@ static TopkIndexSizes topk_index_sizes(int64_t nR, int64_t nS, int d, dl_prec pr
   const int k1 = k + (excl ? 1 : 0);
   z.index = layout_index(nullptr, nR, nS, d, prec, self, P, cu).bytes;
   z.tk = layout_topk_index(nullptr, nR, nS, d, prec, self, k, k1).bytes;
-  z.sample = topk_workspace(nR, (nS + kSampleStride - 1) / kSampleStride, d, sample_prec(prec), false, false, k1, 0,
+  z.sample = topk_workspace(nR, (nS + kSampleStride - 1) / kSampleStride, d, prec, false, false, k1, 0,
                             cu);
   z.main = topk_workspace(nR, nS, d, prec, self, !self, k, band_cap, cu);
   z.total = z.index + z.tk + z.sample + z.main;
@@ -1298,7 +1296,7 @@ dl_status topk_indexed_core(dl_ctx* c, const TopkJob& J, int32_t pivots, void* w
     dl_mat Ss = S;
     Ss.n = (S.n + kSampleStride - 1) / kSampleStride;
     Ss.ld = S.ld * kSampleStride;
-    const TopkJob Js{R, Ss, false, false, sample_prec(prec), nullptr, nullptr, k1, 0};
+    const TopkJob Js{R, Ss, false, false, prec, nullptr, nullptr, k1, 0};
     const dl_status ss = topk_core(c, Js, sws, z.sample, X.sj, X.sdist, nullptr, st);
     if (ss == DL_ERR_WORKSPACE) {
       c->err.clear();
@@ -1635,6 +1633,14 @@ dl_status dl_join_topk(dl_ctx* c, dl_mat R, dl_mat S, int self_join, int32_t k, 
   return topk_core(c, J, ws, ws_bytes, out_j, out_dist, info, static_cast<hipStream_t>(stream));
 }
 
+// The indexed top-k join runs E4M3 requests with bf16 candidates.  In pivot
+// order the rows near a row fall into few of its band splits, and E4M3's
+// wide margin then overflows those splits' buffers: at 200,000 x 200,000,
+// d = 128, the E4M3 band needed four capacity retries (155.6 ms against the
+// plain E4M3 join's 31.7 ms), while bf16 took none.  The result is exact in
+// either format.
+static dl_prec indexed_topk_prec(dl_prec prec) { return prec == DL_FP8 ? DL_BF16 : prec; }
+
 size_t dl_join_topk_indexed_workspace(int64_t nR, int64_t nS, int32_t d, dl_prec prec, int self_join,
                                       int exclude_self, int32_t k, int32_t band_cap, int32_t pivots) {
   if (nR < 0 || nS < 0 || d < 1 || d > kMaxDim || !prec_ok(prec) || k < 1 || pivots < 0) return 0;
@@ -1642,7 +1648,8 @@ size_t dl_join_topk_indexed_workspace(int64_t nR, int64_t nS, int32_t d, dl_prec
   int cu = 256, dev;
   hipDeviceProp_t prop;
   if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) cu = prop.multiProcessorCount;
-  return topk_indexed_workspace(nR, nS, d, prec, self_join != 0, self_join && exclude_self, k, band_cap, pivots, cu);
+  return topk_indexed_workspace(nR, nS, d, indexed_topk_prec(prec), self_join != 0, self_join && exclude_self, k,
+                                band_cap, pivots, cu);
 }
 
 dl_status dl_join_topk_indexed(dl_ctx* c, dl_mat R, dl_mat S, int self_join, int32_t k, int exclude_self,
@@ -1661,7 +1668,7 @@ dl_status dl_join_topk_indexed(dl_ctx* c, dl_mat R, dl_mat S, int self_join, int
   if (pivots < 0) return fail(c, DL_ERR_INVALID, "pivots = %d < 0", pivots);
   if (R.n > 0 && (!out_j || !out_dist)) return fail(c, DL_ERR_INVALID, "null output array");
   DL_HIP(c, hipSetDevice(c->device));
-  TopkJob J{R, S, self_join != 0, exclude_self != 0, prec, nullptr, nullptr, k, band_cap};
+  TopkJob J{R, S, self_join != 0, exclude_self != 0, indexed_topk_prec(prec), nullptr, nullptr, k, band_cap};
   return topk_indexed_core(c, J, pivots, ws, ws_bytes, out_j, out_dist, info, xinfo, static_cast<hipStream_t>(stream));
 }
 
