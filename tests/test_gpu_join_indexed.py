@@ -162,3 +162,49 @@ def test_index_degenerate_inputs(orc, prec):
         got, info = ops.join_eps_indexed(dev(R), dev(S), eps, prec, pivots=piv)
         assert_eps_equal(got, orc.eps_join(R, S, eps), 24, "two tiles pivots=%d/%s" % (piv, prec))
         assert info.tiles_total == 4 and 0 < info.pivots <= 512
+
+
+def _two_support_clusters(seed, stream, shuffle):
+    """16,384 rows of d = 256 histogram-like vectors in 8 clusters of 2,048
+    rows, cluster-major unless shuffled: clusters 0-3 nonzero only in bins
+    64c .. 64c + 63 (one fp16 K-step), clusters 4-7 in all 256 bins (four
+    K-steps).  Each row is its cluster's centre (drawn from seed, the same
+    for every stream) plus small noise (drawn from seed and stream).  With
+    16 pivots at a stride of 1,024 rows of the cluster-major relation, each
+    cluster holds two pivots and every tile of the pivot order one cluster."""
+    c = np.random.default_rng(seed)
+    cent = [c.dirichlet(np.ones(64)) for _ in range(4)] + [c.dirichlet(np.ones(256)) for _ in range(4)]
+    rng = np.random.default_rng([seed, stream])
+    out = np.zeros((8 * 2048, 256), np.float32)
+    for k in range(8):
+        rows = slice(2048 * k, 2048 * (k + 1))
+        if k < 4:
+            out[rows, 64 * k:64 * k + 64] = np.clip(cent[k] + rng.normal(0, 0.002, (2048, 64)), 0, None)
+        else:
+            out[rows] = np.clip(cent[k] + rng.normal(0, 0.001, (2048, 256)), 0, None)
+    return out[rng.permutation(len(out))] if shuffle else out
+
+
+_TWO_SUPPORT = {}
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_single_kstep_tiles_beside_wider_ones(orc, prec):
+    """16,384 x 16,384 rows in 8 clusters whose tiles run one or four
+    K-steps (2-byte formats): with 512 surviving tiles over the persistent
+    workgroups,
+    a workgroup's first tile often has a single K-step and its next tile
+    more (the masked pass takes each tile's step count from the step it
+    issued).  Equal to the oracle; the cross-cluster tiles are pruned."""
+    if not _TWO_SUPPORT:
+        R = _two_support_clusters(211, 0, True)
+        S = _two_support_clusters(211, 1, False)
+        rng = np.random.default_rng(213)
+        pi, pj = rng.integers(0, len(R), 20000), rng.integers(0, len(S), 20000)
+        eps = eps_quantile(orc, R, S, (pi, pj), 0.002)
+        _TWO_SUPPORT.update(R=R, S=S, eps=eps, ref=orc.eps_join(R, S, eps))
+    R, S, eps, ref = (_TWO_SUPPORT[k] for k in ("R", "S", "eps", "ref"))
+    got, info = ops.join_eps_indexed(dev(R), dev(S), eps, prec)
+    assert_eps_equal(got, ref, 256, "two-support clusters/" + prec)
+    assert info.tiles_computed <= info.tiles_total // 4, info
+    assert info.ksteps_computed < info.tiles_computed * info.ksteps_per_tile, info
